@@ -1,0 +1,302 @@
+"""Pins of the oracle's proximal operators, FISTA, power iteration, counter
+generator and NCC against closed forms and optimality conditions (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def cn(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# --- l1 prox (eq. (13)) -----------------------------------------------------------
+def test_prox_l1_closed_form():
+    v = np.array([3 + 4j, 0.5 - 0.5j, 1.0 + 0j, 0j, -2j])
+    z = O.prox_l1(v, 1.0)
+    assert z[0] == pytest.approx(2.4 + 3.2j, abs=1e-15)
+    assert z[1] == 0 and z[2] == 0 and z[3] == 0        # |v| <= tau (tie -> 0)
+    assert z[4] == pytest.approx(-1j, abs=1e-15)
+
+
+def test_prox_l1_subgradient_optimality():
+    rng = np.random.default_rng(1)
+    v = cn(rng, 1000)
+    tau = 0.9
+    z = O.prox_l1(v, tau)
+    on = z != 0
+    # (v - z)/tau is a subgradient of sum|z|: z/|z| on the support, |.| <= 1 off it
+    np.testing.assert_allclose((v[on] - z[on]) / tau, z[on] / np.abs(z[on]), atol=1e-14)
+    assert np.all(np.abs(v[~on]) / tau <= 1 + 1e-15)
+
+
+# --- TV prox (eq. (14)) -----------------------------------------------------------
+def test_tv_value_matches_eq14_loops():
+    rng = np.random.default_rng(2)
+    x = cn(rng, (1, 1, 5, 4))            # (B, N_y, N_x=5 lateral, N_z=4 depth)
+    tot = 0.0
+    a = x[0, 0].T                        # a[i, j]: i depth, j lateral
+    for i in range(a.shape[0]):
+        for j in range(a.shape[1]):
+            di = a[i + 1, j] - a[i, j] if i + 1 < a.shape[0] else 0.0
+            dj = a[i, j + 1] - a[i, j] if j + 1 < a.shape[1] else 0.0
+            tot += math.sqrt(abs(di) ** 2 + abs(dj) ** 2)
+    assert O.tv_value(x, (3, 2)) == pytest.approx(tot, rel=1e-14)
+
+
+@pytest.mark.parametrize("axes,shape", [((3, 2), (1, 1, 6, 5)), ((3, 2, 1), (2, 3, 4, 5))])
+def test_div_is_negative_adjoint_of_grad(axes, shape):
+    rng = np.random.default_rng(3)
+    x = cn(rng, shape)
+    p = cn(rng, (len(axes),) + shape)
+    lhs = np.real(np.vdot(p, O.tv_grad(x, axes)))
+    rhs = -np.real(np.vdot(O.tv_div(p, axes), x))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("along", ["depth", "lateral"])
+def test_prox_tv_two_pixel_closed_form(along):
+    """Two pixels: if |v1 - v2| <= 2 tau both become the mean, otherwise the
+    difference shrinks by 2 tau along (v1 - v2)/|v1 - v2|."""
+    shape = (1, 1, 1, 2) if along == "depth" else (1, 1, 2, 1)
+    for v1, v2, tau in [(1 + 1j, 0.2 - 0.3j, 0.3), (1 + 1j, 0.8 + 0.9j, 0.3), (2.0, -1j, 0.05)]:
+        v = np.array([v1, v2]).reshape(shape)
+        x, _ = O.prox_tv(v, tau, (3, 2), n_inner=3000)
+        x = x.ravel()
+        dv = v1 - v2
+        if abs(dv) <= 2 * tau:
+            e = np.array([(v1 + v2) / 2, (v1 + v2) / 2])
+        else:
+            u = dv / abs(dv)
+            e = np.array([v1 - tau * u, v2 + tau * u])
+        np.testing.assert_allclose(x, e, atol=1e-9)
+
+
+def test_prox_tv_constant_fixed_point_and_mean():
+    rng = np.random.default_rng(4)
+    c = np.full((1, 1, 7, 9), 0.3 - 0.7j)
+    x, _ = O.prox_tv(c, 0.5, (3, 2), n_inner=10)
+    np.testing.assert_allclose(x, c, atol=1e-15)
+    v = cn(rng, (1, 1, 7, 9))
+    x, _ = O.prox_tv(v, 0.4, (3, 2), n_inner=10)
+    assert abs(np.sum(x) - np.sum(v)) < 1e-12 * np.sum(np.abs(v))
+
+
+@pytest.mark.parametrize("axes,shape", [((3, 2), (1, 1, 8, 10)), ((3, 2, 1), (1, 4, 5, 6))])
+def test_prox_tv_duality_gap_vanishes(axes, shape):
+    """Primal P(x) = 1/2||x - v||^2 + tau TV(x) and dual D(p) = 1/2||v||^2 -
+    1/2||v + tau div p||^2 (|p_i| <= 1) bracket the optimum; the gap of the
+    FGP pair falls towards zero as the inner count grows."""
+    rng = np.random.default_rng(5)
+    v = cn(rng, shape)
+    tau = 0.35
+    gaps = []
+    for n_inner in (10, 100, 2000):
+        x, p = O.prox_tv(v, tau, axes, n_inner=n_inner)
+        assert np.max(np.sqrt(np.sum(np.abs(p) ** 2, axis=0))) <= 1 + 1e-12
+        P = 0.5 * np.sum(np.abs(x - v) ** 2) + tau * O.tv_value(x, axes)
+        D = 0.5 * np.sum(np.abs(v) ** 2) - 0.5 * np.sum(np.abs(v + tau * O.tv_div(p, axes)) ** 2)
+        gaps.append(P - D)
+    assert gaps[0] >= -1e-12 and gaps[0] > gaps[1] > gaps[2]
+    assert gaps[2] < 1e-6 * np.sum(np.abs(v) ** 2)
+
+
+def test_prox_tv_warm_start_continues():
+    """Ten inner steps from the dual of ten earlier steps are closer to the
+    exact prox than ten from zero."""
+    rng = np.random.default_rng(6)
+    v = cn(rng, (1, 1, 12, 12))
+    tau = 0.5
+    xe, _ = O.prox_tv(v, tau, (3, 2), n_inner=4000)
+    x1, p1 = O.prox_tv(v, tau, (3, 2), n_inner=10)
+    x2, _ = O.prox_tv(v, tau, (3, 2), n_inner=10, p0=p1)
+    assert np.linalg.norm(x2 - xe) < np.linalg.norm(x1 - xe)
+
+
+# --- Haar prox ----------------------------------------------------------------------
+def test_haar_single_level_hand_example():
+    a = np.array([[1.0, 2.0], [3.0, 5.0]])          # a[l, n]
+    x = a.reshape(1, 1, 2, 2).astype(complex)
+    c = O.haar_forward(x, (3, 2), 1)[0, 0]
+    x00, x01, x10, x11 = 1.0, 2.0, 3.0, 5.0
+    np.testing.assert_allclose(c, [[(x00 + x01 + x10 + x11) / 2, (x00 - x01 + x10 - x11) / 2],
+                                   [(x00 + x01 - x10 - x11) / 2, (x00 - x01 - x10 + x11) / 2]],
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("axes,shape", [((3, 2), (1, 1, 8, 8)), ((3, 2, 1), (1, 8, 8, 8))])
+def test_haar_orthonormal(axes, shape):
+    n = int(np.prod(shape))
+    W = np.empty((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        W[:, j] = O.haar_forward(e.reshape(shape), axes, 3).real.ravel()
+    np.testing.assert_allclose(W.T @ W, np.eye(n), atol=1e-14)
+    rng = np.random.default_rng(8)
+    x = cn(rng, shape)
+    np.testing.assert_allclose(O.haar_inverse(O.haar_forward(x, axes, 3), axes, 3), x, atol=1e-14)
+
+
+@pytest.mark.parametrize("axes,shape,blk", [((3, 2), (2, 1, 16, 24), (1, 1, 8, 8)),
+                                            ((3, 2, 1), (1, 16, 8, 16), (1, 8, 8, 8))])
+def test_haar_prox_limits(axes, shape, blk):
+    """tau = 0 is the identity; a huge tau zeroes every detail band, leaving the
+    mean of each 8 x 8 (x 8) block."""
+    rng = np.random.default_rng(9)
+    v = cn(rng, shape)
+    np.testing.assert_allclose(O.prox_haar(v, 0.0, axes, 3), v, atol=1e-13)
+    z = O.prox_haar(v, 1e9, axes, 3)
+    r = v.reshape(shape[0], shape[1] // blk[1], blk[1], shape[2] // blk[2], blk[2],
+                  shape[3] // blk[3], blk[3])
+    means = r.mean(axis=(2, 4, 6), keepdims=True)
+    expect = np.broadcast_to(means, r.shape).reshape(shape)
+    np.testing.assert_allclose(z, expect, atol=1e-12)
+
+
+def test_haar_prox_is_soft_threshold_in_coefficients():
+    rng = np.random.default_rng(10)
+    axes = (3, 2)
+    v = cn(rng, (1, 1, 8, 16))
+    tau = 0.4
+    z = O.prox_haar(v, tau, axes, 3)
+    cz = O.haar_forward(z, axes, 3)
+    cv = O.haar_forward(v, axes, 3)
+    dm = O.haar_detail_mask(cv.shape, axes, 3)
+    np.testing.assert_allclose(cz[~dm], cv[~dm], atol=1e-13)
+    mag = np.abs(cv[dm])
+    expect = np.where(mag > tau, cv[dm] * (1 - tau / mag), 0)
+    np.testing.assert_allclose(cz[dm], expect, atol=1e-13)
+
+
+# --- FISTA (eq. (15)) --------------------------------------------------------------
+def test_fista_momenta():
+    mu = O.fista_momenta(50)
+    assert mu[0] == 0.0
+    t = [1.0]
+    for _ in range(51):
+        t.append((1 + math.sqrt(1 + 4 * t[-1] ** 2)) / 2)
+    assert t[1] == pytest.approx((1 + math.sqrt(5)) / 2, abs=1e-15)
+    for k in range(1, 51):
+        assert t[k - 1] >= (k + 1) / 2 - 1e-12 or k == 1
+    np.testing.assert_allclose(mu, [(t[k] - 1) / t[k + 1] for k in range(50)], atol=1e-15)
+
+
+def _dense_problem():
+    g = O.Geometry(n_depth=8, n_x=4, n_k=12)
+    rng = np.random.default_rng(11)
+    mask = (rng.random((1, 4, 12)) < 0.8).astype(np.uint8)
+    n = int(np.prod(O.img_shape(g)))
+    cols = []
+    for unit in (1.0, 1j):
+        for j in range(n):
+            e = np.zeros(n, dtype=complex)
+            e[j] = unit
+            cols.append(O.forward(e.reshape(O.img_shape(g)), g, mask).ravel())
+    A = np.array(cols).T
+    xt = np.zeros(O.img_shape(g), dtype=complex)
+    xt[0, 0, 1, 3] = 1 + 0.5j
+    xt[0, 0, 3, 6] = -0.7j
+    y = O.forward(xt, g, mask) + 0.01 * rng.standard_normal(O.meas_shape(g)) * mask
+    return g, mask, A, y
+
+
+def _dense_fista(A, y, shape, prox, delta, iters):
+    n = A.shape[1] // 2
+    x = np.zeros(n, dtype=complex)
+    zp = x.copy()
+    mu = O.fista_momenta(iters)
+    for k in range(iters):
+        xr = np.concatenate([x.real, x.imag])
+        gr = A.T @ (A @ xr - y.ravel())
+        gc = gr[:n] + 1j * gr[n:]
+        z = prox((x - delta * gc).reshape(shape)).ravel()
+        x = z + mu[k] * (z - zp)
+        zp = z
+    return zp.reshape(shape)
+
+
+@pytest.mark.parametrize("pen", [O.PEN_L1, O.PEN_HAAR])
+def test_fista_equals_dense_matrix_fista(pen):
+    g, mask, A, y = _dense_problem()
+    L = np.linalg.svd(A, compute_uv=False)[0] ** 2
+    delta = 1 / (1.05 * L)
+    lam = 0.05
+    shape = O.img_shape(g)
+    if pen == O.PEN_L1:
+        prox = lambda v: O.prox_l1(v, lam * delta)       # noqa: E731
+    else:
+        g = g.with_(n_x=8, n_depth=8)
+        rng = np.random.default_rng(12)
+        mask = (rng.random((1, 8, 12)) < 0.8).astype(np.uint8)
+        n = int(np.prod(O.img_shape(g)))
+        A = np.array([O.forward((np.eye(n)[j] * u).reshape(O.img_shape(g)), g, mask).ravel()
+                      for u in (1.0, 1j) for j in range(n)]).T
+        y = (A @ rng.standard_normal(2 * n)).reshape(O.meas_shape(g))
+        L = np.linalg.svd(A, compute_uv=False)[0] ** 2
+        delta = 1 / (1.05 * L)
+        shape = O.img_shape(g)
+        prox = lambda v: O.prox_haar(v, lam * delta, (3, 2), 3)   # noqa: E731
+    z, _ = O.fista(y, g, mask, pen, lam, delta, 30)
+    zd = _dense_fista(A, y, shape, prox, delta, 30)
+    assert np.max(np.abs(z - zd)) < 1e-12 * max(1.0, np.max(np.abs(zd)))
+
+
+def test_fista_l1_kkt_and_rate():
+    """Long-run l1 FISTA satisfies the KKT conditions (|g_i| <= lam off the
+    support, g_i = -lam z_i/|z_i| on it) and the O(1/k^2) bound of Beck and
+    Teboulle: F(z_k) - F* <= 2 ||x0 - x*||^2 / (delta (k+1)^2)."""
+    g, mask, A, y = _dense_problem()
+    L = np.linalg.svd(A, compute_uv=False)[0] ** 2
+    delta = 1 / (1.05 * L)
+    lam = 0.05
+    zs, _ = O.fista(y, g, mask, O.PEN_L1, lam, delta, 20000)
+    gr, _ = O.grad(zs, y, g, mask)
+    on = np.abs(zs) > 1e-9
+    assert np.all(np.abs(gr[~on]) <= lam * (1 + 1e-6))
+    np.testing.assert_allclose(gr[on], -lam * zs[on] / np.abs(zs[on]), atol=1e-6 * lam)
+
+    def F(z):
+        return O.data_loss(z, y, g, mask) + lam * np.sum(np.abs(z))
+    Fs = F(zs)
+    for k in (5, 20, 80):
+        zk, hist = O.fista(y, g, mask, O.PEN_L1, lam, delta, k)
+        assert F(zk) - Fs <= 2 * np.sum(np.abs(zs) ** 2) / (delta * (k + 1) ** 2) + 1e-12
+        # history[k-1] = 1/2||Phi x^k - y||^2 + lam R(z^k)
+        assert hist[-1] >= lam * np.sum(np.abs(zk)) - 1e-12
+
+
+def test_fista_tv_reduces_objective():
+    g, mask, A, y = _dense_problem()
+    L = np.linalg.svd(A, compute_uv=False)[0] ** 2
+    delta = 1 / (1.05 * L)
+    lam = 0.02
+
+    def F(z):
+        return O.data_loss(z, y, g, mask) + lam * O.tv_value(z, (3, 2))
+    z10, _ = O.fista(y, g, mask, O.PEN_TV, lam, delta, 10, tv_inner=50)
+    z200, _ = O.fista(y, g, mask, O.PEN_TV, lam, delta, 200, tv_inner=50)
+    assert F(z200) < F(z10) < F(np.zeros_like(z10))
+
+
+# --- power iteration start (SplitMix64) and NCC (eq. (17)) ---------------------------
+def test_splitmix64_published_sequence():
+    """SplitMix64 seeded with 0 produces e220a8397b1dcdaf, 6e789e6aa1b965f4,
+    06c45d188009454f, f88bb8a8724c81ec (Vigna's reference sequence)."""
+    v = O.splitmix64(np.arange(4, dtype=np.uint64), 0)
+    assert [int(a) for a in v] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                   0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    u = O.counter_uniform(np.arange(100000, dtype=np.uint64), 7)
+    assert u.min() >= -1.0 and u.max() < 1.0 and abs(u.mean()) < 0.01
+
+
+def test_ncc_closed_forms():
+    rng = np.random.default_rng(13)
+    z = cn(rng, 500)
+    assert O.ncc(z, z) == pytest.approx(1.0, abs=1e-14)
+    assert O.ncc((0.3 - 2j) * z, z) == pytest.approx(1.0, abs=1e-14)
+    assert O.ncc(z * np.exp(1j * rng.uniform(0, 6, 500)), z) == pytest.approx(1.0, abs=1e-14)
+    w = cn(rng, 500)
+    assert -1.0 <= O.ncc(w, z) < 0.5
