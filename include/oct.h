@@ -1,0 +1,171 @@
+/*
+ * liboct: MI355X (gfx950) library for model-based iterative reconstruction
+ * (MBIR) of spectral-domain OCT with the ISAM system model
+ * (Mason et al., "Model-based iterative reconstruction for spectral-domain
+ * optical coherence tomography", Sec. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Problem statement (Sec. 2.1, eq. (1)): image x in C^N, measurements
+ * y in R^M.  N = batch * n_y * n_x * n_depth, M = batch * n_y * n_x * n_k
+ * (n_y = 1 for a B-scan).
+ *
+ * Layouts (all buffers are device pointers, dense, A-scan contiguous):
+ *   image        complex64 (interleaved float re, im), [batch][n_y][n_x][n_depth]
+ *   measurement  float32,                                [batch][n_y][n_x][n_k]
+ * Measurements are full length; pixels with mask 0 are ignored (eq. (7)).
+ *
+ * Arithmetic: complex FP32 with FP32 accumulation in the transforms; FP64
+ * for the wavenumber-grid coordinates, the per-wavenumber phase tables, the
+ * reductions (residual norm, objective, power-iteration norms) and the
+ * FISTA momentum scalars.
+ *
+ * Ownership: the caller owns every data buffer; a plan owns its tables and
+ * workspace (allocated by oct_plan_create, freed by oct_plan_destroy).
+ * Execution: calls are asynchronous on the given stream (a hipStream_t passed
+ * as void*, NULL = the default stream) unless stated otherwise.  One plan
+ * must not be used from two streams at once.
+ * Errors: no exception crosses the ABI.  Every call returns an oct_status;
+ * oct_last_error() gives a message for the last failure of the calling thread.
+ *   OCT_E_INVALID      null pointer, non-positive size, sigma * n_depth not an
+ *                      integer, odd or unsupported kb_width, bad penalty
+ *   OCT_E_UNSUPPORTED  a transform length with a prime factor above 7, sizes
+ *                      beyond the kernels' limits, Haar with a dimension not
+ *                      divisible by 2^levels
+ *   OCT_E_NOMEM        device or host allocation failed
+ *   OCT_E_DEVICE       a HIP runtime error
+ */
+#ifndef OCT_H
+#define OCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct oct_plan* oct_plan_t;
+
+typedef enum {
+  OCT_OK = 0,
+  OCT_E_INVALID = 1,
+  OCT_E_NOMEM = 2,
+  OCT_E_DEVICE = 3,
+  OCT_E_UNSUPPORTED = 4
+} oct_status;
+
+/* Regularisers R of Sec. 2.2: l1 with Psi = I (eq. (13)), isotropic total
+ * variation (eq. (14)), and a multi-level orthonormal Haar wavelet l1. */
+typedef enum { OCT_PEN_L1 = 0, OCT_PEN_TV = 1, OCT_PEN_HAAR = 2 } oct_penalty;
+
+/* Acquisition geometry (Sec. 2.1, eq. (4)-(9); optics of Sec. 3.1). */
+typedef struct {
+  int32_t lateral_dims;   /* 1 = B-scan (one lateral axis), 2 = volume          */
+  int32_t kb_width;       /* J, Kaiser-Bessel taps: 4, 6 or 8                    */
+  int64_t n_depth;        /* N_z image depth samples                             */
+  int64_t n_x, n_y;       /* lateral A-scans (n_y = 1 for a B-scan)              */
+  int64_t n_k;            /* M_k spectrometer pixels per A-scan (>= 2)           */
+  int64_t batch;          /* independent problems of the same geometry           */
+  double k_min, k_max;    /* rad/um; linear-k grid with inclusive endpoints      */
+  double dx, dy;          /* lateral pitch, um                                   */
+  double dz;              /* depth pitch, um; <= 0 selects pi / (2 N_z dk)       */
+  double z_focus;         /* focal depth, um; < 0 selects floor(N_z/2) dz        */
+  double beam_waist;      /* w0 (1/e^2 intensity radius), um; <= 0: no beam term */
+  double disp_a, disp_b;  /* Omega_m = a (m-m_c)^2 + b (m-m_c)^3, m_c=(M_k-1)/2   */
+  double oversamp;        /* sigma; K = sigma * N_z must be an integer            */
+  double kb_beta;         /* KB shape; <= 0 selects pi sqrt(J^2/s^2 (s-1/2)^2-0.8)*/
+} oct_geometry;
+
+/* Create a plan: builds the FP64-derived tables (wavenumber grid, filter
+ * phases, deapodisation, KB polynomial pieces, twiddles), packs the mask and
+ * allocates the workspace on the current device.
+ * mask: HOST pointer to uint8 [n_y][n_x][n_k] (nonzero = observed), shared by
+ * the batch; NULL means every pixel is observed (Sec. 2.1, diag(s) of eq. (7)).
+ * Synchronous. */
+oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_t* out);
+
+/* Free a plan and everything it owns.  Synchronises the device first. */
+oct_status oct_plan_destroy(oct_plan_t plan);
+
+/* Upper bound of the device bytes a plan plus one oct_mbir_solve of the given
+ * penalty hold (tables, workspace, solver state); used for admission control.
+ * Host-only, returns 0 for an invalid geometry. */
+size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty);
+
+/* y = Phi x = diag(s) Re{ diag(e^{j Omega}) D Q K x }  (eq. (7)), computed as
+ * lateral FFT, per-lateral-frequency KB-NUFFT at beta = sqrt(4k^2 - q^2)
+ * (eq. (5)-(6)), beam/focus/dispersion filter, inverse lateral FFT, real part
+ * and mask.  x: image (read), y: measurement (written). */
+oct_status oct_forward(oct_plan_t plan, const void* x, float* y, void* stream);
+
+/* x = Phi^H r, the exact adjoint of oct_forward under <a,b> = Re(a^H b)
+ * (the operator used in the gradient of eq. (3)).  r: measurement (read,
+ * masked on use), x: image (written). */
+oct_status oct_adjoint(oct_plan_t plan, const float* r, void* x, void* stream);
+
+/* g = Phi^H (Phi x - y), the gradient of eq. (2)-(3).  half_resid_sq: device
+ * double, receives 1/2 ||diag(s)(Phi x - y)||^2 summed over the batch;
+ * may be NULL. */
+oct_status oct_grad(oct_plan_t plan, const void* x, const float* y, void* g,
+                    double* half_resid_sq, void* stream);
+
+/* z = prox_{lambda delta R}(v) (eq. (16) with C = C^N).
+ * OCT_PEN_L1: complex soft threshold by tau = lambda * delta.
+ * OCT_PEN_TV: isotropic TV over the depth and lateral axes (forward
+ *   differences, zero at the last index), solved by tv_inner steps of the fast
+ *   gradient projection on the dual; state, if not NULL, is the dual
+ *   (complex64 [lateral_dims + 1][image]) used as the warm start and
+ *   overwritten with the new dual; NULL starts from zero.
+ * OCT_PEN_HAAR: haar_levels-level orthonormal Haar over the depth and lateral
+ *   axes, soft threshold on the detail bands.
+ * v and z are images and may not alias. */
+oct_status oct_prox(oct_plan_t plan, int32_t penalty, double lambda, double delta,
+                    int32_t tv_inner, int32_t haar_levels, const void* v, void* z,
+                    void* state, void* stream);
+
+/* Power iteration on Phi^H Phi (the Lipschitz constant behind the step size of
+ * Sec. 2.3): x_0 = u / ||u|| with u from the SplitMix64 counter generator
+ * (element e: real part u(2e), imaginary part u(2e+1), u uniform in [-1,1)
+ * from the top 53 bits), then iters steps of x <- w / ||w||, w = Phi^H Phi x.
+ * Writes the last ||w|| to *L_out (host).  Synchronous. */
+oct_status oct_lipschitz(oct_plan_t plan, int32_t iters, uint64_t seed, double* L_out,
+                         void* stream);
+
+typedef struct {
+  int32_t penalty;        /* oct_penalty                                          */
+  int32_t iters;          /* FISTA iterations K (>= 1)                            */
+  int32_t tv_inner;       /* inner FGP steps for TV (>= 1)                        */
+  int32_t haar_levels;    /* Haar levels (>= 1)                                   */
+  int32_t power_iters;    /* power-iteration steps when delta <= 0               */
+  int32_t reserved;
+  uint64_t seed;          /* power-iteration start vector seed                    */
+  double lambda;          /* regularisation weight (absolute)                     */
+  double delta;           /* step size; <= 0 selects 1 / (1.05 L_power)          */
+  const void* x0;         /* device image, start point; NULL = zero               */
+} oct_solve_params;
+
+typedef struct {
+  double delta_used;      /* step size actually used                              */
+  double lipschitz_est;   /* power-iteration estimate (0 when delta was given)    */
+  double* objective;      /* HOST [iters] or NULL: 1/2||Phi x^k - y||^2 +
+                             lambda R(z^k) per iteration                          */
+} oct_solve_report;
+
+/* FISTA (Sec. 2.3, eq. (15)): x^1 = x0, z^0 = x^1, t^1 = 1;
+ * z^k = prox(x^k - delta Phi^H(Phi x^k - y)); t^{k+1} = (1 + sqrt(1 + 4 t_k^2))/2;
+ * x^{k+1} = z^k + (t^k - 1)/t^{k+1} (z^k - z^{k-1}).  Writes z^K to x_out.
+ * y: measurement (read), x_out: image (written).  Synchronous when a report
+ * with an objective array or a power iteration is requested, otherwise
+ * asynchronous. */
+oct_status oct_mbir_solve(oct_plan_t plan, const float* y, const oct_solve_params* params,
+                          void* x_out, oct_solve_report* report, void* stream);
+
+/* Message for the last non-OK status returned to the calling thread. */
+const char* oct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCT_H */

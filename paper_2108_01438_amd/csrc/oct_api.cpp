@@ -1,0 +1,813 @@
+// Host side of liboct: plan construction (FP64 tables), argument validation
+// and the orchestration of the kernels behind the C ABI in include/oct.h.
+#include "../../include/oct.h"
+#include "oct_common.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+oct_status fail(oct_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(OCT_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Modified Bessel function I0 by its power series sum_k ((x/2)^k / k!)^2.
+double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 500; ++k) {
+    term *= q / ((double)k * k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+// Zero-edge Kaiser-Bessel window and its continuous Fourier transform.
+double kb0(double u, int J, double b) {
+  const double s = 1.0 - (2.0 * u / J) * (2.0 * u / J);
+  if (s < 0.0) return 0.0;
+  return (bessel_i0(b * std::sqrt(s)) - 1.0) / (bessel_i0(b) - 1.0);
+}
+
+double kb0_ft(double f, int J, double b) {
+  const double w = kPi * J * f;
+  const double a2 = b * b - w * w;
+  double sh;
+  if (a2 > 0) {
+    const double a = std::sqrt(a2);
+    sh = J * std::sinh(a) / a;
+  } else if (a2 < 0) {
+    const double a = std::sqrt(-a2);
+    sh = J * std::sin(a) / a;
+  } else {
+    sh = J;
+  }
+  const double box = (w == 0.0) ? (double)J : J * std::sin(w) / w;
+  return (sh - box) / (bessel_i0(b) - 1.0);
+}
+
+// Tap j of the J-tap window as a polynomial in x = 2 f - 1, f = frac(t):
+// Chebyshev interpolation at KB_DEG+1 nodes, converted to monomials.
+void kb_pieces(int J, double b, std::vector<float>& out) {
+  const int D = OCT_KB_DEG;
+  out.assign((size_t)J * (D + 1), 0.f);
+  for (int j = 0; j < J; ++j) {
+    std::vector<double> c(D + 1, 0.0);
+    for (int k = 0; k <= D; ++k) {
+      double s = 0.0;
+      for (int i = 0; i <= D; ++i) {
+        const double th = kPi * (i + 0.5) / (D + 1);
+        const double x = std::cos(th);
+        const double f = 0.5 * (x + 1.0);
+        s += kb0(f + J / 2 - 1 - j, J, b) * std::cos(k * th);
+      }
+      c[k] = s * (k == 0 ? 1.0 : 2.0) / (D + 1);
+    }
+    // Chebyshev -> monomial: accumulate T_k coefficients
+    std::vector<double> mono(D + 1, 0.0), tkm1(D + 1, 0.0), tk(D + 1, 0.0), tkp1(D + 1, 0.0);
+    tkm1[0] = 1.0;          // T0
+    tk[1] = 1.0;            // T1
+    for (int i = 0; i <= D; ++i) mono[i] += c[0] * tkm1[i];
+    if (D >= 1)
+      for (int i = 0; i <= D; ++i) mono[i] += c[1] * tk[i];
+    for (int k = 2; k <= D; ++k) {
+      std::fill(tkp1.begin(), tkp1.end(), 0.0);
+      for (int i = 0; i < D; ++i) tkp1[i + 1] += 2.0 * tk[i];
+      for (int i = 0; i <= D; ++i) tkp1[i] -= tkm1[i];
+      for (int i = 0; i <= D; ++i) mono[i] += c[k] * tkp1[i];
+      tkm1 = tk;
+      tk = tkp1;
+    }
+    for (int i = 0; i <= D; ++i) out[(size_t)j * (D + 1) + i] = (float)mono[i];
+  }
+}
+
+bool factorize(int n, FftDesc& d) {
+  std::memset(&d, 0, sizeof(d));
+  d.n = n;
+  if (n < 1) return false;
+  // powers of two as radix 8 with a 4 (or 4 x 4) instead of a trailing 2
+  int m = n, a = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  std::vector<int> rad;
+  const int q = a / 3, r = a % 3;
+  if (r == 1 && q >= 1) {
+    for (int i = 0; i < q - 1; ++i) rad.push_back(8);
+    rad.push_back(4);
+    rad.push_back(4);
+  } else {
+    for (int i = 0; i < q; ++i) rad.push_back(8);
+    if (r == 1) rad.push_back(2);
+    if (r == 2) rad.push_back(4);
+  }
+  for (int p : {5, 3, 7})
+    while (m % p == 0) { m /= p; rad.push_back(p); }
+  if (m != 1 || (int)rad.size() > OCT_MAX_STAGES) return false;
+  int prod = 1, mr = 8;
+  for (size_t s = 0; s < rad.size(); ++s) {
+    d.radix[s] = rad[s];
+    d.ns[s] = prod;
+    prod *= rad[s];
+    if (rad[s] < mr) mr = rad[s];
+  }
+  d.nstages = (int)rad.size();
+  d.min_radix = mr;
+  return true;
+}
+
+std::vector<float2> twiddles(int n) {
+  std::vector<float2> t(n);
+  for (int j = 0; j < n; ++j) {
+    const double a = -2.0 * kPi * (double)j / (double)n;
+    t[j] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  return t;
+}
+
+}  // namespace
+
+struct oct_plan {
+  oct_geometry g{};
+  int device = 0;
+  int lat_dims = 1;
+  int64_t Nz = 0, Nx = 0, Ny = 1, Mk = 0, B = 1, Nlat = 0, K = 0;
+  int nc = 0, J = 6;
+  double dk = 0, dz = 0, zf = 0, kbb = 0, ct = 0, df = 0;
+  FftDesc fK{}, fX{}, fY{};
+  float2 *twK = nullptr, *twX = nullptr, *twY = nullptr;
+  float* deap = nullptr;
+  double* k2x4 = nullptr;
+  float2* phase = nullptr;
+  double* q2 = nullptr;
+  float* beam = nullptr;
+  float* kbc = nullptr;
+  uint32_t* mask = nullptr;
+  int mask_words = 0;
+  float2 *X1 = nullptr, *W = nullptr;
+  double* partial = nullptr;
+  int partial_cap = 0;
+  double* dscal = nullptr;       // device scalars
+  // solver state, allocated on first use
+  float2 *za = nullptr, *zb = nullptr;
+  float2 *p0 = nullptr, *p1 = nullptr, *tvwork = nullptr;
+  double* hist = nullptr;
+  int hist_cap = 0;
+  std::vector<void*> allocs;
+
+  int64_t n_img() const { return B * Nlat * Nz; }
+  int64_t n_meas() const { return B * Nlat * Mk; }
+};
+
+namespace {
+
+template <typename T>
+oct_status dev_alloc(oct_plan* p, T** out, size_t count) {
+  void* ptr = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+  if (e != hipSuccess) return fail(OCT_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  p->allocs.push_back(ptr);
+  *out = reinterpret_cast<T*>(ptr);
+  return OCT_OK;
+}
+
+template <typename T>
+oct_status upload(oct_plan* p, T** out, const std::vector<T>& h) {
+  oct_status s = dev_alloc(p, out, h.size());
+  if (s != OCT_OK) return s;
+  HIPCHK(hipMemcpy(*out, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return OCT_OK;
+}
+
+#define OCTCHK(expr)                \
+  do {                              \
+    oct_status s_ = (expr);         \
+    if (s_ != OCT_OK) return s_;    \
+  } while (0)
+
+oct_status validate(const oct_geometry* g) {
+  if (!g) return fail(OCT_E_INVALID, "geometry is NULL");
+  if (g->lateral_dims != 1 && g->lateral_dims != 2) return fail(OCT_E_INVALID, "lateral_dims must be 1 or 2");
+  if (g->n_depth < 2 || g->n_x < 1 || g->n_y < 1 || g->n_k < 2 || g->batch < 1)
+    return fail(OCT_E_INVALID, "sizes must be positive (n_depth, n_k >= 2)");
+  if (g->lateral_dims == 1 && g->n_y != 1) return fail(OCT_E_INVALID, "a B-scan has n_y = 1");
+  if (!(g->k_max > g->k_min) || !(g->k_min > 0)) return fail(OCT_E_INVALID, "need 0 < k_min < k_max");
+  if (!(g->dx > 0) || (g->lateral_dims == 2 && !(g->dy > 0))) return fail(OCT_E_INVALID, "lateral pitch must be > 0");
+  if (g->kb_width != 4 && g->kb_width != 6 && g->kb_width != 8)
+    return fail(OCT_E_INVALID, "kb_width must be 4, 6 or 8");
+  if (!(g->oversamp >= 1.0)) return fail(OCT_E_INVALID, "oversamp must be >= 1");
+  const double Kf = g->oversamp * (double)g->n_depth;
+  if (std::fabs(Kf - std::round(Kf)) > 1e-9) return fail(OCT_E_INVALID, "oversamp * n_depth must be an integer");
+  if (std::llround(Kf) < 2 * g->kb_width) return fail(OCT_E_INVALID, "oversampled grid must hold at least 2 J cells");
+  return OCT_OK;
+}
+
+oct_status unsupported_sizes(const oct_geometry* g) {
+  const int64_t K = (int64_t)std::llround(g->oversamp * (double)g->n_depth);
+  FftDesc d;
+  if (K > 8192) return fail(OCT_E_UNSUPPORTED, "oversampled grid K > 8192");
+  if (!factorize((int)K, d)) return fail(OCT_E_UNSUPPORTED, "K has a prime factor above 7");
+  if (g->n_x > 4096 || !factorize((int)g->n_x, d)) return fail(OCT_E_UNSUPPORTED, "n_x must be 7-smooth and <= 4096");
+  if (g->lateral_dims == 2 && (g->n_y > 4096 || !factorize((int)g->n_y, d)))
+    return fail(OCT_E_UNSUPPORTED, "n_y must be 7-smooth and <= 4096");
+  if (g->n_k > 8192) return fail(OCT_E_UNSUPPORTED, "n_k > 8192");
+  // adjoint column kernel keeps the grid and the samples in LDS
+  const size_t lds = (size_t)K * 8 + (size_t)g->n_k * 16;
+  if (lds > 160 * 1024 - 4096) return fail(OCT_E_UNSUPPORTED, "grid + samples exceed the LDS of one CU");
+  return OCT_OK;
+}
+
+LineGeom lines_x(const oct_plan* p, int rows) {
+  LineGeom lg{};
+  lg.L = (int)p->Nx;
+  lg.rows = rows;
+  lg.n_lines = (int)(p->B * p->Ny);
+  lg.ocnt = 1;
+  lg.sa = p->Nx * rows;
+  lg.sb = 0;
+  lg.es = rows;
+  lg.lat_lines = (int)p->Ny;
+  return lg;
+}
+
+LineGeom lines_y(const oct_plan* p, int rows) {
+  LineGeom lg{};
+  lg.L = (int)p->Ny;
+  lg.rows = rows;
+  lg.n_lines = (int)(p->B * p->Nx);
+  lg.ocnt = (int)p->Nx;
+  lg.sa = p->Ny * p->Nx * rows;
+  lg.sb = rows;
+  lg.es = p->Nx * rows;
+  lg.lat_lines = 1;
+  return lg;
+}
+
+LatArgs lat_args(const oct_plan* p, const LineGeom& lg, bool yaxis) {
+  LatArgs a{};
+  a.lg = lg;
+  a.fd = yaxis ? p->fY : p->fX;
+  a.tw = yaxis ? p->twY : p->twX;
+  int nthr = 256, rs = lg.L;
+  a.T = lateral_pick_tile(lg, a.fd, &nthr, &rs);
+  a.rowstride = rs;
+  a.n_tiles = (lg.rows + a.T - 1) / a.T;
+  a.scale = 1.f;
+  a.scale2 = 1.f;
+  a.mask = p->mask;
+  a.mask_words = p->mask_words;
+  return a;
+}
+
+int lat_blocks(const LatArgs& a) { return a.lg.n_lines * a.n_tiles; }
+
+NufftArgs nufft_args(const oct_plan* p) {
+  NufftArgs a{};
+  a.Nz = (int)p->Nz;
+  a.Mk = (int)p->Mk;
+  a.K = (int)p->K;
+  a.nc = p->nc;
+  a.J = p->J;
+  a.Nlat = (int)p->Nlat;
+  a.n_cols = (int)(p->B * p->Nlat);
+  a.ct = p->ct;
+  a.df = p->df;
+  a.k2x4 = p->k2x4;
+  a.phase = p->phase;
+  a.q2 = p->q2;
+  a.beam = p->beam;
+  a.deap = p->deap;
+  a.kbc = p->kbc;
+  a.fK = p->fK;
+  a.twK = p->twK;
+  return a;
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// x (image, or z + mu (z - zo) when z != NULL) -> X1 = F_lat x
+oct_status run_lat_forward(oct_plan* p, const float2* x, const float2* z, const float2* zo, float mu, hipStream_t s) {
+  LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
+  a.src = x;
+  a.z = z;
+  a.zo = const_cast<float2*>(zo);
+  a.mu = mu;
+  a.dst = p->X1;
+  HIPCHK(launch_lateral(LAT_FFT, a, s));
+  if (p->lat_dims == 2) {
+    LatArgs b = lat_args(p, lines_y(p, (int)p->Nz), true);
+    b.src = p->X1;
+    b.dst = p->X1;
+    HIPCHK(launch_lateral(LAT_FFT, b, s));
+  }
+  return OCT_OK;
+}
+
+// W (after the NUFFT) -> y = s . Re(F_lat^{-1} W)
+oct_status run_meas_forward(oct_plan* p, float* y, hipStream_t s) {
+  if (p->lat_dims == 2) {
+    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    b.src = p->W;
+    b.dst = p->W;
+    b.inverse = 1;
+    b.scale = 1.f / (float)p->Ny;
+    HIPCHK(launch_lateral(LAT_FFT, b, s));
+  }
+  LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+  a.src = p->W;
+  a.dstf = y;
+  a.inverse = 1;
+  a.scale = 1.f / (float)p->Nx;
+  HIPCHK(launch_lateral(LAT_FWD_MEAS, a, s));
+  return OCT_OK;
+}
+
+// r -> W = F_lat(s . r) / N_lat
+oct_status run_meas_adjoint(oct_plan* p, const float* r, hipStream_t s) {
+  LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+  a.srcf = r;
+  a.dst = p->W;
+  a.scale = 1.f / (float)p->Nx;
+  HIPCHK(launch_lateral(LAT_ADJ_MEAS, a, s));
+  if (p->lat_dims == 2) {
+    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    b.src = p->W;
+    b.dst = p->W;
+    b.scale = 1.f / (float)p->Ny;
+    HIPCHK(launch_lateral(LAT_FFT, b, s));
+  }
+  return OCT_OK;
+}
+
+// W -> W = F_lat(s . (Re F_lat^{-1} W - y)) / N_lat with per-block sum r^2; returns #partials
+oct_status run_normal(oct_plan* p, const float* y, double* partial, int* nparts, hipStream_t s) {
+  if (p->lat_dims == 2) {
+    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    b.src = p->W;
+    b.dst = p->W;
+    b.inverse = 1;
+    b.scale = 1.f / (float)p->Ny;
+    HIPCHK(launch_lateral(LAT_FFT, b, s));
+  }
+  LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+  a.src = p->W;
+  a.dst = p->W;
+  a.y = y;
+  a.inverse = 1;
+  a.scale = 1.f / (float)p->Nx;
+  a.scale2 = 1.f / (float)p->Nx;
+  a.partial = partial;
+  if (nparts) *nparts = lat_blocks(a);
+  HIPCHK(launch_lateral(LAT_NORMAL, a, s));
+  if (p->lat_dims == 2) {
+    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    b.src = p->W;
+    b.dst = p->W;
+    b.scale = 1.f / (float)p->Ny;
+    HIPCHK(launch_lateral(LAT_FFT, b, s));
+  }
+  return OCT_OK;
+}
+
+// X1 (adjoint NUFFT output) -> g = F_lat^H X1 written to out
+oct_status run_lat_adjoint(oct_plan* p, float2* out, hipStream_t s) {
+  if (p->lat_dims == 2) {
+    LatArgs b = lat_args(p, lines_y(p, (int)p->Nz), true);
+    b.src = p->X1;
+    b.dst = p->X1;
+    b.inverse = 1;
+    HIPCHK(launch_lateral(LAT_FFT, b, s));
+  }
+  LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
+  a.src = p->X1;
+  a.dst = out;
+  a.inverse = 1;
+  HIPCHK(launch_lateral(LAT_FFT, a, s));
+  return OCT_OK;
+}
+
+int partial_need(oct_plan* p) {
+  int need = 2048;
+  const LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+  need = std::max(need, lat_blocks(a));
+  const LatArgs b = lat_args(p, lines_x(p, (int)p->Nz), false);
+  need = std::max(need, lat_blocks(b));
+  ProxGeom pg{(int)p->B, (int)p->Ny, (int)p->Nx, (int)p->Nz, p->lat_dims};
+  for (int lv = 1; lv <= 5; ++lv) need = std::max(need, haar_partials(pg, lv));
+  return need;
+}
+
+oct_status ensure_solver_state(oct_plan* p, int pen, int iters) {
+  if (!p->za) {
+    OCTCHK(dev_alloc(p, &p->za, p->n_img()));
+    OCTCHK(dev_alloc(p, &p->zb, p->n_img()));
+  }
+  if (pen == OCT_PEN_TV && !p->p0) {
+    const int nd = p->lat_dims + 1;
+    OCTCHK(dev_alloc(p, &p->p0, (size_t)p->n_img() * nd));
+    OCTCHK(dev_alloc(p, &p->p1, (size_t)p->n_img() * nd));
+    ProxGeom pg{(int)p->B, (int)p->Ny, (int)p->Nx, (int)p->Nz, p->lat_dims};
+    OCTCHK(dev_alloc(p, &p->tvwork, tv_work_elems(pg)));
+  }
+  if (iters > p->hist_cap) {
+    OCTCHK(dev_alloc(p, &p->hist, (size_t)iters));
+    p->hist_cap = iters;
+  }
+  return OCT_OK;
+}
+
+std::vector<float> fgp_momenta(int n) {
+  std::vector<float> mu(n);
+  double t = 1.0;
+  for (int k = 0; k < n; ++k) {
+    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    mu[k] = (float)((t - 1.0) / tn);
+    t = tn;
+  }
+  return mu;
+}
+
+ProxGeom prox_geom(const oct_plan* p) {
+  return ProxGeom{(int)p->B, (int)p->Ny, (int)p->Nx, (int)p->Nz, p->lat_dims};
+}
+
+oct_status check_haar(const oct_plan* p, int levels) {
+  if (levels < 1 || levels > (p->lat_dims == 1 ? 5 : 4))
+    return fail(OCT_E_UNSUPPORTED, "haar_levels must be 1..5 (B-scan) or 1..4 (volume)");
+  const int64_t bs = (int64_t)1 << levels;
+  if (p->Nz % bs || p->Nx % bs || (p->lat_dims == 2 && p->Ny % bs))
+    return fail(OCT_E_UNSUPPORTED, "Haar needs every image dimension divisible by 2^levels");
+  return OCT_OK;
+}
+
+// z = prox(v) with FP64 partials of R(z) in p->partial[0..*np)
+oct_status run_prox(oct_plan* p, int pen, float tau, int tv_inner, int haar_levels, const float2* v, float2* z,
+                    const float2* p_in, float2* p_out, int* np, hipStream_t s) {
+  ProxGeom pg = prox_geom(p);
+  if (pen == OCT_PEN_L1) {
+    const int nb = 1024;
+    HIPCHK(launch_prox_l1(v, z, p->n_img(), tau, p->partial, nb, s));
+    *np = nb;
+  } else if (pen == OCT_PEN_HAAR) {
+    OCTCHK(check_haar(p, haar_levels));
+    HIPCHK(launch_prox_haar(pg, haar_levels, v, z, tau, p->partial, s));
+    *np = haar_partials(pg, haar_levels);
+  } else if (pen == OCT_PEN_TV) {
+    if (tv_inner < 1 || tv_inner > 1000) return fail(OCT_E_INVALID, "tv_inner must be 1..1000");
+    std::vector<float> mom = fgp_momenta(tv_inner);
+    HIPCHK(launch_prox_tv(pg, tv_inner, mom.data(), v, z, p_in, p_out, tau, p->partial, p->tvwork, s));
+    *np = tv_partials(pg, tv_inner);
+  } else {
+    return fail(OCT_E_INVALID, "unknown penalty");
+  }
+  return OCT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* oct_last_error(void) { return g_err.c_str(); }
+
+size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
+  if (validate(g) != OCT_OK) return 0;
+  const int64_t Nlat = g->n_x * g->n_y;
+  const int64_t N = g->batch * Nlat * g->n_depth;
+  const int64_t M = g->batch * Nlat * g->n_k;
+  const int64_t K = (int64_t)std::llround(g->oversamp * (double)g->n_depth);
+  const int nd = g->lateral_dims + 1;
+  size_t b = 0;
+  b += (size_t)(K + g->n_x + g->n_y) * 8 + (size_t)g->n_depth * 4 + (size_t)g->n_k * (8 + 8) +
+       (size_t)Nlat * (8 + 4) + (size_t)Nlat * ((g->n_k + 31) / 32) * 4;
+  b += (size_t)N * 8 + (size_t)M * 8;            // workspace X1, W
+  b += (size_t)N * 8 * 2;                        // FISTA iterates
+  if (penalty == OCT_PEN_TV) b += (size_t)N * 8 * (2 * nd + 1 + nd);
+  b += 64 * 1024 * 8;                            // partials, scalars, history
+  return b;
+}
+
+oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_t* out) {
+  if (!out) return fail(OCT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  OCTCHK(validate(g));
+  OCTCHK(unsupported_sizes(g));
+  oct_plan* p = new (std::nothrow) oct_plan();
+  if (!p) return fail(OCT_E_NOMEM, "host allocation failed");
+  p->g = *g;
+  HIPCHK(hipGetDevice(&p->device));
+  p->lat_dims = g->lateral_dims;
+  p->Nz = g->n_depth;
+  p->Nx = g->n_x;
+  p->Ny = g->n_y;
+  p->Mk = g->n_k;
+  p->B = g->batch;
+  p->Nlat = p->Nx * p->Ny;
+  p->K = (int64_t)std::llround(g->oversamp * (double)g->n_depth);
+  p->nc = (int)(p->Nz / 2);
+  p->J = g->kb_width;
+  p->dk = (g->k_max - g->k_min) / (double)(p->Mk - 1);
+  p->dz = g->dz > 0 ? g->dz : kPi / (2.0 * (double)p->Nz * p->dk);
+  p->zf = g->z_focus >= 0 ? g->z_focus : p->nc * p->dz;
+  const double s = g->oversamp;
+  p->kbb = g->kb_beta > 0 ? g->kb_beta
+                          : kPi * std::sqrt((double)p->J * p->J / (s * s) * (s - 0.5) * (s - 0.5) - 0.8);
+  p->ct = (double)p->K * p->dz / (2.0 * kPi);
+  p->df = p->zf - p->nc * p->dz;
+  if (std::fabs(p->df) < 1e-12 * std::max(1.0, std::fabs(p->zf))) p->df = 0.0;
+  factorize((int)p->K, p->fK);
+  factorize((int)p->Nx, p->fX);
+  factorize((int)p->Ny, p->fY);
+
+  oct_status st = OCT_OK;
+  auto cleanup = [&](oct_status e) {
+    oct_plan_destroy(p);
+    return e;
+  };
+  // wavenumber grid as linspace(k_min, k_max, M_k) with an exact last point
+  std::vector<double> k(p->Mk), k2x4(p->Mk);
+  for (int64_t m = 0; m < p->Mk; ++m) k[m] = g->k_min + (double)m * p->dk;
+  k[p->Mk - 1] = g->k_max;
+  std::vector<float2> ph(p->Mk);
+  const double mc = (double)(p->Mk - 1) / 2.0;
+  for (int64_t m = 0; m < p->Mk; ++m) {
+    k2x4[m] = 4.0 * k[m] * k[m];
+    const double u = (double)m - mc;
+    const double om = g->disp_a * u * u + g->disp_b * u * u * u;
+    const double a = -2.0 * k[m] * p->zf + om;
+    ph[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  std::vector<double> q2(p->Nlat);
+  std::vector<float> beam(p->Nlat);
+  auto fftfreq = [](int64_t i, int64_t n, double d) {
+    const int64_t h = (n - 1) / 2 + 1;
+    const double f = (i < h) ? (double)i : (double)(i - n);
+    return f / ((double)n * d);
+  };
+  for (int64_t iy = 0; iy < p->Ny; ++iy) {
+    for (int64_t ix = 0; ix < p->Nx; ++ix) {
+      const double qx = 2.0 * kPi * fftfreq(ix, p->Nx, g->dx);
+      const double qy = (p->lat_dims == 2) ? 2.0 * kPi * fftfreq(iy, p->Ny, g->dy) : 0.0;
+      const double qq = qy * qy + qx * qx;
+      q2[iy * p->Nx + ix] = qq;
+      beam[iy * p->Nx + ix] = g->beam_waist > 0 ? (float)std::exp(-qq * g->beam_waist * g->beam_waist / 8.0) : 1.f;
+    }
+  }
+  std::vector<float> deap(p->Nz);
+  for (int64_t n = 0; n < p->Nz; ++n) {
+    const double f = (double)(n - p->nc) / (double)p->K;
+    deap[n] = (float)(1.0 / kb0_ft(f, p->J, p->kbb));
+  }
+  std::vector<float> kbc;
+  kb_pieces(p->J, p->kbb, kbc);
+
+  if ((st = upload(p, &p->twK, twiddles((int)p->K))) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->twX, twiddles((int)p->Nx))) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->twY, twiddles((int)p->Ny))) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->k2x4, k2x4)) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->phase, ph)) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->q2, q2)) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->beam, beam)) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->deap, deap)) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->kbc, kbc)) != OCT_OK) return cleanup(st);
+  if (mask) {
+    p->mask_words = (int)((p->Mk + 31) / 32);
+    std::vector<uint32_t> bits((size_t)p->Nlat * p->mask_words, 0u);
+    for (int64_t l = 0; l < p->Nlat; ++l)
+      for (int64_t m = 0; m < p->Mk; ++m)
+        if (mask[l * p->Mk + m]) bits[(size_t)l * p->mask_words + (m >> 5)] |= 1u << (m & 31);
+    if ((st = upload(p, &p->mask, bits)) != OCT_OK) return cleanup(st);
+  }
+  if ((st = dev_alloc(p, &p->X1, p->n_img())) != OCT_OK) return cleanup(st);
+  if ((st = dev_alloc(p, &p->W, p->n_meas())) != OCT_OK) return cleanup(st);
+  p->partial_cap = partial_need(p);
+  if ((st = dev_alloc(p, &p->partial, (size_t)p->partial_cap * 2)) != OCT_OK) return cleanup(st);
+  if ((st = dev_alloc(p, &p->dscal, 16)) != OCT_OK) return cleanup(st);
+  // the adjoint column kernel may need more than 64 KB of dynamic LDS
+  *out = p;
+  return OCT_OK;
+}
+
+oct_status oct_plan_destroy(oct_plan_t p) {
+  if (!p) return OCT_OK;
+  hipDeviceSynchronize();
+  for (void* a : p->allocs) hipFree(a);
+  delete p;
+  return OCT_OK;
+}
+
+oct_status oct_forward(oct_plan_t p, const void* x, float* y, void* stream) {
+  if (!p || !x || !y) return fail(OCT_E_INVALID, "null argument");
+  hipStream_t s = S(stream);
+  OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
+  HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+  OCTCHK(run_meas_forward(p, y, s));
+  return OCT_OK;
+}
+
+oct_status oct_adjoint(oct_plan_t p, const float* r, void* x, void* stream) {
+  if (!p || !r || !x) return fail(OCT_E_INVALID, "null argument");
+  hipStream_t s = S(stream);
+  OCTCHK(run_meas_adjoint(p, r, s));
+  HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+  OCTCHK(run_lat_adjoint(p, (float2*)x, s));
+  return OCT_OK;
+}
+
+oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, double* half_resid_sq, void* stream) {
+  if (!p || !x || !y || !gout) return fail(OCT_E_INVALID, "null argument");
+  hipStream_t s = S(stream);
+  OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
+  HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+  int np = 0;
+  OCTCHK(run_normal(p, y, p->partial, &np, s));
+  if (half_resid_sq) HIPCHK(launch_reduce_sum(p->partial, np, half_resid_sq, 0.5, 0, s));
+  HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+  OCTCHK(run_lat_adjoint(p, (float2*)gout, s));
+  return OCT_OK;
+}
+
+oct_status oct_prox(oct_plan_t p, int32_t pen, double lambda, double delta, int32_t tv_inner, int32_t haar_levels,
+                    const void* v, void* z, void* state, void* stream) {
+  if (!p || !v || !z) return fail(OCT_E_INVALID, "null argument");
+  if (v == z) return fail(OCT_E_INVALID, "v and z may not alias");
+  if (!(lambda >= 0) || !(delta > 0)) return fail(OCT_E_INVALID, "need lambda >= 0 and delta > 0");
+  hipStream_t s = S(stream);
+  OCTCHK(ensure_solver_state(p, pen, 1));
+  const float tau = (float)(lambda * delta);
+  int np = 0;
+  if (pen == OCT_PEN_TV) {
+    if (!(tau > 0)) {
+      HIPCHK(launch_copy((const float2*)v, (float2*)z, p->n_img(), s));
+      return OCT_OK;
+    }
+    const int64_t npel = p->n_img() * (p->lat_dims + 1);
+    OCTCHK(run_prox(p, pen, tau, tv_inner, haar_levels, (const float2*)v, (float2*)z, (const float2*)state, p->p0,
+                    &np, s));
+    if (state) HIPCHK(launch_copy(p->p0, (float2*)state, npel, s));
+    return OCT_OK;
+  }
+  return run_prox(p, pen, tau, tv_inner, haar_levels, (const float2*)v, (float2*)z, nullptr, nullptr, &np, s);
+}
+
+oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, double* L_out, void* stream) {
+  if (!p || !L_out || iters < 1) return fail(OCT_E_INVALID, "bad argument");
+  hipStream_t s = S(stream);
+  OCTCHK(ensure_solver_state(p, OCT_PEN_L1, 1));
+  const int64_t n = p->n_img();
+  const int nb = 1024;
+  HIPCHK(launch_fill_counter_uniform(p->za, n, seed, s));
+  HIPCHK(launch_norm2_partial(p->za, n, p->partial, nb, s));
+  HIPCHK(launch_reduce_sum(p->partial, nb, p->dscal, 1.0, 0, s));
+  HIPCHK(launch_scale_by_inv_sqrt(p->za, p->za, n, p->dscal, s));
+  for (int it = 0; it < iters; ++it) {
+    OCTCHK(run_lat_forward(p, p->za, nullptr, nullptr, 0.f, s));
+    HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+    OCTCHK(run_normal(p, nullptr, nullptr, nullptr, s));
+    HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+    OCTCHK(run_lat_adjoint(p, p->zb, s));
+    HIPCHK(launch_norm2_partial(p->zb, n, p->partial, nb, s));
+    HIPCHK(launch_reduce_sum(p->partial, nb, p->dscal, 1.0, 0, s));
+    HIPCHK(launch_scale_by_inv_sqrt(p->zb, p->za, n, p->dscal, s));
+  }
+  double sumsq = 0.0;
+  HIPCHK(hipMemcpyAsync(&sumsq, p->dscal, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *L_out = std::sqrt(sumsq);
+  return OCT_OK;
+}
+
+oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* prm, void* x_out,
+                          oct_solve_report* rep, void* stream) {
+  if (!p || !y || !prm || !x_out) return fail(OCT_E_INVALID, "null argument");
+  if (prm->iters < 1) return fail(OCT_E_INVALID, "iters must be >= 1");
+  if (prm->penalty < 0 || prm->penalty > 2) return fail(OCT_E_INVALID, "unknown penalty");
+  if (!(prm->lambda >= 0)) return fail(OCT_E_INVALID, "lambda must be >= 0");
+  if (prm->penalty == OCT_PEN_HAAR) OCTCHK(check_haar(p, prm->haar_levels));
+  if (prm->penalty == OCT_PEN_TV && (prm->tv_inner < 1 || prm->tv_inner > 1000))
+    return fail(OCT_E_INVALID, "tv_inner must be 1..1000");
+  hipStream_t s = S(stream);
+  OCTCHK(ensure_solver_state(p, prm->penalty, prm->iters));
+  double delta = prm->delta, Lest = 0.0;
+  if (!(delta > 0)) {
+    if (prm->power_iters < 1) return fail(OCT_E_INVALID, "power_iters must be >= 1 when delta <= 0");
+    OCTCHK(oct_lipschitz(p, prm->power_iters, prm->seed, &Lest, stream));
+    delta = 1.0 / (1.05 * Lest);
+  }
+  const int64_t n = p->n_img();
+  // FISTA momenta mu_k = (t_k - 1) / t_{k+1}, t_1 = 1 (FP64)
+  std::vector<double> mu(prm->iters);
+  {
+    double t = 1.0;
+    for (int k = 0; k < prm->iters; ++k) {
+      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+      mu[k] = (t - 1.0) / tn;
+      t = tn;
+    }
+  }
+  float2* zc = p->za;   // z^{k-1}
+  float2* zo = p->zb;   // z^{k-2}
+  if (prm->x0) {
+    HIPCHK(launch_copy((const float2*)prm->x0, zc, n, s));
+    HIPCHK(launch_copy((const float2*)prm->x0, zo, n, s));
+  } else {
+    HIPCHK(launch_zero(zc, n, s));
+    HIPCHK(launch_zero(zo, n, s));
+  }
+  const bool want_obj = rep && rep->objective;
+  const float tau = (float)(prm->lambda * delta);
+  float2* pin = nullptr;
+  float2* pout = p->p0;
+  const bool fused_l1 = (prm->penalty == OCT_PEN_L1) && p->lat_dims == 1;
+  double* res_part = p->partial;
+  double* pen_part = p->partial + p->partial_cap;
+  float mu_prev = 0.f;
+  if (fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, 0.f, s));
+  for (int k = 0; k < prm->iters; ++k) {
+    if (!fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s));
+    HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+    int nres = 0, npen = 0;
+    OCTCHK(run_normal(p, y, res_part, &nres, s));
+    HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+    if (fused_l1) {
+      LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
+      a.src = p->X1;
+      a.dst = p->X1;
+      a.inverse = 1;
+      a.z = zc;
+      a.zo = zo;
+      a.mu = mu_prev;
+      a.mu_next = (float)mu[k];
+      a.delta = (float)delta;
+      a.tau = tau;
+      a.partial = pen_part;
+      npen = lat_blocks(a);
+      HIPCHK(launch_lateral(LAT_UPDATE_L1, a, s));
+    } else {
+      if (p->lat_dims == 2) {
+        LatArgs b = lat_args(p, lines_y(p, (int)p->Nz), true);
+        b.src = p->X1;
+        b.dst = p->X1;
+        b.inverse = 1;
+        HIPCHK(launch_lateral(LAT_FFT, b, s));
+      }
+      LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
+      a.src = p->X1;
+      a.dst = p->X1;
+      a.inverse = 1;
+      a.z = zc;
+      a.zo = zo;
+      a.mu = mu_prev;
+      a.delta = (float)delta;
+      HIPCHK(launch_lateral(LAT_UPDATE, a, s));
+      // z^k -> zo (z^{k-2} is no longer needed)
+      if (prm->penalty == OCT_PEN_TV && !(tau > 0)) {
+        HIPCHK(launch_copy(p->X1, zo, n, s));
+        HIPCHK(launch_zero(reinterpret_cast<float2*>(pen_part), 1, s));
+        npen = 1;
+      } else {
+        double* save = p->partial;
+        p->partial = pen_part;
+        oct_status st = run_prox(p, prm->penalty, tau, prm->tv_inner, prm->haar_levels, p->X1, zo, pin, pout,
+                                 &npen, s);
+        p->partial = save;
+        OCTCHK(st);
+        if (prm->penalty == OCT_PEN_TV) {
+          pin = pout;
+          pout = (pout == p->p0) ? p->p1 : p->p0;
+        }
+      }
+    }
+    if (want_obj) HIPCHK(launch_objective(res_part, nres, pen_part, npen, prm->lambda, p->hist + k, s));
+    std::swap(zc, zo);
+    mu_prev = (float)mu[k];
+  }
+  HIPCHK(launch_copy(zc, (float2*)x_out, n, s));
+  if (rep) {
+    rep->delta_used = delta;
+    rep->lipschitz_est = Lest;
+    if (want_obj) {
+      HIPCHK(hipMemcpyAsync(rep->objective, p->hist, sizeof(double) * prm->iters, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+  }
+  return OCT_OK;
+}
+
+}  // extern "C"

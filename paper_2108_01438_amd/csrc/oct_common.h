@@ -1,0 +1,118 @@
+// Internal declarations shared by the host plan and the kernels of liboct.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define OCT_MAX_STAGES 16
+#define OCT_KB_DEG 9             // degree of each KB polynomial piece
+#define OCT_MAX_J 8
+
+// Mixed-radix factorisation of one transform length for the LDS Stockham FFT.
+struct FftDesc {
+  int n;
+  int nstages;
+  int radix[OCT_MAX_STAGES];
+  int ns[OCT_MAX_STAGES];        // product of the radices before each stage
+  int min_radix;
+};
+
+// Lines of a lateral transform.  Element (line o, lateral index l, row i) of a
+// [.. ][lateral][rows] array lives at base(o) + l * es + i, with
+// base(o) = (o / ocnt) * sa + (o % ocnt) * sb (all in elements).
+struct LineGeom {
+  int L;             // transform length
+  int rows;          // rows per lateral position (n_depth or n_k)
+  int n_lines;
+  int ocnt;
+  int64_t sa, sb, es;
+  int lat_lines;     // lines per batch item that carry a mask (x-lines of a volume)
+};
+
+// Operation applied by the lateral pass around its transform.
+enum LatMode {
+  LAT_FFT = 0,        // dst = scale * FFT_sign(src)  [src optionally z + mu (z - zo)]
+  LAT_FWD_MEAS = 1,   // y = s . Re( scale * IFFT(src) )                 -> float dst
+  LAT_ADJ_MEAS = 2,   // dst = scale * FFT( s . r )                      <- float src
+  LAT_NORMAL = 3,     // dst = scale2 * FFT( s . (Re(scale * IFFT(src)) - y) ), sum r^2
+  LAT_UPDATE = 4,     // v = x - delta * scale * IFFT(src), x = z + mu (z - zo)
+  LAT_UPDATE_L1 = 5   // as UPDATE, then z' = soft(v), x' = z' + mu' (z' - z),
+                      // z' -> zo, dst = FFT(x')
+};
+
+struct LatArgs {
+  LineGeom lg;
+  FftDesc fd;
+  const float2* tw;      // e^{-2 pi i j / L}, j < L
+  int T;                 // rows per tile
+  int n_tiles;
+  int rowstride;         // LDS row stride (>= L)
+  int inverse;           // transform sign (+ when 1)
+  float scale, scale2;
+  // operands (meaning depends on mode)
+  const float2* src;
+  const float* srcf;
+  float2* dst;
+  float* dstf;
+  const float* y;
+  const uint32_t* mask;  // [lat][mask_words] bits, NULL = all observed
+  int mask_words;
+  const float2* z;       // current iterate z^{k-1}
+  float2* zo;            // previous iterate z^{k-2}; receives z^k in UPDATE_L1
+  float mu;              // momentum forming x from (z, zo)
+  float mu_next;         // momentum forming the next x (UPDATE_L1)
+  float delta;
+  float tau;
+  double* partial;       // per-block FP64 partial sums (NORMAL: 1/2 r^2; UPDATE_L1: |z'|)
+};
+
+struct NufftArgs {
+  int Nz, Mk, K, nc, J, Nlat;
+  int n_cols;
+  double ct;             // K dz / (2 pi): oversampled-grid coordinate per unit beta
+  double df;             // z_f - n_c dz (focus offset); 0 skips its phase
+  const double* k2x4;    // [Mk] 4 k_m^2
+  const float2* phase;   // [Mk] e^{j(-2 k_m z_f + Omega_m)}
+  const double* q2;      // [Nlat] |q|^2
+  const float* beam;     // [Nlat] e^{-q^2 w0^2 / 8}
+  const float* deap;     // [Nz] 1 / Psi0((n - n_c) / K)
+  const float* kbc;      // [J][OCT_KB_DEG + 1] polynomial pieces in x = 2f - 1
+  FftDesc fK;
+  const float2* twK;
+};
+
+// Launchers (kernels in the .hip files; all asynchronous on `s`).
+hipError_t launch_lateral(LatMode mode, const LatArgs& a, hipStream_t s);
+int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* rowstride);
+hipError_t launch_nufft_fwd(const NufftArgs& a, const float2* X1, float2* W, hipStream_t s);
+hipError_t launch_nufft_adj(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s);
+size_t nufft_adj_lds_bytes(const NufftArgs& a);
+
+// Reductions and elementwise helpers.
+hipError_t launch_reduce_sum(const double* partial, int n, double* out, double scale,
+                             int accumulate, hipStream_t s);
+hipError_t launch_norm2_partial(const float2* x, int64_t n, double* partial, int nblocks,
+                                hipStream_t s);
+hipError_t launch_scale_by_inv_sqrt(const float2* x, float2* y, int64_t n, const double* sumsq,
+                                    hipStream_t s);
+hipError_t launch_fill_counter_uniform(float2* x, int64_t n, uint64_t seed, hipStream_t s);
+hipError_t launch_copy(const float2* x, float2* y, int64_t n, hipStream_t s);
+hipError_t launch_zero(float2* x, int64_t n, hipStream_t s);
+hipError_t launch_objective(const double* res_partial, int nres, const double* pen_partial,
+                            int npen, double lambda, double* out, hipStream_t s);
+
+// Proximal operators.
+struct ProxGeom {
+  int B, Ny, Nx, Nz;     // image [B][Ny][Nx][Nz]
+  int lateral_dims;
+};
+hipError_t launch_prox_l1(const float2* v, float2* z, int64_t n, float tau, double* partial,
+                          int nblocks, hipStream_t s);
+int haar_partials(const ProxGeom& g, int levels);
+hipError_t launch_prox_haar(const ProxGeom& g, int levels, const float2* v, float2* z,
+                            float tau, double* partial, hipStream_t s);
+int tv_partials(const ProxGeom& g, int n_inner);
+hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, const float2* v,
+                          float2* z, const float2* p_in, float2* p_out, float tau,
+                          double* partial, float2* work, hipStream_t s);
+size_t tv_work_elems(const ProxGeom& g);

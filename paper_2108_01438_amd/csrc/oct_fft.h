@@ -1,0 +1,204 @@
+// In-LDS mixed-radix Stockham FFT (radices 2, 3, 4, 5, 7, 8) for gfx950.
+//
+// Each stage with radix R and sub-transform size Ns reads butterfly j from
+// positions j + r n/R, applies the twiddles w^{r (j mod Ns)} with
+// w = e^{-+2 pi i / (Ns R)}, takes a radix-R DFT and writes output r to
+// (j div Ns) Ns R + (j mod Ns) + r Ns, which leaves the result in natural
+// order (the Stockham autosort formulation of Govindaraju et al., 2008).
+// The transform runs in place in one LDS buffer: every thread first pulls
+// all of its butterflies into registers, a barrier separates the reads from
+// the writes, so the per-stage work must fit MAXB butterflies per thread.
+// Twiddles come from an FP64-built table e^{-2 pi i j / n} rounded to FP32.
+#pragma once
+#include "oct_common.h"
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 rot90(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <int R, bool INV> struct Dft;
+
+template <bool INV> struct Dft<2, INV> {
+  static __device__ __forceinline__ void run(float2* a) {
+    float2 t = a[1];
+    a[1] = csub(a[0], t);
+    a[0] = cadd(a[0], t);
+  }
+};
+
+template <bool INV> struct Dft<4, INV> {
+  static __device__ __forceinline__ void run(float2* a) {
+    float2 s0 = cadd(a[0], a[2]), d0 = csub(a[0], a[2]);
+    float2 s1 = cadd(a[1], a[3]), d1 = rot90<INV>(csub(a[1], a[3]));
+    a[0] = cadd(s0, s1);
+    a[2] = csub(s0, s1);
+    a[1] = cadd(d0, d1);
+    a[3] = csub(d0, d1);
+  }
+};
+
+template <bool INV> struct Dft<8, INV> {
+  static __device__ __forceinline__ void run(float2* a) {
+    const float h = 0.70710678118654752440f;
+    float2 b[4], c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      b[k] = cadd(a[k], a[k + 4]);
+      c[k] = csub(a[k], a[k + 4]);
+    }
+    // c_k *= w8^k, w8 = e^{-+ i pi / 4}
+    {
+      float2 t = c[1];
+      c[1] = INV ? make_float2(h * (t.x - t.y), h * (t.x + t.y))
+                 : make_float2(h * (t.x + t.y), h * (t.y - t.x));
+      c[2] = rot90<INV>(c[2]);
+      t = c[3];
+      c[3] = INV ? make_float2(-h * (t.x + t.y), h * (t.x - t.y))
+                 : make_float2(h * (t.y - t.x), -h * (t.x + t.y));
+    }
+    Dft<4, INV>::run(b);
+    Dft<4, INV>::run(c);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      a[2 * m] = b[m];
+      a[2 * m + 1] = c[m];
+    }
+  }
+};
+
+// Radix 3, 5, 7: direct DFT with compile-time roots of unity.
+template <int R> struct Roots;
+template <> struct Roots<3> {
+  static __device__ __forceinline__ float c(int k) {
+    const float v[3] = {1.0f, -0.5f, -0.5f};
+    return v[k];
+  }
+  static __device__ __forceinline__ float s(int k) {
+    const float v[3] = {0.0f, 0.86602540378443864676f, -0.86602540378443864676f};
+    return v[k];
+  }
+};
+template <> struct Roots<5> {
+  static __device__ __forceinline__ float c(int k) {
+    const float v[5] = {1.0f, 0.30901699437494742410f, -0.80901699437494742410f,
+                        -0.80901699437494742410f, 0.30901699437494742410f};
+    return v[k];
+  }
+  static __device__ __forceinline__ float s(int k) {
+    const float v[5] = {0.0f, 0.95105651629515357212f, 0.58778525229247312917f,
+                        -0.58778525229247312917f, -0.95105651629515357212f};
+    return v[k];
+  }
+};
+template <> struct Roots<7> {
+  static __device__ __forceinline__ float c(int k) {
+    const float v[7] = {1.0f, 0.62348980185873353053f, -0.22252093395631440429f,
+                        -0.90096886790241912624f, -0.90096886790241912624f,
+                        -0.22252093395631440429f, 0.62348980185873353053f};
+    return v[k];
+  }
+  static __device__ __forceinline__ float s(int k) {
+    const float v[7] = {0.0f, 0.78183148246802980871f, 0.97492791218182360702f,
+                        0.43388373911755812048f, -0.43388373911755812048f,
+                        -0.97492791218182360702f, -0.78183148246802980871f};
+    return v[k];
+  }
+};
+
+template <int R, bool INV> struct DftOdd {
+  static __device__ __forceinline__ void run(float2* a) {
+    float2 out[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      float2 acc = a[0];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const int k = (r * s) % R;
+        // e^{-+ 2 pi i k / R} = cos - + i sin
+        const float cr = Roots<R>::c(k);
+        const float si = INV ? Roots<R>::s(k) : -Roots<R>::s(k);
+        acc.x += a[r].x * cr - a[r].y * si;
+        acc.y += a[r].x * si + a[r].y * cr;
+      }
+      out[s] = acc;
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) a[s] = out[s];
+  }
+};
+template <bool INV> struct Dft<3, INV> : DftOdd<3, INV> {};
+template <bool INV> struct Dft<5, INV> : DftOdd<5, INV> {};
+template <bool INV> struct Dft<7, INV> : DftOdd<7, INV> {};
+
+// One Stockham stage over `nrows` transforms of length n stored at
+// buf[row * rowstride + i].
+template <int R, int MAXB, bool INV>
+__device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride, int n, int Ns,
+                                          const float2* __restrict__ tw, int tid, int nthr) {
+  const int nb = n / R;
+  const int total = nrows * nb;
+  const int tws = n / (Ns * R);
+  float2 v[MAXB][R];
+  int off[MAXB], jj[MAXB];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int item = tid + b * nthr;
+    if (item < total) {
+      const int row = item / nb;
+      const int j = item - row * nb;
+      const float2* src = buf + row * rowstride + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = src[r * nb];
+      off[b] = row * rowstride;
+      jj[b] = j;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int item = tid + b * nthr;
+    if (item < total) {
+      const int j = jj[b];
+      const int k = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[r * k * tws];
+          if (INV) w.y = -w.y;
+          v[b][r] = cmul(v[b][r], w);
+        }
+      }
+      Dft<R, INV>::run(v[b]);
+      float2* dst = buf + off[b] + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of `nrows` rows in LDS; all threads of the block participate.
+template <int MAXB, bool INV>
+__device__ __forceinline__ void fft_rows(float2* buf, int nrows, int rowstride, const FftDesc& d,
+                                         const float2* __restrict__ tw, int tid, int nthr) {
+  for (int s = 0; s < d.nstages; ++s) {
+    const int Ns = d.ns[s];
+    switch (d.radix[s]) {
+      case 8: fft_stage<8, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 4: fft_stage<4, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 2: fft_stage<2, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 5: fft_stage<5, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 3: fft_stage<3, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      default: fft_stage<7, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+    }
+  }
+}

@@ -1,0 +1,534 @@
+// Proximal operators of Sec. 2.2-2.3 (eq. (12)-(14), (16)), FP64 reductions
+// and small elementwise helpers.
+//
+// * l1 (Psi = I): complex soft threshold z = v max(0, 1 - tau/|v|).
+// * Haar: a multi-level orthonormal Haar pyramid over the depth and lateral
+//   axes is local to blocks of 2^levels samples per axis.  Each thread takes a
+//   2x2(x2) group, keeps its soft-thresholded detail coefficients in registers
+//   and hands the low band one level up through LDS; the coarsest low band is
+//   left untouched and the synthesis walks back down.
+// * TV: isotropic complex TV (forward differences, zero at the last index)
+//   by the fast gradient projection (FGP) of Beck and Teboulle on the dual,
+//   x = v + tau div p.  The 2-D path runs all inner steps of a tile in LDS
+//   (temporal blocking with a halo as wide as the dependence cone); the
+//   general path (volumes) runs one pass per inner step in global memory.
+// All partial sums are per block in FP64 and summed in a fixed order.
+#include "oct_fft.h"
+
+namespace {
+
+__device__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += sh[i];
+  }
+  return s;
+}
+
+__global__ void reduce_kernel(const double* __restrict__ p, int n, double* out, double scale, int accumulate) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += p[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = accumulate ? out[0] + scale * s : scale * s;
+}
+
+__global__ void objective_kernel(const double* __restrict__ rp, int nr, const double* __restrict__ pp, int np,
+                                 double lambda, double* out) {
+  __shared__ double sh[16];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) a += rp[i];
+  const double sa = block_sum(a, sh);
+  __syncthreads();
+  for (int i = threadIdx.x; i < np; i += blockDim.x) b += pp[i];
+  const double sb = block_sum(b, sh);
+  if (threadIdx.x == 0) out[0] = 0.5 * sa + lambda * sb;
+}
+
+__global__ void norm2_kernel(const float2* __restrict__ x, int64_t n, double* partial) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float2 v = x[i];
+    acc += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void scale_inv_sqrt_kernel(const float2* __restrict__ x, float2* y, int64_t n, const double* sumsq) {
+  const float sc = (float)(1.0 / sqrt(sumsq[0]));
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = cscale(x[i], sc);
+}
+
+// SplitMix64 (Steele, Lea and Flood 2014) as a counter generator.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t counter, uint64_t seed) {
+  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double counter_uniform(uint64_t c, uint64_t seed) {
+  return (double)(splitmix64(c, seed) >> 11) * 0x1.0p-52 - 1.0;
+}
+
+__global__ void uniform_kernel(float2* x, int64_t n, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = make_float2((float)counter_uniform(2ull * i, seed), (float)counter_uniform(2ull * i + 1ull, seed));
+}
+
+__global__ void copy_kernel(const float2* __restrict__ x, float2* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+__global__ void zero_kernel(float2* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = make_float2(0.f, 0.f);
+}
+
+__global__ void prox_l1_kernel(const float2* __restrict__ v, float2* z, int64_t n, float tau, double* partial) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float2 a = v[i];
+    const float mag = sqrtf(a.x * a.x + a.y * a.y);
+    const float sc = mag > tau ? 1.f - tau / mag : 0.f;
+    const float2 r = make_float2(a.x * sc, a.y * sc);
+    acc += (double)sqrtf(r.x * r.x + r.y * r.y);
+    z[i] = r;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Haar pyramid on blocks of 2^LV per axis.  D = 2 (depth, x) or 3 (depth, x, y).
+// A workgroup covers NBN blocks along depth; level-l groups are indexed
+// (a, b, c) with a along depth fastest.
+// ---------------------------------------------------------------------------
+constexpr float RS2 = 0.70710678118654752440f;
+
+// analysis of one group in place: index bits (depth, x, y), 0 = low
+template <int D>
+__device__ __forceinline__ void haar_fwd_group(float2* v) {
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    const int bit = 1 << ax;
+#pragma unroll
+    for (int i = 0; i < (1 << D); ++i) {
+      if (i & bit) continue;
+      const float2 e = v[i], o = v[i | bit];
+      v[i] = make_float2((e.x + o.x) * RS2, (e.y + o.y) * RS2);
+      v[i | bit] = make_float2((e.x - o.x) * RS2, (e.y - o.y) * RS2);
+    }
+  }
+}
+template <int D>
+__device__ __forceinline__ void haar_inv_group(float2* v) {
+#pragma unroll
+  for (int ax = D - 1; ax >= 0; --ax) {
+    const int bit = 1 << ax;
+#pragma unroll
+    for (int i = 0; i < (1 << D); ++i) {
+      if (i & bit) continue;
+      const float2 lo = v[i], hi = v[i | bit];
+      v[i] = make_float2((lo.x + hi.x) * RS2, (lo.y + hi.y) * RS2);
+      v[i | bit] = make_float2((lo.x - hi.x) * RS2, (lo.y - hi.y) * RS2);
+    }
+  }
+}
+
+__device__ __forceinline__ float2 soft(float2 a, float tau, double& acc) {
+  const float mag = sqrtf(a.x * a.x + a.y * a.y);
+  const float sc = mag > tau ? 1.f - tau / mag : 0.f;
+  const float2 r = make_float2(a.x * sc, a.y * sc);
+  acc += (double)sqrtf(r.x * r.x + r.y * r.y);
+  return r;
+}
+
+template <int D, int LV, int NBN>
+__global__ void __launch_bounds__(1024) haar_kernel(ProxGeom g, const float2* __restrict__ vin, float2* zout,
+                                                    float tau, double* partial) {
+  constexpr int NV = 1 << D;
+  constexpr int BS = 1 << LV;                     // block side
+  constexpr int GA0 = NBN * BS / 2;               // level-0 groups along depth
+  constexpr int GB0 = BS / 2;                     // along x (and y)
+  constexpr int GC0 = (D == 3) ? BS / 2 : 1;
+  constexpr int NG0 = GA0 * GB0 * GC0;
+  __shared__ float2 ll[2][NG0];
+  __shared__ double sh[16];
+  const int tid = threadIdx.x;
+  const int Nz = g.Nz, Nx = g.Nx, Ny = g.Ny;
+  // tile origin
+  const int tz = Nz / (NBN * BS) + ((Nz % (NBN * BS)) ? 1 : 0);
+  const int tx = Nx / BS;
+  const int ty = (D == 3) ? Ny / BS : 1;
+  int t = blockIdx.x;
+  const int iz = t % tz; t /= tz;
+  const int ix = t % tx; t /= tx;
+  const int iy = t % ty; t /= ty;
+  const int b = t;
+  const int z0 = iz * NBN * BS, x0 = ix * BS, y0 = iy * BS;
+
+  float2 det[LV][NV];
+  double acc = 0.0;
+  // level 0: load a 2x2(x2) group
+  {
+    if (tid < NG0) {
+      const int a = tid % GA0, bb = (tid / GA0) % GB0, c = tid / (GA0 * GB0);
+      float2 v[NV];
+      const bool ok = z0 + 2 * a < Nz;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int zz = z0 + 2 * a + (i & 1);
+        const int xx = x0 + 2 * bb + ((i >> 1) & 1);
+        const int yy = (D == 3) ? y0 + 2 * c + ((i >> 2) & 1) : 0;
+        v[i] = ok ? vin[(((int64_t)b * Ny + yy) * Nx + xx) * Nz + zz] : make_float2(0.f, 0.f);
+      }
+      haar_fwd_group<D>(v);
+#pragma unroll
+      for (int i = 1; i < NV; ++i) det[0][i] = soft(v[i], tau, acc);
+      ll[0][tid] = v[0];
+    }
+  }
+  __syncthreads();
+  // analysis up the pyramid
+  int GA = GA0, GB = GB0, GC = GC0;
+#pragma unroll
+  for (int l = 1; l < LV; ++l) {
+    const int nA = GA / 2, nB = GB / 2, nC = (D == 3) ? GC / 2 : 1;
+    const int src = (l - 1) & 1, dstb = l & 1;
+    if (tid < nA * nB * nC) {
+      const int a = tid % nA, bb = (tid / nA) % nB, c = tid / (nA * nB);
+      float2 v[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int aa = 2 * a + (i & 1), b2 = 2 * bb + ((i >> 1) & 1), c2 = (D == 3) ? 2 * c + ((i >> 2) & 1) : 0;
+        v[i] = ll[src][(c2 * GB + b2) * GA + aa];
+      }
+      haar_fwd_group<D>(v);
+#pragma unroll
+      for (int i = 1; i < NV; ++i) det[l][i] = soft(v[i], tau, acc);
+      det[l][0] = v[0];   // coarsest low band kept (only used at l = LV-1)
+      ll[dstb][tid] = v[0];
+    }
+    GA = nA; GB = nB; GC = nC;
+    __syncthreads();
+  }
+  // synthesis down the pyramid (the top level keeps its low band)
+#pragma unroll
+  for (int l = LV - 1; l >= 1; --l) {
+    // groups at level l: count GA*GB*GC (current sizes); parents write into ll[(l-1)&1]
+    const int dstb = (l - 1) & 1;
+    const int srcb = l & 1;
+    if (tid < GA * GB * GC) {
+      const int a = tid % GA, bb = (tid / GA) % GB, c = tid / (GA * GB);
+      float2 v[NV];
+      v[0] = (l == LV - 1) ? det[l][0] : ll[srcb][tid];
+#pragma unroll
+      for (int i = 1; i < NV; ++i) v[i] = det[l][i];
+      haar_inv_group<D>(v);
+      const int pA = GA * 2, pB = GB * 2;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int aa = 2 * a + (i & 1), b2 = 2 * bb + ((i >> 1) & 1), c2 = (D == 3) ? 2 * c + ((i >> 2) & 1) : 0;
+        ll[dstb][(c2 * pB + b2) * pA + aa] = v[i];
+      }
+    }
+    GA *= 2; GB *= 2; if (D == 3) GC *= 2;
+    __syncthreads();
+  }
+  if (tid < NG0) {
+    const int a = tid % GA0, bb = (tid / GA0) % GB0, c = tid / (GA0 * GB0);
+    float2 v[NV];
+    v[0] = ll[0][tid];
+#pragma unroll
+    for (int i = 1; i < NV; ++i) v[i] = det[0][i];
+    haar_inv_group<D>(v);
+    if (z0 + 2 * a < Nz) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int zz = z0 + 2 * a + (i & 1);
+        const int xx = x0 + 2 * bb + ((i >> 1) & 1);
+        const int yy = (D == 3) ? y0 + 2 * c + ((i >> 2) & 1) : 0;
+        zout[(((int64_t)b * Ny + yy) * Nx + xx) * Nz + zz] = v[i];
+      }
+    }
+  }
+  const double s = block_sum(acc, sh);
+  if (tid == 0 && partial) partial[blockIdx.x] = s;
+}
+
+template <int D, int LV> struct HaarCfg;
+template <int LV> struct HaarCfg<2, LV> { static constexpr int NBN = (LV <= 3) ? (256 >> (2 * LV - 2)) / 1 * 1 : 1; };
+template <int LV> struct HaarCfg<3, LV> { static constexpr int NBN = (LV <= 2) ? 8 : (LV == 3 ? 4 : 1); };
+
+template <int D, int LV>
+int haar_threads() {
+  constexpr int BS = 1 << LV;
+  constexpr int NBN = HaarCfg<D, LV>::NBN;
+  return NBN * (BS / 2) * (BS / 2) * (D == 3 ? BS / 2 : 1);
+}
+
+template <int D, int LV>
+int haar_blocks(const ProxGeom& g) {
+  constexpr int BS = 1 << LV;
+  constexpr int NBN = HaarCfg<D, LV>::NBN;
+  const int tz = (g.Nz + NBN * BS - 1) / (NBN * BS);
+  return tz * (g.Nx / BS) * ((D == 3) ? g.Ny / BS : 1) * g.B;
+}
+
+template <int D, int LV>
+hipError_t haar_launch(const ProxGeom& g, const float2* v, float2* z, float tau, double* partial, hipStream_t s) {
+  constexpr int NBN = HaarCfg<D, LV>::NBN;
+  const int nt = haar_threads<D, LV>();
+  const int nb = haar_blocks<D, LV>(g);
+  hipLaunchKernelGGL((haar_kernel<D, LV, NBN>), dim3(nb), dim3(nt < 64 ? 64 : nt), 0, s, g, v, z, tau, partial);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// TV by FGP, one pass per inner step (any dimension).
+// strides: depth 1, x Nz, y Nx*Nz.  p, r: [nd][n] complex.
+// ---------------------------------------------------------------------------
+struct TvIdx {
+  int Nz, Nx, Ny, nd;
+  int64_t n;
+};
+
+__device__ __forceinline__ void tv_coords(const TvIdx& d, int64_t i, int& iz, int& ix, int& iy) {
+  iz = (int)(i % d.Nz);
+  const int64_t r = i / d.Nz;
+  ix = (int)(r % d.Nx);
+  iy = (int)((r / d.Nx) % d.Ny);
+}
+
+__device__ __forceinline__ float2 tv_div_at(const TvIdx& d, const float2* __restrict__ p, int64_t i, int iz,
+                                            int ix, int iy) {
+  float2 acc = make_float2(0.f, 0.f);
+  const int64_t sx = d.Nz, sy = (int64_t)d.Nx * d.Nz;
+  // depth
+  if (iz < d.Nz - 1) acc = cadd(acc, p[i]);
+  if (iz > 0) acc = csub(acc, p[i - 1]);
+  // x
+  if (ix < d.Nx - 1) acc = cadd(acc, p[d.n + i]);
+  if (ix > 0) acc = csub(acc, p[d.n + i - sx]);
+  if (d.nd == 3) {
+    if (iy < d.Ny - 1) acc = cadd(acc, p[2 * d.n + i]);
+    if (iy > 0) acc = csub(acc, p[2 * d.n + i - sy]);
+  }
+  return acc;
+}
+
+__global__ void tv_div_kernel(TvIdx d, const float2* __restrict__ v, const float2* __restrict__ r, float tau,
+                              float2* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
+    int iz, ix, iy;
+    tv_coords(d, i, iz, ix, iy);
+    const float2 dv = tv_div_at(d, r, i, iz, ix, iy);
+    const float2 a = v[i];
+    out[i] = make_float2(a.x + tau * dv.x, a.y + tau * dv.y);
+  }
+}
+
+__global__ void tv_step_kernel(TvIdx d, const float2* __restrict__ dd, float2* r, float2* p, float step, float mom) {
+  const int64_t sx = d.Nz, sy = (int64_t)d.Nx * d.Nz;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
+    int iz, ix, iy;
+    tv_coords(d, i, iz, ix, iy);
+    const float2 c = dd[i];
+    float2 gz = (iz < d.Nz - 1) ? csub(dd[i + 1], c) : make_float2(0.f, 0.f);
+    float2 gx = (ix < d.Nx - 1) ? csub(dd[i + sx], c) : make_float2(0.f, 0.f);
+    float2 gy = make_float2(0.f, 0.f);
+    if (d.nd == 3 && iy < d.Ny - 1) gy = csub(dd[i + sy], c);
+    float2 pz = r[i], px = r[d.n + i], py = make_float2(0.f, 0.f);
+    pz = make_float2(pz.x + step * gz.x, pz.y + step * gz.y);
+    px = make_float2(px.x + step * gx.x, px.y + step * gx.y);
+    float m2 = pz.x * pz.x + pz.y * pz.y + px.x * px.x + px.y * px.y;
+    if (d.nd == 3) {
+      py = r[2 * d.n + i];
+      py = make_float2(py.x + step * gy.x, py.y + step * gy.y);
+      m2 += py.x * py.x + py.y * py.y;
+    }
+    const float sc = m2 > 1.f ? 1.f / sqrtf(m2) : 1.f;
+    pz = cscale(pz, sc);
+    px = cscale(px, sc);
+    py = cscale(py, sc);
+    const float2 oz = p[i], ox = p[d.n + i];
+    r[i] = make_float2(pz.x + mom * (pz.x - oz.x), pz.y + mom * (pz.y - oz.y));
+    r[d.n + i] = make_float2(px.x + mom * (px.x - ox.x), px.y + mom * (px.y - ox.y));
+    p[i] = pz;
+    p[d.n + i] = px;
+    if (d.nd == 3) {
+      const float2 oy = p[2 * d.n + i];
+      r[2 * d.n + i] = make_float2(py.x + mom * (py.x - oy.x), py.y + mom * (py.y - oy.y));
+      p[2 * d.n + i] = py;
+    }
+  }
+}
+
+__global__ void tv_value_kernel(TvIdx d, const float2* __restrict__ z, double* partial) {
+  __shared__ double sh[16];
+  const int64_t sx = d.Nz, sy = (int64_t)d.Nx * d.Nz;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
+    int iz, ix, iy;
+    tv_coords(d, i, iz, ix, iy);
+    const float2 c = z[i];
+    float m2 = 0.f;
+    if (iz < d.Nz - 1) { const float2 g = csub(z[i + 1], c); m2 += g.x * g.x + g.y * g.y; }
+    if (ix < d.Nx - 1) { const float2 g = csub(z[i + sx], c); m2 += g.x * g.x + g.y * g.y; }
+    if (d.nd == 3 && iy < d.Ny - 1) { const float2 g = csub(z[i + sy], c); m2 += g.x * g.x + g.y * g.y; }
+    acc += (double)sqrtf(m2);
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
+}
+
+int grid_for(int64_t n, int nt) {
+  int64_t b = (n + nt - 1) / nt;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_reduce_sum(const double* partial, int n, double* out, double scale, int accumulate,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, partial, n, out, scale, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_objective(const double* rp, int nr, const double* pp, int np, double lambda, double* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(objective_kernel, dim3(1), dim3(1024), 0, s, rp, nr, pp, np, lambda, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2_partial(const float2* x, int64_t n, double* partial, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(norm2_kernel, dim3(nblocks), dim3(256), 0, s, x, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_by_inv_sqrt(const float2* x, float2* y, int64_t n, const double* sumsq, hipStream_t s) {
+  hipLaunchKernelGGL(scale_inv_sqrt_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n, sumsq);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_counter_uniform(float2* x, int64_t n, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(uniform_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, n, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float2* x, float2* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(float2* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_prox_l1(const float2* v, float2* z, int64_t n, float tau, double* partial, int nblocks,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(prox_l1_kernel, dim3(nblocks), dim3(256), 0, s, v, z, n, tau, partial);
+  return hipGetLastError();
+}
+
+int haar_partials(const ProxGeom& g, int levels) {
+  if (g.lateral_dims == 1) {
+    switch (levels) {
+      case 1: return haar_blocks<2, 1>(g);
+      case 2: return haar_blocks<2, 2>(g);
+      case 3: return haar_blocks<2, 3>(g);
+      case 4: return haar_blocks<2, 4>(g);
+      case 5: return haar_blocks<2, 5>(g);
+    }
+  } else {
+    switch (levels) {
+      case 1: return haar_blocks<3, 1>(g);
+      case 2: return haar_blocks<3, 2>(g);
+      case 3: return haar_blocks<3, 3>(g);
+      case 4: return haar_blocks<3, 4>(g);
+    }
+  }
+  return -1;
+}
+
+hipError_t launch_prox_haar(const ProxGeom& g, int levels, const float2* v, float2* z, float tau, double* partial,
+                            hipStream_t s) {
+  if (g.lateral_dims == 1) {
+    switch (levels) {
+      case 1: return haar_launch<2, 1>(g, v, z, tau, partial, s);
+      case 2: return haar_launch<2, 2>(g, v, z, tau, partial, s);
+      case 3: return haar_launch<2, 3>(g, v, z, tau, partial, s);
+      case 4: return haar_launch<2, 4>(g, v, z, tau, partial, s);
+      case 5: return haar_launch<2, 5>(g, v, z, tau, partial, s);
+    }
+  } else {
+    switch (levels) {
+      case 1: return haar_launch<3, 1>(g, v, z, tau, partial, s);
+      case 2: return haar_launch<3, 2>(g, v, z, tau, partial, s);
+      case 3: return haar_launch<3, 3>(g, v, z, tau, partial, s);
+      case 4: return haar_launch<3, 4>(g, v, z, tau, partial, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+size_t tv_work_elems(const ProxGeom& g) {
+  const int nd = g.lateral_dims + 1;
+  const int64_t n = (int64_t)g.B * g.Ny * g.Nx * g.Nz;
+  return (size_t)n * (size_t)(1 + nd);     // d, r
+}
+
+int tv_partials(const ProxGeom& g, int) {
+  const int64_t n = (int64_t)g.B * g.Ny * g.Nx * g.Nz;
+  return grid_for(n, 256);
+}
+
+// p_in (nullable = zero) -> p_out; z = v + tau div p_out; partial = TV(z).
+hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, const float2* v, float2* z,
+                          const float2* p_in, float2* p_out, float tau, double* partial, float2* work,
+                          hipStream_t s) {
+  TvIdx d;
+  d.Nz = g.Nz;
+  d.Nx = g.Nx;
+  d.Ny = (g.lateral_dims == 2) ? g.Ny : 1;
+  d.nd = g.lateral_dims + 1;
+  d.n = (int64_t)g.B * g.Ny * g.Nx * g.Nz;
+  // batch items are independent: the y index wraps per item only for volumes;
+  // for B-scans Ny = 1 and the x index never crosses a batch boundary because
+  // coordinates are taken modulo each axis length.
+  const int64_t np = d.n * d.nd;
+  float2* dd = work;
+  float2* r = work + d.n;
+  const int gb = grid_for(d.n, 256);
+  if (p_in) {
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(np, 256)), dim3(256), 0, s, p_in, p_out, np);
+  } else {
+    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(np, 256)), dim3(256), 0, s, p_out, np);
+  }
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(np, 256)), dim3(256), 0, s, p_out, r, np);
+  const float step = 1.0f / (4.0f * d.nd * tau);
+  for (int k = 0; k < n_inner; ++k) {
+    hipLaunchKernelGGL(tv_div_kernel, dim3(gb), dim3(256), 0, s, d, v, r, tau, dd);
+    hipLaunchKernelGGL(tv_step_kernel, dim3(gb), dim3(256), 0, s, d, dd, r, p_out, step, mom[k]);
+  }
+  hipLaunchKernelGGL(tv_div_kernel, dim3(gb), dim3(256), 0, s, d, v, p_out, tau, z);
+  hipLaunchKernelGGL(tv_value_kernel, dim3(gb), dim3(256), 0, s, d, z, partial);
+  return hipGetLastError();
+}

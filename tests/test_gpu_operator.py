@@ -1,0 +1,142 @@
+"""Parity of the HIP operator, adjoint and gradient with the FP64 oracle
+(relative L2 <= 1e-5), the FP32 adjoint identity, determinism and edge cases."""
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import both_geoms, flush, rand_image, rand_meas, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+OP_TOL = 1e-5
+
+CASES = {
+    # several lateral tiles, ragged last tile (n_x = 60 rows of depth 200)
+    "bscan_200x60_k300_b2": dict(n_depth=200, n_x=60, n_k=300, batch=2, disp_b=1e-6),
+    "bscan_512x64": dict(n_depth=512, n_x=64, n_k=512),
+    "bscan_odd_75x45_k90_focus": dict(n_depth=75, n_x=45, n_k=90, z_focus=20.0),
+    "bscan_j4_128x30": dict(n_depth=128, n_x=30, n_k=128, kb_width=4),
+    "bscan_j8_128x42_k256": dict(n_depth=128, n_x=42, n_k=256, kb_width=8),
+    "bscan_sigma25_96x24": dict(n_depth=96, n_x=24, n_k=100, oversamp=2.5),
+    "ascan_single_256": dict(n_depth=256, n_x=1, n_k=256),
+    "evanescent_64x32": dict(n_depth=64, n_x=32, n_k=64, k_min=0.3, k_max=0.9, dx=0.5),
+    "volume_64x16x12_b2": dict(n_depth=64, n_x=16, n_y=12, lateral_dims=2, n_k=96, batch=2),
+    "volume_128x8x8": dict(n_depth=128, n_x=8, n_y=8, lateral_dims=2, n_k=128),
+    "wide_2000x64": dict(n_depth=64, n_x=2000, n_k=64),
+}
+
+
+def _mask(rng, og, kind):
+    shp = (og.n_y if og.lateral_dims == 2 else 1, og.n_x, og.n_k)
+    if kind == "ones":
+        return None
+    return (rng.random(shp) < 0.55).astype(np.uint8)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("mask_kind", ["ones", "random"])
+def test_forward_adjoint_grad_match_oracle(name, mask_kind):
+    import paper_2108_01438_amd as P
+    flush(f"[operator] {name} mask={mask_kind}")
+    og, pg = both_geoms(**CASES[name])
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    mask = _mask(rng, og, mask_kind)
+    plan = P.Plan(pg, mask)
+    x32, x64 = rand_image(rng, O.img_shape(og))
+    r32, r64 = rand_meas(rng, O.meas_shape(og))
+    y_or = O.forward(x64, og, mask)
+    y = to_host(plan.forward(to_dev(x32)))
+    assert rel(y, y_or) <= OP_TOL
+    a_or = O.adjoint(r64, og, mask)
+    a = to_host(plan.adjoint(to_dev(r32)))
+    assert rel(a, a_or) <= OP_TOL
+    g_or, res = O.grad(x64, r64, og, mask)
+    g, hr = plan.grad(to_dev(x32), to_dev(r32))
+    assert rel(to_host(g), g_or) <= OP_TOL
+    assert abs(float(hr.item()) - 0.5 * float(np.sum(res * res))) <= 1e-5 * 0.5 * float(np.sum(res * res))
+
+
+@pytest.mark.parametrize("name", ["bscan_512x64", "volume_64x16x12_b2", "bscan_200x60_k300_b2"])
+def test_adjoint_identity_fp32(name):
+    """<Phi x, r> = Re<x, Phi^H r> with FP64 inner products of FP32 results."""
+    import paper_2108_01438_amd as P
+    flush(f"[adjoint identity] {name}")
+    og, pg = both_geoms(**CASES[name])
+    rng = np.random.default_rng(7)
+    plan = P.Plan(pg)
+    x32, _ = rand_image(rng, O.img_shape(og))
+    r32, _ = rand_meas(rng, O.meas_shape(og))
+    y = to_host(plan.forward(to_dev(x32))).astype(np.float64)
+    a = to_host(plan.adjoint(to_dev(r32))).astype(np.complex128)
+    lhs = float(np.sum(y * r32.astype(np.float64)))
+    rhs = float(np.real(np.vdot(x32.astype(np.complex128), a)))
+    scale = np.linalg.norm(y) * np.linalg.norm(r32)
+    assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+def test_determinism_bitwise():
+    import paper_2108_01438_amd as P
+    flush("[determinism] adjoint and grad repeat bitwise")
+    og, pg = both_geoms(**CASES["bscan_200x60_k300_b2"])
+    rng = np.random.default_rng(9)
+    plan = P.Plan(pg, _mask(rng, og, "random"))
+    x32, _ = rand_image(rng, O.img_shape(og))
+    r32, _ = rand_meas(rng, O.meas_shape(og))
+    xd, rd = to_dev(x32), to_dev(r32)
+    a1 = to_host(plan.adjoint(rd))
+    a2 = to_host(plan.adjoint(rd))
+    g1, h1 = plan.grad(xd, rd)
+    g1 = to_host(g1)
+    h1 = float(h1.item())
+    g2, h2 = plan.grad(xd, rd)
+    assert np.array_equal(a1.view(np.uint32), a2.view(np.uint32))
+    assert np.array_equal(g1.view(np.uint32), to_host(g2).view(np.uint32))
+    assert h1 == float(h2.item())
+
+
+def test_full_size_bscan_2048x1000():
+    """The full-size B-scan workload (2048 spectral pixels x 1000 A-scans, 50%
+    random mask): forward, adjoint and gradient against the oracle."""
+    import paper_2108_01438_amd as P
+    import synth
+    flush("[full size] bscan 2048x1000")
+    pr = synth.preset("bscan_2048x1000_tv")
+    og, pg = both_geoms(**pr["geom"])
+    rng = np.random.default_rng(1)
+    mask = synth.mask_random_exact(rng, (1, og.n_x), og.n_k, og.n_k // 2)
+    plan = P.Plan(pg, mask)
+    x32, x64 = rand_image(rng, O.img_shape(og))
+    r32, r64 = rand_meas(rng, O.meas_shape(og))
+    assert rel(to_host(plan.forward(to_dev(x32))), O.forward(x64, og, mask)) <= OP_TOL
+    assert rel(to_host(plan.adjoint(to_dev(r32))), O.adjoint(r64, og, mask)) <= OP_TOL
+
+
+def test_batch_items_are_independent():
+    import paper_2108_01438_amd as P
+    flush("[batch] items independent")
+    kw = dict(CASES["bscan_200x60_k300_b2"])
+    og, pg = both_geoms(**kw)
+    _, pg1 = both_geoms(**dict(kw, batch=1))
+    rng = np.random.default_rng(3)
+    plan = P.Plan(pg)
+    plan1 = P.Plan(pg1)
+    x32, _ = rand_image(rng, O.img_shape(og))
+    y = to_host(plan.forward(to_dev(x32)))
+    y1 = to_host(plan1.forward(to_dev(x32[1:2].copy())))
+    assert np.array_equal(y[1:2].view(np.uint32), y1.view(np.uint32))
+
+
+def test_nonfinite_inputs_stay_local():
+    """A NaN in one batch item does not leak into another."""
+    import paper_2108_01438_amd as P
+    flush("[edge] NaN isolation")
+    og, pg = both_geoms(**CASES["bscan_200x60_k300_b2"])
+    rng = np.random.default_rng(4)
+    plan = P.Plan(pg)
+    x32, _ = rand_image(rng, O.img_shape(og))
+    x32[0, 0, 3, 5] = np.nan
+    y = to_host(plan.forward(to_dev(x32)))
+    assert np.isnan(y[0]).any()
+    assert np.isfinite(y[1]).all()

@@ -1,0 +1,158 @@
+"""Parity of the HIP proximal steps, power iteration and FISTA solve with the
+FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import both_geoms, flush, rand_image, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+PROX_TOL = 1e-5
+SOLVE_TOL = 1e-4
+
+
+@pytest.mark.parametrize("kw", [dict(n_depth=64, n_x=40, n_k=64, batch=2),
+                                dict(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=32)])
+def test_prox_l1(kw):
+    import paper_2108_01438_amd as P
+    flush(f"[prox l1] {kw}")
+    og, pg = both_geoms(**kw)
+    rng = np.random.default_rng(1)
+    plan = P.Plan(pg)
+    v32, v64 = rand_image(rng, O.img_shape(og))
+    z = to_host(plan.prox("l1", 0.5, 1.2, to_dev(v32)))
+    assert rel(z, O.prox_l1(v64, 0.6)) <= 1e-6
+
+
+@pytest.mark.parametrize("kw,levels", [
+    (dict(n_depth=64, n_x=40, n_k=64, batch=2), 3),
+    (dict(n_depth=96, n_x=32, n_k=64), 1),
+    (dict(n_depth=64, n_x=32, n_k=64), 5),
+    (dict(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=32, batch=2), 3),
+    (dict(n_depth=32, n_x=16, n_y=16, lateral_dims=2, n_k=32), 4),
+    (dict(n_depth=8, n_x=4, n_y=4, lateral_dims=2, n_k=32), 2),
+])
+def test_prox_haar(kw, levels):
+    import paper_2108_01438_amd as P
+    flush(f"[prox haar] {kw} levels={levels}")
+    og, pg = both_geoms(**kw)
+    rng = np.random.default_rng(2)
+    plan = P.Plan(pg)
+    v32, v64 = rand_image(rng, O.img_shape(og))
+    axes = (3, 2, 1) if og.lateral_dims == 2 else (3, 2)
+    z = to_host(plan.prox("haar", 0.3, 1.0, to_dev(v32), haar_levels=levels))
+    assert rel(z, O.prox_haar(v64, 0.3, axes, levels)) <= PROX_TOL
+
+
+@pytest.mark.parametrize("kw", [dict(n_depth=64, n_x=40, n_k=64, batch=2),
+                                dict(n_depth=75, n_x=33, n_k=64),
+                                dict(n_depth=24, n_x=12, n_y=10, lateral_dims=2, n_k=32)])
+def test_prox_tv_cold_and_warm(kw):
+    import torch
+    import paper_2108_01438_amd as P
+    flush(f"[prox tv] {kw}")
+    og, pg = both_geoms(**kw)
+    rng = np.random.default_rng(3)
+    plan = P.Plan(pg)
+    v32, v64 = rand_image(rng, O.img_shape(og))
+    axes = (3, 2, 1) if og.lateral_dims == 2 else (3, 2)
+    tau = 0.4
+    z1 = to_host(plan.prox("tv", tau, 1.0, to_dev(v32), tv_inner=10))
+    zr1, p1 = O.prox_tv(v64, tau, axes, 10)
+    assert rel(z1, zr1) <= PROX_TOL
+    state = torch.zeros((len(axes),) + O.img_shape(og), dtype=torch.complex64, device="cuda")
+    plan.prox("tv", tau, 1.0, to_dev(v32), state=state, tv_inner=10)
+    assert rel(to_host(state), p1) <= PROX_TOL
+    z2 = to_host(plan.prox("tv", tau, 1.0, to_dev(v32), state=state, tv_inner=7))
+    zr2, _ = O.prox_tv(v64, tau, axes, 7, p0=p1)
+    assert rel(z2, zr2) <= PROX_TOL
+
+
+def test_lipschitz_matches_oracle():
+    import paper_2108_01438_amd as P
+    flush("[lipschitz] 50 power steps")
+    og, pg = both_geoms(n_depth=128, n_x=32, n_k=128, batch=2)
+    rng = np.random.default_rng(4)
+    mask = (rng.random((1, 32, 128)) < 0.5).astype(np.uint8)
+    plan = P.Plan(pg, mask)
+    L = plan.lipschitz(50, seed=11)
+    Lo = O.lipschitz(og, mask, iters=50, seed=11)
+    assert abs(L - Lo) <= 1e-5 * Lo
+
+
+def _problem(og, rng, n_scat, mask=None, noise=0.01):
+    x_true = synth.scatterers(rng, O.img_shape(og), n_scat)
+    y_clean = O.forward(x_true, og, mask)
+    y = synth.noisy(y_clean, synth.standard_normal(rng, y_clean.shape), mask, noise)
+    return x_true, y
+
+
+SOLVES = {
+    "bscan_512x64_l1_50": (dict(n_depth=512, n_x=64, n_k=512), "l1", 0.01, 50, 20),
+    "bscan_128x48_tv_30": (dict(n_depth=128, n_x=48, n_k=128), "tv", 0.005, 30, 40),
+    "bscan_128x48_haar_30": (dict(n_depth=128, n_x=48, n_k=128, batch=2), "haar", 0.01, 30, 40),
+    "volume_64x16x16_haar_20": (dict(n_depth=64, n_x=16, n_y=16, lateral_dims=2, n_k=64), "haar", 0.01, 20, 60),
+    "volume_32x16x8_tv_15": (dict(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=48), "tv", 0.005, 15, 30),
+    "volume_32x16x8_l1_25": (dict(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=48), "l1", 0.01, 25, 30),
+}
+
+
+@pytest.mark.parametrize("name", list(SOLVES))
+def test_fista_matches_oracle(name):
+    import paper_2108_01438_amd as P
+    kw, pen, lam_frac, iters, nsc = SOLVES[name]
+    flush(f"[fista] {name}")
+    og, pg = both_geoms(**kw)
+    rng = np.random.default_rng(5)
+    mask = None
+    if pen == "tv":
+        lat = (og.n_y if og.lateral_dims == 2 else 1, og.n_x)
+        mask = synth.mask_random_exact(rng, lat, og.n_k, og.n_k // 2)
+    _, y = _problem(og, rng, nsc, mask)
+    y32 = y.astype(np.float32)
+    y64 = y32.astype(np.float64)
+    lam = lam_frac * O.lambda_max(y64, og, mask)
+    delta = O.step_size(O.lipschitz(og, mask, iters=50))
+    penc = {"l1": O.PEN_L1, "tv": O.PEN_TV, "haar": O.PEN_HAAR}[pen]
+    zo, ho = O.fista(y64, og, mask, penc, lam, delta, iters, tv_inner=10, haar_levels=3)
+    plan = P.Plan(pg, mask)
+    z, info = plan.mbir_solve(to_dev(y32), pen, lam, iters, delta=delta, tv_inner=10, haar_levels=3,
+                              objective=True)
+    err = rel(to_host(z), zo)
+    flush(f"    rel err {err:.3e}")
+    assert err <= SOLVE_TOL
+    np.testing.assert_allclose(info["objective"], ho, rtol=1e-5)
+
+
+def test_fista_power_iteration_step():
+    """delta <= 0: the solver runs the power iteration itself."""
+    import paper_2108_01438_amd as P
+    flush("[fista] power-iteration step size")
+    og, pg = both_geoms(n_depth=128, n_x=32, n_k=128)
+    rng = np.random.default_rng(6)
+    _, y = _problem(og, rng, 10)
+    plan = P.Plan(pg)
+    lam = 0.01 * O.lambda_max(y, og)
+    z, info = plan.mbir_solve(to_dev(y.astype(np.float32)), "l1", lam, 5, delta=0.0, power_iters=50, seed=3)
+    Lo = O.lipschitz(og, None, iters=50, seed=3)
+    assert abs(info["lipschitz"] - Lo) <= 1e-5 * Lo
+    assert abs(info["delta"] - O.step_size(Lo)) <= 1e-5 * O.step_size(Lo)
+
+
+def test_fista_warm_start_resume():
+    """Start point x0: the solver starts from it (one iteration from x0 equals
+    the oracle's)."""
+    import paper_2108_01438_amd as P
+    flush("[fista] warm start")
+    og, pg = both_geoms(n_depth=64, n_x=32, n_k=64)
+    rng = np.random.default_rng(8)
+    _, y = _problem(og, rng, 8)
+    y32 = y.astype(np.float32)
+    x032, x064 = rand_image(rng, O.img_shape(og))
+    plan = P.Plan(pg)
+    lam, delta = 0.1, O.step_size(O.lipschitz(og, None))
+    z, _ = plan.mbir_solve(to_dev(y32), "l1", lam, 3, delta=delta, x0=to_dev(x032))
+    zo, _ = O.fista(y32.astype(np.float64), og, None, O.PEN_L1, lam, delta, 3, x0=x064)
+    assert rel(to_host(z), zo) <= SOLVE_TOL
