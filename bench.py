@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the MBIR hot path on one MI355X.
+
+Workload (the full-size B-scan): 2048 spectral pixels x 1000 A-scans, image
+2048 x 1000 complex64, 500 seeded point scatterers plus 3 layered interfaces
+with Gaussian depth falloff and speckle, 1% Gaussian noise, a random 50% of
+the spectral pixels kept per A-scan, isotropic TV with lambda = 0.005
+lambda_max and 10 inner FGP steps, Kaiser-Bessel J = 6, sigma = 2.
+
+A step is one FISTA iteration: Phi, Phi^H and the TV prox.  The timed region
+is one oct_mbir_solve of --steps iterations with every input resident in
+device memory.  Per-stage kernel durations come from HIP events on the
+stream the library launches on (torch's current stream); the dominant stage
+gives the roofline entry.  The CPU baseline times the FP64 oracle on a
+bounded sample of the same workload on the host.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Φ+Φᴴ applications/s & HBM GB/s; MBIR iters/s; serving p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+WORKLOAD = "bscan_2048x1000_tv"
+
+
+def stage_bytes(g, masked: bool) -> dict:
+    """Algorithmic HBM bytes of each stage for one FISTA iteration (B-scan):
+    every stage reads its inputs and writes its outputs once."""
+    N = g.batch * g.n_y * g.n_x * g.n_depth
+    M = g.batch * g.n_y * g.n_x * g.n_k
+    mbits = M / 8.0 if masked else 0.0
+    return {
+        "lat_fwd": 24.0 * N,                 # z, z_prev in; X1 out
+        "nufft_fwd": 8.0 * N + 8.0 * M,      # X1 in; W out
+        "normal": 20.0 * M + mbits,          # W, y, mask in; R out
+        "nufft_adj": 8.0 * M + 8.0 * N,      # R in; X1 out
+        "lat_update": 32.0 * N,              # X1, z, z_prev in; v out
+        "prox": 48.0 * N,                    # v, dual in; z, dual out
+    }
+
+
+def grad_bytes(g, masked: bool) -> float:
+    """Phi + Phi^H (oct_grad): x in, lateral FFT, NUFFT, residual seam,
+    adjoint NUFFT, inverse lateral FFT, g out."""
+    N = g.batch * g.n_y * g.n_x * g.n_depth
+    M = g.batch * g.n_y * g.n_x * g.n_k
+    return 48.0 * N + 36.0 * M + (M / 8.0 if masked else 0.0)
+
+
+STAGE_KERNEL = {
+    "lat_fwd": "lat_kernel<0, false>",
+    "nufft_fwd": "nufft_fwd_kernel<6, false>",
+    "normal": "lat_kernel<3, false>",
+    "nufft_adj": "nufft_adj_kernel<6, false>",
+    "lat_update": "lat_kernel<4, false>",
+    "prox": "tv2d_tile_kernel",
+}
+STAGE_SOURCE = {
+    "lat_fwd": "oct_lateral.hip", "normal": "oct_lateral.hip", "lat_update": "oct_lateral.hip",
+    "nufft_fwd": "oct_nufft.hip", "nufft_adj": "oct_nufft.hip", "prox": "oct_prox.hip",
+}
+
+
+def source_digest(stage: str) -> str:
+    h = hashlib.sha256()
+    for f in (STAGE_SOURCE[stage], "oct_fft.h", "oct_common.h"):
+        with open(os.path.join(ROOT, "paper_2108_01438_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(stage: str, launches_per_run: int = 1):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{WORKLOAD}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    s = rec.get("stages", {}).get(stage)
+    if not s or s.get("source_digest") != source_digest(stage):
+        return None
+    return float(s["hbm_bytes_per_launch"])
+
+
+def make_workload(P, synth, torch):
+    import numpy as np
+    pr = synth.preset(WORKLOAD)
+    geom = P.Geometry.from_dict(pr["geom"])
+    rng = np.random.default_rng(1)
+    x_true = synth.scatterers(rng, geom.img_shape, pr["scatterers"])
+    x_true[0, 0] += synth.layers(rng, geom.n_depth, geom.n_x, pr["layers"])
+    mask = synth.mask_random_exact(rng, (1, geom.n_x), geom.n_k, geom.n_k // 2)
+    noise = synth.standard_normal(rng, geom.meas_shape)
+    return geom, pr, x_true, mask, noise
+
+
+def cpu_baseline(pr, x_true, mask, noise, iters: int) -> dict:
+    """The FP64 oracle, as it stands, on `iters` FISTA iterations of the same
+    workload (its own data synthesis, lambda and a short power iteration)."""
+    import numpy as np
+    import oracle as O
+    import synth
+    g = O.Geometry(**pr["geom"])
+    y = synth.noisy(O.forward(x_true, g, mask), noise, mask, pr["noise"])
+    lam = pr["lam"] * O.lambda_max(y, g, mask)
+    delta = O.step_size(O.lipschitz(g, mask, iters=2))
+    t0 = time.perf_counter()
+    O.fista(y, g, mask, O.PEN_TV, lam, delta, iters, tv_inner=10)
+    dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "MBIR iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} FISTA iterations (Phi, Phi^H, 10-step TV prox) of the 2048x1000 "
+                      f"B-scan workload, NumPy/SciPy FP64 single-threaded; {dt:.1f} s on "
+                      f"{os.cpu_count()} visible host cores"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--stage-reps", type=int, default=50)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import paper_2108_01438_amd as P
+    import synth
+
+    torch.cuda.set_device(0)
+    geom, pr, x_true, mask, noise = make_workload(P, synth, torch)
+    plan = P.Plan(geom, mask)
+    mask_d = torch.from_numpy(mask.astype(np.float32)[None]).cuda()
+    xt = torch.from_numpy(x_true.astype(np.complex64)).cuda()
+    y_clean = plan.forward(xt)
+    sigma = pr["noise"] * float(y_clean.abs().max().item())
+    y = ((y_clean + sigma * torch.from_numpy(noise.astype(np.float32)).cuda()) * mask_d).contiguous()
+    lam = pr["lam"] * float(plan.adjoint(y).abs().max().item())
+    L = plan.lipschitz(50, seed=0)
+    delta = 1.0 / (1.05 * L)
+    print(f"[bench] workload ready: lambda={lam:.4g} L={L:.4g}", file=sys.stderr, flush=True)
+
+    # ---- whole-job throughput: one solve of `steps` iterations
+    plan.mbir_solve(y, "tv", lam, max(1, args.warmup), delta=delta, tv_inner=10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    z, _ = plan.mbir_solve(y, "tv", lam, args.steps, delta=delta, tv_inner=10)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_solve = e0.elapsed_time(e1)
+    ms_per_step = max(ms_solve, wall * 1e3) / args.steps
+    print(f"[bench] solve: {ms_per_step:.4f} ms/iteration", file=sys.stderr, flush=True)
+
+    # ---- per-stage kernel durations (HIP events on the launch stream)
+    sb = stage_bytes(geom, True)
+    stages = {}
+    for st in P.Plan.STAGES:
+        for _ in range(3):
+            plan.run_stage(st, "tv", y)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(args.stage_reps):
+            plan.run_stage(st, "tv", y)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.stage_reps
+        stages[st] = {"ms": ms, "bytes": sb[st], "GBps": sb[st] / (ms * 1e-3) / 1e9}
+    # ---- Phi + Phi^H
+    gbuf = torch.empty(geom.img_shape, dtype=torch.complex64, device="cuda")
+    rbuf = torch.empty((), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        plan.grad(z, y, gbuf, rbuf)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(args.stage_reps):
+        plan.grad(z, y, gbuf, rbuf)
+    b.record()
+    torch.cuda.synchronize()
+    ms_grad = a.elapsed_time(b) / args.stage_reps
+    gb = grad_bytes(geom, True)
+
+    dom = max(stages, key=lambda k: stages[k]["ms"])
+    ach = stages[dom]["GBps"]
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom),
+            "kernel": STAGE_KERNEL[dom], "stage": dom,
+            "algorithmic_bytes_per_launch": sb[dom], "ms_per_launch": round(stages[dom]["ms"], 5)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms_per_step, 2),
+        "unit": "MBIR iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (complex64; FP64 reductions and momenta)",
+        "data": "synthetic (seeded scatterers + layered speckle, 1% noise, 50% random mask)",
+        "config": {"workload": "B-scan 2048 spectral px x 1000 A-scans, image 2048x1000 complex64, "
+                               "isotropic TV lambda=0.005 lambda_max, 10 FGP steps, KB J=6 sigma=2, "
+                               "one FISTA iteration per step",
+                   "n_depth": geom.n_depth, "n_x": geom.n_x, "n_k": geom.n_k, "penalty": "tv",
+                   "parallelism": "1 GPU"},
+        "phi_phih_per_s": round(1000.0 / ms_grad, 1),
+        "phi_phih_ms": round(ms_grad, 5),
+        "phi_phih_GBps": round(gb / (ms_grad * 1e-3) / 1e9, 1),
+        "stages": {k: {"ms": round(v["ms"], 5), "GBps": round(v["GBps"], 1)} for k, v in stages.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(pr, x_true, mask, noise, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -161,6 +161,24 @@ typedef struct {
 oct_status oct_mbir_solve(oct_plan_t plan, const float* y, const oct_solve_params* params,
                           void* x_out, oct_solve_report* report, void* stream);
 
+/* Stages of one FISTA iteration, for per-kernel timing and profiling. */
+typedef enum {
+  OCT_STAGE_LAT_FWD = 0,    /* X1 = F_lat(z + mu (z - z_prev))          (eq. (4), (15)) */
+  OCT_STAGE_NUFFT_FWD = 1,  /* W = H . KB-NUFFT_q(X1)                   (eq. (5)-(6))   */
+  OCT_STAGE_NORMAL = 2,     /* W = F_lat(s.(Re F_lat^-1 W - y)) / N_lat (eq. (2), (7))  */
+  OCT_STAGE_NUFFT_ADJ = 3,  /* X1 = NUFFT_q^H(conj(H) . W)              (eq. (3))       */
+  OCT_STAGE_LAT_UPDATE = 4, /* v = x - delta F_lat^H X1                 (eq. (15))      */
+  OCT_STAGE_PROX = 5        /* z = prox(v) for the given penalty        (eq. (16))      */
+} oct_stage;
+
+/* Run one stage of a FISTA iteration on the plan's own workspace and solver
+ * buffers (their contents are whatever earlier calls left, zero at first
+ * use), with the kernels and launch shapes oct_mbir_solve uses.  For timing
+ * and profiling only; y is read by OCT_STAGE_NORMAL (device measurement,
+ * may be NULL for the others); penalty selects the prox (TV with 10 inner
+ * steps, Haar with 3 levels).  Asynchronous. */
+oct_status oct_run_stage(oct_plan_t plan, int32_t stage, int32_t penalty, const float* y, void* stream);
+
 /* Message for the last non-OK status returned to the calling thread. */
 const char* oct_last_error(void);
 

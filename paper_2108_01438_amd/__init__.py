@@ -51,8 +51,11 @@ class _CSolveReport(ctypes.Structure):
 
 
 def _load():
+    # torch brings its own HIP runtime (soname libamdhip64.so.7); loading it
+    # first makes liboct bind to that same runtime instead of a second copy.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2108_01438_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2108_01438_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     sig = {
@@ -67,6 +70,7 @@ def _load():
         "oct_lipschitz": ([P, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
         "oct_mbir_solve": ([P, P, ctypes.POINTER(_CSolveParams), P, ctypes.POINTER(_CSolveReport), P],
                            ctypes.c_int),
+        "oct_run_stage": ([P, ctypes.c_int32, ctypes.c_int32, P, P], ctypes.c_int),
         "oct_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -230,6 +234,16 @@ class Plan:
                              _dev(v, torch.complex64, g.img_shape, "v"), _dev(z, torch.complex64, g.img_shape, "z"),
                              sp, ctypes.c_void_p(_stream_ptr(stream))))
         return z
+
+    STAGES = ("lat_fwd", "nufft_fwd", "normal", "nufft_adj", "lat_update", "prox")
+
+    def run_stage(self, stage, penalty="tv", y=None, stream=None):
+        """One stage of a FISTA iteration on the plan's workspace (timing only)."""
+        import torch
+        st = self.STAGES.index(stage) if isinstance(stage, str) else int(stage)
+        pen = PENALTIES[penalty] if isinstance(penalty, str) else int(penalty)
+        yp = None if y is None else _dev(y, torch.float32, self.geom.meas_shape, "y")
+        _check(_lib.oct_run_stage(self._h, st, pen, yp, ctypes.c_void_p(_stream_ptr(stream))))
 
     def lipschitz(self, iters: int = 50, seed: int = 0, stream=None) -> float:
         out = ctypes.c_double()

@@ -1,6 +1,7 @@
 """Build liboct.so (HIP for gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2108_01438_amd.build   (or build_library() from Python)
+Usage: python paper_2108_01438_amd/build.py   (run as a script: importing the
+package would load the previously built library)
 """
 from __future__ import annotations
 

@@ -411,6 +411,8 @@ int partial_need(oct_plan* p) {
   need = std::max(need, lat_blocks(b));
   ProxGeom pg{(int)p->B, (int)p->Ny, (int)p->Nx, (int)p->Nz, p->lat_dims};
   for (int lv = 1; lv <= 5; ++lv) need = std::max(need, haar_partials(pg, lv));
+  need = std::max(need, tv_partials(pg, TV_MAX_TILED_INNER));
+  need = std::max(need, tv_partials(pg, TV_MAX_TILED_INNER + 1));
   return need;
 }
 
@@ -418,6 +420,8 @@ oct_status ensure_solver_state(oct_plan* p, int pen, int iters) {
   if (!p->za) {
     OCTCHK(dev_alloc(p, &p->za, p->n_img()));
     OCTCHK(dev_alloc(p, &p->zb, p->n_img()));
+    HIPCHK(hipMemset(p->za, 0, sizeof(float2) * p->n_img()));
+    HIPCHK(hipMemset(p->zb, 0, sizeof(float2) * p->n_img()));
   }
   if (pen == OCT_PEN_TV && !p->p0) {
     const int nd = p->lat_dims + 1;
@@ -425,6 +429,8 @@ oct_status ensure_solver_state(oct_plan* p, int pen, int iters) {
     OCTCHK(dev_alloc(p, &p->p1, (size_t)p->n_img() * nd));
     ProxGeom pg{(int)p->B, (int)p->Ny, (int)p->Nx, (int)p->Nz, p->lat_dims};
     OCTCHK(dev_alloc(p, &p->tvwork, tv_work_elems(pg)));
+    HIPCHK(hipMemset(p->p0, 0, sizeof(float2) * p->n_img() * nd));
+    HIPCHK(hipMemset(p->p1, 0, sizeof(float2) * p->n_img() * nd));
   }
   if (iters > p->hist_cap) {
     OCTCHK(dev_alloc(p, &p->hist, (size_t)iters));
@@ -596,6 +602,9 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   }
   if ((st = dev_alloc(p, &p->X1, p->n_img())) != OCT_OK) return cleanup(st);
   if ((st = dev_alloc(p, &p->W, p->n_meas())) != OCT_OK) return cleanup(st);
+  if (hipMemset(p->X1, 0, sizeof(float2) * p->n_img()) != hipSuccess ||
+      hipMemset(p->W, 0, sizeof(float2) * p->n_meas()) != hipSuccess)
+    return cleanup(fail(OCT_E_DEVICE, "hipMemset of the workspace failed"));
   p->partial_cap = partial_need(p);
   if ((st = dev_alloc(p, &p->partial, (size_t)p->partial_cap * 2)) != OCT_OK) return cleanup(st);
   if ((st = dev_alloc(p, &p->dscal, 16)) != OCT_OK) return cleanup(st);
@@ -808,6 +817,54 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
     }
   }
   return OCT_OK;
+}
+
+oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* y, void* stream) {
+  if (!p) return fail(OCT_E_INVALID, "null plan");
+  if (pen < 0 || pen > 2) return fail(OCT_E_INVALID, "unknown penalty");
+  hipStream_t s = S(stream);
+  OCTCHK(ensure_solver_state(p, pen, 1));
+  switch (stage) {
+    case OCT_STAGE_LAT_FWD:
+      return run_lat_forward(p, nullptr, p->za, p->zb, 0.5f, s);
+    case OCT_STAGE_NUFFT_FWD:
+      HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+      return OCT_OK;
+    case OCT_STAGE_NORMAL: {
+      if (!y) return fail(OCT_E_INVALID, "OCT_STAGE_NORMAL needs y");
+      int np = 0;
+      return run_normal(p, y, p->partial, &np, s);
+    }
+    case OCT_STAGE_NUFFT_ADJ:
+      HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+      return OCT_OK;
+    case OCT_STAGE_LAT_UPDATE: {
+      if (p->lat_dims == 2) {
+        LatArgs b = lat_args(p, lines_y(p, (int)p->Nz), true);
+        b.src = p->X1;
+        b.dst = p->X1;
+        b.inverse = 1;
+        HIPCHK(launch_lateral(LAT_FFT, b, s));
+      }
+      LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
+      a.src = p->X1;
+      a.dst = p->X1;
+      a.inverse = 1;
+      a.z = p->za;
+      a.zo = p->zb;
+      a.mu = 0.5f;
+      a.delta = 1e-3f;
+      HIPCHK(launch_lateral(LAT_UPDATE, a, s));
+      return OCT_OK;
+    }
+    case OCT_STAGE_PROX: {
+      int np = 0;
+      return run_prox(p, pen, 1e-3f, 10, 3, p->X1, p->zb, pen == OCT_PEN_TV ? p->p0 : nullptr,
+                      pen == OCT_PEN_TV ? p->p1 : nullptr, &np, s);
+    }
+    default:
+      return fail(OCT_E_INVALID, "unknown stage");
+  }
 }
 
 }  // extern "C"

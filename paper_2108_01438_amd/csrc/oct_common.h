@@ -116,3 +116,17 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
                           float2* z, const float2* p_in, float2* p_out, float tau,
                           double* partial, float2* work, hipStream_t s);
 size_t tv_work_elems(const ProxGeom& g);
+
+// 2-D TV tile kernel arguments (inner steps up to TV_MAX_TILED_INNER).
+#define TV_MAX_TILED_INNER 27
+struct Tv2dArgs {
+  int Nz, Nx, H, n_inner, CZ, CL, ntz, ntl;
+  int64_t n_total;          // image elements (stride between dual components)
+  float tau, step;
+  float mom[TV_MAX_TILED_INNER + 1];
+  const float2* v;
+  float2* z;
+  const float2* pin;        // nullable: cold start
+  float2* pout;
+  double* partial;
+};

@@ -187,18 +187,36 @@ __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride,
 }
 
 // Full transform of `nrows` rows in LDS; all threads of the block participate.
-template <int MAXB, bool INV>
+// R7 selects the code path with radix-7 stages (compiled separately: its
+// register footprint is larger, so it runs one butterfly per thread).
+template <bool R7>
+struct FftCfg {
+  static constexpr int MAXB = R7 ? 1 : 2;
+};
+
+template <bool R7, bool INV>
 __device__ __forceinline__ void fft_rows(float2* buf, int nrows, int rowstride, const FftDesc& d,
                                          const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr int MB = FftCfg<R7>::MAXB;
   for (int s = 0; s < d.nstages; ++s) {
     const int Ns = d.ns[s];
     switch (d.radix[s]) {
-      case 8: fft_stage<8, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
-      case 4: fft_stage<4, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
-      case 2: fft_stage<2, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
-      case 5: fft_stage<5, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
-      case 3: fft_stage<3, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
-      default: fft_stage<7, MAXB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 8: fft_stage<8, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 4: fft_stage<4, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 2: fft_stage<2, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 5: fft_stage<5, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 3: fft_stage<3, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      default:
+        if (R7) fft_stage<7, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr);
+        break;
     }
   }
 }
+
+// butterflies per thread the kernels may use for a transform of this shape
+inline int fft_maxb(const FftDesc& d) {
+  for (int s = 0; s < d.nstages; ++s)
+    if (d.radix[s] == 7) return 1;
+  return 2;
+}
+inline bool fft_has7(const FftDesc& d) { return fft_maxb(d) == 1; }

@@ -34,7 +34,7 @@ __device__ double block_sum_d(double v, double* sh) {
   return s;
 }
 
-template <int MODE>
+template <int MODE, bool R7>
 __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   extern __shared__ float2 lds[];
   __shared__ double red[16];
@@ -77,8 +77,8 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   }
   __syncthreads();
 
-  if (a.inverse) fft_rows<4, true>(lds, T, rs, a.fd, a.tw, tid, nthr);
-  else fft_rows<4, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
+  if (a.inverse) fft_rows<R7, true>(lds, T, rs, a.fd, a.tw, tid, nthr);
+  else fft_rows<R7, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
 
   if (MODE == LAT_FFT || MODE == LAT_ADJ_MEAS) {
     for (int idx = tid; idx < n; idx += nthr) {
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       lds[t * rs + l] = make_float2(r, 0.f);
     }
     __syncthreads();
-    fft_rows<4, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
+    fft_rows<R7, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx / T, t = idx - l * T;
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       lds[t * rs + l] = xn;
     }
     __syncthreads();
-    fft_rows<4, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
+    fft_rows<R7, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx / T, t = idx - l * T;
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = lds[t * rs + l];
@@ -169,16 +169,17 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
 }  // namespace
 
 // Rows per tile and threads per block: the tile (T rows of L complex) stays
-// within 64 KB of LDS and every FFT stage fits 4 butterflies per thread.
+// within 64 KB of LDS and every FFT stage fits 2 butterflies per thread.
 int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* rowstride) {
   const int rs = (lg.L % 2 == 0) ? lg.L + 1 : lg.L;  // odd stride spreads LDS banks
+  const int mb = fft_maxb(fd);
   int T = 32;
   while (T > 1 && (int64_t)T * rs * 8 > 64512) T >>= 1;
   while (T > 1 && T > lg.rows) T >>= 1;
   for (; T >= 1; T >>= 1) {
     const int64_t bf = (int64_t)T * lg.L / fd.min_radix;
     for (int nt = 256; nt <= 1024; nt <<= 1) {
-      if (bf <= 4 * nt && (int64_t)T * rs * 8 <= 64512) {
+      if (bf <= mb * nt && (int64_t)T * rs * 8 <= 64512) {
         *nthr = nt;
         *rowstride = rs;
         return T;
@@ -188,22 +189,28 @@ int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* row
   return 0;
 }
 
-hipError_t launch_lateral(LatMode mode, const LatArgs& a0, hipStream_t s) {
-  LatArgs a = a0;
+template <bool R7>
+hipError_t launch_lateral_t(LatMode mode, const LatArgs& a, hipStream_t s) {
   const size_t lds = (size_t)a.T * a.rowstride * sizeof(float2);
   const int grid = a.lg.n_lines * a.n_tiles;
+  const int mb = FftCfg<R7>::MAXB;
   int nthr = 256;
   {
     const int64_t bf = (int64_t)a.T * a.lg.L / a.fd.min_radix;
-    while (nthr < 1024 && bf > 4 * nthr) nthr <<= 1;
+    while (nthr < 1024 && bf > (int64_t)mb * nthr) nthr <<= 1;
+    if (bf > (int64_t)mb * nthr) return hipErrorInvalidConfiguration;
   }
   switch (mode) {
-    case LAT_FFT: hipLaunchKernelGGL(lat_kernel<LAT_FFT>, dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_FWD_MEAS: hipLaunchKernelGGL(lat_kernel<LAT_FWD_MEAS>, dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_ADJ_MEAS: hipLaunchKernelGGL(lat_kernel<LAT_ADJ_MEAS>, dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_NORMAL: hipLaunchKernelGGL(lat_kernel<LAT_NORMAL>, dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_UPDATE: hipLaunchKernelGGL(lat_kernel<LAT_UPDATE>, dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_UPDATE_L1: hipLaunchKernelGGL(lat_kernel<LAT_UPDATE_L1>, dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_FFT: hipLaunchKernelGGL((lat_kernel<LAT_FFT, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_FWD_MEAS: hipLaunchKernelGGL((lat_kernel<LAT_FWD_MEAS, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_ADJ_MEAS: hipLaunchKernelGGL((lat_kernel<LAT_ADJ_MEAS, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_NORMAL: hipLaunchKernelGGL((lat_kernel<LAT_NORMAL, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_UPDATE: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_UPDATE_L1: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE_L1, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_lateral(LatMode mode, const LatArgs& a, hipStream_t s) {
+  return fft_has7(a.fd) ? launch_lateral_t<true>(mode, a, s) : launch_lateral_t<false>(mode, a, s);
 }

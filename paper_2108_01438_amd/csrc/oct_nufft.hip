@@ -40,7 +40,7 @@ __device__ __forceinline__ float2 filter_h(const NufftArgs& a, int m, float bq, 
   return h;
 }
 
-template <int J>
+template <int J, bool R7>
 __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const float2* __restrict__ X1,
                                                          float2* __restrict__ W) {
   extern __shared__ float2 grid[];
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
     grid[idx] = cscale(src[n], a.deap[n]);
   }
   __syncthreads();
-  fft_rows<4, false>(grid, 1, K, a.fK, a.twK, tid, nthr);
+  fft_rows<R7, false>(grid, 1, K, a.fK, a.twK, tid, nthr);
 
   const double q2 = a.q2[lat];
   const float bq = a.beam[lat];
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
 
 constexpr int EVANESCENT = -(1 << 29);
 
-template <int J>
+template <int J, bool R7>
 __global__ void __launch_bounds__(1024) nufft_adj_kernel(NufftArgs a, const float2* __restrict__ Rh,
                                                          float2* __restrict__ X) {
   extern __shared__ float4 smem4[];
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(1024) nufft_adj_kernel(NufftArgs a, const floa
     __syncthreads();
   }
 
-  fft_rows<4, true>(grid, 1, K, a.fK, a.twK, tid, nthr);
+  fft_rows<R7, true>(grid, 1, K, a.fK, a.twK, tid, nthr);
   float2* __restrict__ dst = X + (int64_t)col * Nz;
   for (int n = tid; n < Nz; n += nthr) {
     int idx = n - nc;
@@ -182,8 +182,9 @@ __global__ void __launch_bounds__(1024) nufft_adj_kernel(NufftArgs a, const floa
 
 int nufft_threads(const NufftArgs& a) {
   const int bf = a.K / a.fK.min_radix;
+  const int mb = fft_maxb(a.fK);
   int nt = 256;
-  while (nt < 1024 && bf > 4 * nt) nt <<= 1;
+  while (nt < 1024 && bf > mb * nt) nt <<= 1;
   return nt;
 }
 
@@ -193,41 +194,42 @@ size_t nufft_adj_lds_bytes(const NufftArgs& a) {
   return (size_t)a.K * sizeof(float2) + (size_t)a.Mk * (sizeof(float2) + sizeof(int) + sizeof(float));
 }
 
-hipError_t launch_nufft_fwd(const NufftArgs& a, const float2* X1, float2* W, hipStream_t s) {
+template <int J, bool R7>
+hipError_t nufft_fwd_t(const NufftArgs& a, const float2* X1, float2* W, hipStream_t s) {
   const size_t lds = (size_t)a.K * sizeof(float2);
-  const int nt = nufft_threads(a);
-  switch (a.J) {
-    case 4: hipLaunchKernelGGL(nufft_fwd_kernel<4>, dim3(a.n_cols), dim3(nt), lds, s, a, X1, W); break;
-    case 6: hipLaunchKernelGGL(nufft_fwd_kernel<6>, dim3(a.n_cols), dim3(nt), lds, s, a, X1, W); break;
-    default: hipLaunchKernelGGL(nufft_fwd_kernel<8>, dim3(a.n_cols), dim3(nt), lds, s, a, X1, W); break;
-  }
+  hipLaunchKernelGGL((nufft_fwd_kernel<J, R7>), dim3(a.n_cols), dim3(nufft_threads(a)), lds, s, a, X1, W);
   return hipGetLastError();
 }
 
-template <int J>
-void allow_big_lds() {
-  static bool done = false;
-  if (!done) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_adj_kernel<J>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-    done = true;
+hipError_t launch_nufft_fwd(const NufftArgs& a, const float2* X1, float2* W, hipStream_t s) {
+  const bool r7 = fft_has7(a.fK);
+  switch (a.J) {
+    case 4: return r7 ? nufft_fwd_t<4, true>(a, X1, W, s) : nufft_fwd_t<4, false>(a, X1, W, s);
+    case 6: return r7 ? nufft_fwd_t<6, true>(a, X1, W, s) : nufft_fwd_t<6, false>(a, X1, W, s);
+    default: return r7 ? nufft_fwd_t<8, true>(a, X1, W, s) : nufft_fwd_t<8, false>(a, X1, W, s);
   }
+}
+
+template <int J, bool R7>
+hipError_t nufft_adj_t(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s) {
+  const size_t lds = nufft_adj_lds_bytes(a);
+  if (lds > 64 * 1024 - 1024) {
+    static bool done = false;
+    if (!done) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_adj_kernel<J, R7>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+      done = true;
+    }
+  }
+  hipLaunchKernelGGL((nufft_adj_kernel<J, R7>), dim3(a.n_cols), dim3(nufft_threads(a)), lds, s, a, Rh, X);
+  return hipGetLastError();
 }
 
 hipError_t launch_nufft_adj(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s) {
-  const size_t lds = nufft_adj_lds_bytes(a);
-  const int nt = nufft_threads(a);
-  if (lds > 64 * 1024 - 1024) {
-    switch (a.J) {
-      case 4: allow_big_lds<4>(); break;
-      case 6: allow_big_lds<6>(); break;
-      default: allow_big_lds<8>(); break;
-    }
-  }
+  const bool r7 = fft_has7(a.fK);
   switch (a.J) {
-    case 4: hipLaunchKernelGGL(nufft_adj_kernel<4>, dim3(a.n_cols), dim3(nt), lds, s, a, Rh, X); break;
-    case 6: hipLaunchKernelGGL(nufft_adj_kernel<6>, dim3(a.n_cols), dim3(nt), lds, s, a, Rh, X); break;
-    default: hipLaunchKernelGGL(nufft_adj_kernel<8>, dim3(a.n_cols), dim3(nt), lds, s, a, Rh, X); break;
+    case 4: return r7 ? nufft_adj_t<4, true>(a, Rh, X, s) : nufft_adj_t<4, false>(a, Rh, X, s);
+    case 6: return r7 ? nufft_adj_t<6, true>(a, Rh, X, s) : nufft_adj_t<6, false>(a, Rh, X, s);
+    default: return r7 ? nufft_adj_t<8, true>(a, Rh, X, s) : nufft_adj_t<8, false>(a, Rh, X, s);
   }
-  return hipGetLastError();
 }

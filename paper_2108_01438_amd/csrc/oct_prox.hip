@@ -393,6 +393,143 @@ __global__ void tv_value_kernel(TvIdx d, const float2* __restrict__ z, double* p
   if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
 }
 
+// ---------------------------------------------------------------------------
+// 2-D TV by FGP with every inner step of a tile on chip.  Lane = depth sample
+// (64 per wave, coalesced), each thread owns a strip of TV_S lateral samples
+// in registers, 16 waves side by side laterally: a 64 x (16 TV_S) loaded
+// tile.  Depth neighbours move by lane shuffles, lateral neighbours inside a
+// strip are registers and across strips go through LDS.  One inner step
+// reaches one sample further in every direction, so with a halo of
+// n_inner + 1 the dual is exact on the core grown by one sample, which is
+// what z = v + tau div p and TV(z) on the core need.
+// ---------------------------------------------------------------------------
+constexpr int TV_S = 6;
+constexpr int TV_WAVES = 16;
+
+__global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
+  __shared__ float2 xr[TV_WAVES][64];
+  __shared__ float2 xd[TV_WAVES][64];
+  __shared__ double sh[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int bid = blockIdx.x;
+  const int G = gridDim.x;
+  if ((G & 7) == 0) {  // neighbouring tiles (shared halos) on the same XCD
+    const int per = G >> 3;
+    bid = (bid & 7) * per + (bid >> 3);
+  }
+  const int tz = bid % a.ntz;
+  const int tl = (bid / a.ntz) % a.ntl;
+  const int b = bid / (a.ntz * a.ntl);
+  const int Nz = a.Nz, Nx = a.Nx, H = a.H;
+  const int cz0 = tz * a.CZ, cl0 = tl * a.CL;
+  const int n = cz0 - H + lane;
+  const int l0 = cl0 - H + w * TV_S;
+  const bool nin = (n >= 0 && n < Nz);
+  const int64_t ib = (int64_t)b * Nx * Nz;
+  const int64_t N = a.n_total;
+  const bool zfwd = n < Nz - 1, zbwd = n > 0;
+
+  float2 v[TV_S], pz[TV_S], pl[TV_S], rz[TV_S], rl[TV_S];
+#pragma unroll
+  for (int s = 0; s < TV_S; ++s) {
+    const int l = l0 + s;
+    const bool in = nin && l >= 0 && l < Nx;
+    const int64_t idx = ib + (int64_t)l * Nz + n;
+    v[s] = in ? a.v[idx] : make_float2(0.f, 0.f);
+    pz[s] = (in && a.pin) ? a.pin[idx] : make_float2(0.f, 0.f);
+    pl[s] = (in && a.pin) ? a.pin[N + idx] : make_float2(0.f, 0.f);
+    rz[s] = pz[s];
+    rl[s] = pl[s];
+  }
+  const float tau = a.tau, step = a.step;
+  for (int k = 0; k < a.n_inner; ++k) {
+    const float mom = a.mom[k];
+    xr[w][lane] = rl[TV_S - 1];
+    __syncthreads();
+    float2 d[TV_S];
+#pragma unroll
+    for (int s = 0; s < TV_S; ++s) {
+      const int l = l0 + s;
+      float2 up;
+      up.x = __shfl_up(rz[s].x, 1);
+      up.y = __shfl_up(rz[s].y, 1);
+      const float2 lp = (s > 0) ? rl[s - 1] : (w > 0 ? xr[w - 1][lane] : make_float2(0.f, 0.f));
+      float dx = 0.f, dy = 0.f;
+      if (zfwd) { dx += rz[s].x; dy += rz[s].y; }
+      if (zbwd) { dx -= up.x; dy -= up.y; }
+      if (l < Nx - 1) { dx += rl[s].x; dy += rl[s].y; }
+      if (l > 0) { dx -= lp.x; dy -= lp.y; }
+      d[s] = make_float2(v[s].x + tau * dx, v[s].y + tau * dy);
+    }
+    xd[w][lane] = d[0];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < TV_S; ++s) {
+      const int l = l0 + s;
+      float2 dn;
+      dn.x = __shfl_down(d[s].x, 1);
+      dn.y = __shfl_down(d[s].y, 1);
+      const float2 dl = (s < TV_S - 1) ? d[s + 1] : (w < TV_WAVES - 1 ? xd[w + 1][lane] : make_float2(0.f, 0.f));
+      const float2 gz = zfwd ? make_float2(dn.x - d[s].x, dn.y - d[s].y) : make_float2(0.f, 0.f);
+      const float2 gl = (l < Nx - 1) ? make_float2(dl.x - d[s].x, dl.y - d[s].y) : make_float2(0.f, 0.f);
+      float2 qz = make_float2(rz[s].x + step * gz.x, rz[s].y + step * gz.y);
+      float2 ql = make_float2(rl[s].x + step * gl.x, rl[s].y + step * gl.y);
+      const float m2 = qz.x * qz.x + qz.y * qz.y + ql.x * ql.x + ql.y * ql.y;
+      if (m2 > 1.f) {
+        const float sc = 1.f / sqrtf(m2);
+        qz = cscale(qz, sc);
+        ql = cscale(ql, sc);
+      }
+      rz[s] = make_float2(qz.x + mom * (qz.x - pz[s].x), qz.y + mom * (qz.y - pz[s].y));
+      rl[s] = make_float2(ql.x + mom * (ql.x - pl[s].x), ql.y + mom * (ql.y - pl[s].y));
+      pz[s] = qz;
+      pl[s] = ql;
+    }
+  }
+  // z = v + tau div p
+  xr[w][lane] = pl[TV_S - 1];
+  __syncthreads();
+  float2 z[TV_S];
+#pragma unroll
+  for (int s = 0; s < TV_S; ++s) {
+    const int l = l0 + s;
+    float2 up;
+    up.x = __shfl_up(pz[s].x, 1);
+    up.y = __shfl_up(pz[s].y, 1);
+    const float2 lp = (s > 0) ? pl[s - 1] : (w > 0 ? xr[w - 1][lane] : make_float2(0.f, 0.f));
+    float dx = 0.f, dy = 0.f;
+    if (zfwd) { dx += pz[s].x; dy += pz[s].y; }
+    if (zbwd) { dx -= up.x; dy -= up.y; }
+    if (l < Nx - 1) { dx += pl[s].x; dy += pl[s].y; }
+    if (l > 0) { dx -= lp.x; dy -= lp.y; }
+    z[s] = make_float2(v[s].x + tau * dx, v[s].y + tau * dy);
+  }
+  xd[w][lane] = z[0];
+  __syncthreads();
+  double acc = 0.0;
+  const bool zcore = nin && n >= cz0 && n < cz0 + a.CZ;
+#pragma unroll
+  for (int s = 0; s < TV_S; ++s) {
+    const int l = l0 + s;
+    float2 dn;
+    dn.x = __shfl_down(z[s].x, 1);
+    dn.y = __shfl_down(z[s].y, 1);
+    const float2 zl = (s < TV_S - 1) ? z[s + 1] : (w < TV_WAVES - 1 ? xd[w + 1][lane] : make_float2(0.f, 0.f));
+    if (zcore && l >= cl0 && l < cl0 + a.CL && l < Nx) {
+      float m2 = 0.f;
+      if (zfwd) m2 += (dn.x - z[s].x) * (dn.x - z[s].x) + (dn.y - z[s].y) * (dn.y - z[s].y);
+      if (l < Nx - 1) m2 += (zl.x - z[s].x) * (zl.x - z[s].x) + (zl.y - z[s].y) * (zl.y - z[s].y);
+      acc += (double)sqrtf(m2);
+      const int64_t idx = ib + (int64_t)l * Nz + n;
+      a.z[idx] = z[s];
+      a.pout[idx] = pz[s];
+      a.pout[N + idx] = pl[s];
+    }
+  }
+  const double sum = block_sum(acc, sh);
+  if (threadIdx.x == 0 && a.partial) a.partial[bid] = sum;
+}
+
 int grid_for(int64_t n, int nt) {
   int64_t b = (n + nt - 1) / nt;
   if (b > 2048) b = 2048;
@@ -492,10 +629,27 @@ hipError_t launch_prox_haar(const ProxGeom& g, int levels, const float2* v, floa
 size_t tv_work_elems(const ProxGeom& g) {
   const int nd = g.lateral_dims + 1;
   const int64_t n = (int64_t)g.B * g.Ny * g.Nx * g.Nz;
-  return (size_t)n * (size_t)(1 + nd);     // d, r
+  return (size_t)n * (size_t)(1 + nd);     // d, r of the general path
 }
 
-int tv_partials(const ProxGeom& g, int) {
+static bool tv_tiled(const ProxGeom& g, int n_inner) {
+  return g.lateral_dims == 1 && n_inner >= 1 && n_inner <= TV_MAX_TILED_INNER;
+}
+
+static void tv2d_tiles(const ProxGeom& g, int n_inner, int* CZ, int* CL, int* ntz, int* ntl) {
+  const int H = n_inner + 1;
+  *CZ = 64 - 2 * H;
+  *CL = TV_WAVES * TV_S - 2 * H;
+  *ntz = (g.Nz + *CZ - 1) / *CZ;
+  *ntl = (g.Nx + *CL - 1) / *CL;
+}
+
+int tv_partials(const ProxGeom& g, int n_inner) {
+  if (tv_tiled(g, n_inner)) {
+    int CZ, CL, ntz, ntl;
+    tv2d_tiles(g, n_inner, &CZ, &CL, &ntz, &ntl);
+    return ntz * ntl * g.B;
+  }
   const int64_t n = (int64_t)g.B * g.Ny * g.Nx * g.Nz;
   return grid_for(n, 256);
 }
@@ -504,6 +658,26 @@ int tv_partials(const ProxGeom& g, int) {
 hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, const float2* v, float2* z,
                           const float2* p_in, float2* p_out, float tau, double* partial, float2* work,
                           hipStream_t s) {
+  if (tv_tiled(g, n_inner)) {
+    Tv2dArgs a{};
+    a.Nz = g.Nz;
+    a.Nx = g.Nx;
+    a.H = n_inner + 1;
+    a.n_inner = n_inner;
+    tv2d_tiles(g, n_inner, &a.CZ, &a.CL, &a.ntz, &a.ntl);
+    a.n_total = (int64_t)g.B * g.Nx * g.Nz;
+    a.tau = tau;
+    a.step = 1.0f / (8.0f * tau);
+    for (int k = 0; k < n_inner; ++k) a.mom[k] = mom[k];
+    a.v = v;
+    a.z = z;
+    a.pin = p_in;
+    a.pout = p_out;
+    a.partial = partial;
+    const int nb = a.ntz * a.ntl * g.B;
+    hipLaunchKernelGGL(tv2d_tile_kernel, dim3(nb), dim3(TV_WAVES * 64), 0, s, a);
+    return hipGetLastError();
+  }
   TvIdx d;
   d.Nz = g.Nz;
   d.Nx = g.Nx;

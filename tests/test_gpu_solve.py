@@ -46,24 +46,33 @@ def test_prox_haar(kw, levels):
     assert rel(z, O.prox_haar(v64, 0.3, axes, levels)) <= PROX_TOL
 
 
-@pytest.mark.parametrize("kw", [dict(n_depth=64, n_x=40, n_k=64, batch=2),
-                                dict(n_depth=75, n_x=33, n_k=64),
-                                dict(n_depth=24, n_x=12, n_y=10, lateral_dims=2, n_k=32)])
-def test_prox_tv_cold_and_warm(kw):
+TV_CASES = [
+    (dict(n_depth=64, n_x=40, n_k=64, batch=2), 10),          # tiled, 2 depth tiles
+    (dict(n_depth=75, n_x=35, n_k=64), 10),
+    (dict(n_depth=130, n_x=160, n_k=64), 10),                 # several tiles both ways
+    (dict(n_depth=130, n_x=160, n_k=64), 3),                  # small halo
+    (dict(n_depth=64, n_x=40, n_k=64), 27),                   # largest tiled inner count
+    (dict(n_depth=64, n_x=40, n_k=64), 30),                   # general path (per-step passes)
+    (dict(n_depth=24, n_x=12, n_y=10, lateral_dims=2, n_k=32), 10),   # volume
+]
+
+
+@pytest.mark.parametrize("kw,inner", TV_CASES)
+def test_prox_tv_cold_and_warm(kw, inner):
     import torch
     import paper_2108_01438_amd as P
-    flush(f"[prox tv] {kw}")
+    flush(f"[prox tv] {kw} inner={inner}")
     og, pg = both_geoms(**kw)
     rng = np.random.default_rng(3)
     plan = P.Plan(pg)
     v32, v64 = rand_image(rng, O.img_shape(og))
     axes = (3, 2, 1) if og.lateral_dims == 2 else (3, 2)
     tau = 0.4
-    z1 = to_host(plan.prox("tv", tau, 1.0, to_dev(v32), tv_inner=10))
-    zr1, p1 = O.prox_tv(v64, tau, axes, 10)
+    z1 = to_host(plan.prox("tv", tau, 1.0, to_dev(v32), tv_inner=inner))
+    zr1, p1 = O.prox_tv(v64, tau, axes, inner)
     assert rel(z1, zr1) <= PROX_TOL
     state = torch.zeros((len(axes),) + O.img_shape(og), dtype=torch.complex64, device="cuda")
-    plan.prox("tv", tau, 1.0, to_dev(v32), state=state, tv_inner=10)
+    plan.prox("tv", tau, 1.0, to_dev(v32), state=state, tv_inner=inner)
     assert rel(to_host(state), p1) <= PROX_TOL
     z2 = to_host(plan.prox("tv", tau, 1.0, to_dev(v32), state=state, tv_inner=7))
     zr2, _ = O.prox_tv(v64, tau, axes, 7, p0=p1)
@@ -121,7 +130,7 @@ def test_fista_matches_oracle(name):
     z, info = plan.mbir_solve(to_dev(y32), pen, lam, iters, delta=delta, tv_inner=10, haar_levels=3,
                               objective=True)
     err = rel(to_host(z), zo)
-    flush(f"    rel err {err:.3e}")
+    print(f"[fista] {name}: rel err vs oracle {err:.3e}")
     assert err <= SOLVE_TOL
     np.testing.assert_allclose(info["objective"], ho, rtol=1e-5)
 
