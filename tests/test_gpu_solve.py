@@ -49,8 +49,8 @@ def test_prox_haar(kw, levels):
 TV_CASES = [
     (dict(n_depth=64, n_x=40, n_k=64, batch=2), 10),          # tiled, 2 depth tiles
     (dict(n_depth=75, n_x=35, n_k=64), 10),
-    (dict(n_depth=130, n_x=160, n_k=64), 10),                 # several tiles both ways
-    (dict(n_depth=130, n_x=160, n_k=64), 3),                  # small halo
+    (dict(n_depth=140, n_x=160, n_k=64), 10),                 # several tiles both ways
+    (dict(n_depth=140, n_x=160, n_k=64), 3),                  # small halo
     (dict(n_depth=64, n_x=40, n_k=64), 27),                   # largest tiled inner count
     (dict(n_depth=64, n_x=40, n_k=64), 30),                   # general path (per-step passes)
     (dict(n_depth=24, n_x=12, n_y=10, lateral_dims=2, n_k=32), 10),   # volume
