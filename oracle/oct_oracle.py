@@ -427,11 +427,18 @@ def prox_tv(v: np.ndarray, tau: float, axes, n_inner: int, p0=None):
     """Isotropic complex TV prox by the fast gradient projection (FGP) method of
     Beck and Teboulle (2009) on the dual: x = v + tau div p,
     p <- Proj_{|p_i| <= 1}( r + 1/(4 d tau) grad(v + tau div r) ), with FISTA
-    momentum on p restarted each call; p0 warm-starts the dual.
+    momentum on p restarted each call; p0 warm-starts the dual (its entries
+    without a forward neighbour, which carry no edge, are taken as zero).
     Returns (x, p)."""
     v = np.asarray(v, dtype=np.complex128)
     nd = len(axes)
     p = np.zeros((nd,) + v.shape, dtype=np.complex128) if p0 is None else np.array(p0, dtype=np.complex128)
+    # the dual lives on the grid edges of the forward differences: component
+    # c has no entry at the last index along axis c
+    for c, ax in enumerate(axes):
+        last = [slice(None)] * v.ndim
+        last[ax] = -1
+        p[c][tuple(last)] = 0.0
     if tau <= 0:
         return v.copy(), p
     step = 1.0 / (4.0 * nd * tau)

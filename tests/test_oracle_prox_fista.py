@@ -103,6 +103,21 @@ def test_prox_tv_duality_gap_vanishes(axes, shape):
     assert gaps[2] < 1e-6 * np.sum(np.abs(v) ** 2)
 
 
+def test_prox_tv_dual_lives_on_edges():
+    """Dual entries with no forward neighbour never matter: junk there in the
+    warm start gives the same prox and comes back zero."""
+    rng = np.random.default_rng(61)
+    v = cn(rng, (1, 1, 9, 7))
+    p0 = cn(rng, (2, 1, 1, 9, 7)) * 0.3
+    clean = p0.copy()
+    clean[0][..., -1] = 0.0           # depth component at the last depth index
+    clean[1][..., -1, :] = 0.0        # lateral component at the last lateral index
+    x1, p1 = O.prox_tv(v, 0.3, (3, 2), 6, p0=p0)
+    x2, p2 = O.prox_tv(v, 0.3, (3, 2), 6, p0=clean)
+    np.testing.assert_array_equal(x1, x2)
+    assert np.all(p1[0][..., -1] == 0) and np.all(p1[1][..., -1, :] == 0)
+
+
 def test_prox_tv_warm_start_continues():
     """Ten inner steps from the dual of ten earlier steps are closer to the
     exact prox than ten from zero."""
