@@ -289,6 +289,8 @@ NufftArgs nufft_args(const oct_plan* p) {
   a.n_cols = (int)(p->B * p->Nlat);
   a.ct = p->ct;
   a.df = p->df;
+  a.k_min = p->g.k_min;
+  a.dk = p->dk;
   a.k2x4 = p->k2x4;
   a.phase = p->phase;
   a.q2 = p->q2;

@@ -71,6 +71,7 @@ struct NufftArgs {
   int n_cols;
   double ct;             // K dz / (2 pi): oversampled-grid coordinate per unit beta
   double df;             // z_f - n_c dz (focus offset); 0 skips its phase
+  double k_min, dk;      // linear wavenumber grid k_m = k_min + m dk
   const double* k2x4;    // [Mk] 4 k_m^2
   const float2* phase;   // [Mk] e^{j(-2 k_m z_f + Omega_m)}
   const double* q2;      // [Nlat] |q|^2

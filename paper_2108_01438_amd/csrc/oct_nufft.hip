@@ -140,21 +140,27 @@ __global__ void __launch_bounds__(1024) nufft_adj_kernel(NufftArgs a, const floa
   }
   const int span = umax - umin + 1;
   const int nph = span > K ? (span + K - 1) / K : 1;
-  const int C = (K + nthr - 1) / nthr;
+  const double q2c = q2;
   for (int ph = 0; ph < nph; ++ph) {
     const int pbeg = umin + ph * K;
-    const int u0 = pbeg + tid * C;
-    int u1 = min(u0 + C, pbeg + K);
-    if (ph > 0) u1 = min(u1, umax + 1);
-    // first sample whose base cell reaches u0 - J/2
-    int p = mf, q = Mk;
-    const int key = u0 - J / 2;
-    while (p < q) {
-      const int mid = (p + q) >> 1;
-      if (bm[mid] < key) p = mid + 1; else q = mid;
-    }
-    for (int u = u0; u < u1; ++u) {
-      while (p < Mk && bm[p] < u - J / 2) ++p;
+    int pend = pbeg + K;
+    if (ph > 0) pend = min(pend, umax + 1);
+    // consecutive lanes take consecutive cells, so their samples are
+    // consecutive too (conflict-free LDS reads)
+    for (int u = pbeg + tid; u < pend; u += nthr) {
+      const int key = u - J / 2;   // first contributor: smallest m with bm[m] >= key
+      int p = mf;
+      if (mf < Mk) {
+        // invert t = ct sqrt(4 k^2 - q^2) for the starting sample, then walk
+        // to the exact boundary on the stored base cells
+        const double bta = fmax((double)key, 0.0) / a.ct;
+        const double km = 0.5 * sqrt(bta * bta + q2c);
+        double mstar = floor((km - a.k_min) / a.dk);
+        mstar = fmin(fmax(mstar, (double)mf), (double)Mk);
+        p = (int)mstar;
+        while (p > mf && bm[p - 1] >= key) --p;
+        while (p < Mk && bm[p] < key) ++p;
+      }
       float2 acc = make_float2(0.f, 0.f);
       for (int m = p; m < Mk && bm[m] <= u + J / 2 - 1; ++m) {
         const int j = u - (bm[m] - J / 2 + 1);

@@ -475,11 +475,9 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
       float2 qz = make_float2(rz[s].x + step * gz.x, rz[s].y + step * gz.y);
       float2 ql = make_float2(rl[s].x + step * gl.x, rl[s].y + step * gl.y);
       const float m2 = qz.x * qz.x + qz.y * qz.y + ql.x * ql.x + ql.y * ql.y;
-      if (m2 > 1.f) {
-        const float sc = 1.f / sqrtf(m2);
-        qz = cscale(qz, sc);
-        ql = cscale(ql, sc);
-      }
+      const float sc = m2 > 1.f ? rsqrtf(m2) : 1.f;
+      qz = cscale(qz, sc);
+      ql = cscale(ql, sc);
       rz[s] = make_float2(qz.x + mom * (qz.x - pz[s].x), qz.y + mom * (qz.y - pz[s].y));
       rl[s] = make_float2(ql.x + mom * (ql.x - pl[s].x), ql.y + mom * (ql.y - pl[s].y));
       pz[s] = qz;
