@@ -124,6 +124,8 @@ bool factorize(int n, FftDesc& d) {
   for (size_t s = 0; s < rad.size(); ++s) {
     d.radix[s] = rad[s];
     d.ns[s] = prod;
+    d.div_nb[s] = make_fastdiv((uint32_t)(n / rad[s]));
+    d.div_ns[s] = make_fastdiv((uint32_t)prod);
     prod *= rad[s];
     if (rad[s] < mr) mr = rad[s];
   }
@@ -267,6 +269,8 @@ LatArgs lat_args(const oct_plan* p, const LineGeom& lg, bool yaxis) {
   a.tw = yaxis ? p->twY : p->twX;
   int nthr = 256, rs = lg.L;
   a.T = lateral_pick_tile(lg, a.fd, &nthr, &rs);
+  a.log2T = 0;
+  while ((1 << a.log2T) < a.T) ++a.log2T;
   a.rowstride = rs;
   a.n_tiles = (lg.rows + a.T - 1) / a.T;
   a.scale = 1.f;

@@ -8,12 +8,39 @@
 #define OCT_KB_DEG 9             // degree of each KB polynomial piece
 #define OCT_MAX_J 8
 
+// Division of a 32-bit unsigned by a runtime constant d >= 1 through a
+// multiply-high (Granlund-Montgomery round-up method): with l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1, q = (t + ((x - t) >> 1)) >> (l - 1),
+// t = mulhi(m, x), exact for every 32-bit x; d = 1 is flagged by s = -1.
+struct FastDiv {
+  uint32_t m;
+  int s;
+  uint32_t d;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  if (d <= 1) {
+    f.m = 0;
+    f.s = -1;
+    return f;
+  }
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  f.m = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+  f.s = l - 1;
+  return f;
+}
+
 // Mixed-radix factorisation of one transform length for the LDS Stockham FFT.
 struct FftDesc {
   int n;
   int nstages;
   int radix[OCT_MAX_STAGES];
   int ns[OCT_MAX_STAGES];        // product of the radices before each stage
+  FastDiv div_nb[OCT_MAX_STAGES];  // by n / radix (butterflies per row)
+  FastDiv div_ns[OCT_MAX_STAGES];  // by ns
   int min_radix;
 };
 
@@ -44,7 +71,8 @@ struct LatArgs {
   LineGeom lg;
   FftDesc fd;
   const float2* tw;      // e^{-2 pi i j / L}, j < L
-  int T;                 // rows per tile
+  int T;                 // rows per tile (a power of two)
+  int log2T;
   int n_tiles;
   int rowstride;         // LDS row stride (>= L)
   int inverse;           // transform sign (+ when 1)

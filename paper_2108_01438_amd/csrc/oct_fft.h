@@ -25,6 +25,12 @@ __device__ __forceinline__ float2 rot90(float2 a) {
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) {
+  if (f.s < 0) return x;
+  const uint32_t t = __umulhi(f.m, x);
+  return (t + ((x - t) >> 1)) >> f.s;
+}
+
 template <int R, bool INV> struct Dft;
 
 template <bool INV> struct Dft<2, INV> {
@@ -143,6 +149,7 @@ template <bool INV> struct Dft<7, INV> : DftOdd<7, INV> {};
 // buf[row * rowstride + i].
 template <int R, int MAXB, bool INV>
 __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride, int n, int Ns,
+                                          const FastDiv& dnb, const FastDiv& dns,
                                           const float2* __restrict__ tw, int tid, int nthr) {
   const int nb = n / R;
   const int total = nrows * nb;
@@ -153,7 +160,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride,
   for (int b = 0; b < MAXB; ++b) {
     const int item = tid + b * nthr;
     if (item < total) {
-      const int row = item / nb;
+      const int row = (int)fdiv((uint32_t)item, dnb);
       const int j = item - row * nb;
       const float2* src = buf + row * rowstride + j;
 #pragma unroll
@@ -168,7 +175,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride,
     const int item = tid + b * nthr;
     if (item < total) {
       const int j = jj[b];
-      const int k = j % Ns;
+      const int k = j - (int)fdiv((uint32_t)j, dns) * Ns;
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -201,13 +208,13 @@ __device__ __forceinline__ void fft_rows(float2* buf, int nrows, int rowstride, 
   for (int s = 0; s < d.nstages; ++s) {
     const int Ns = d.ns[s];
     switch (d.radix[s]) {
-      case 8: fft_stage<8, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
-      case 4: fft_stage<4, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
-      case 2: fft_stage<2, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
-      case 5: fft_stage<5, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
-      case 3: fft_stage<3, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr); break;
+      case 8: fft_stage<8, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
+      case 4: fft_stage<4, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
+      case 2: fft_stage<2, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
+      case 5: fft_stage<5, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
+      case 3: fft_stage<3, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
       default:
-        if (R7) fft_stage<7, MB, INV>(buf, nrows, rowstride, d.n, Ns, tw, tid, nthr);
+        if (R7) fft_stage<7, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr);
         break;
     }
   }

@@ -57,8 +57,8 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
 
   // ---- load the tile: element (row t, lateral l) -> lds[t * rs + l]
   for (int idx = tid; idx < n; idx += nthr) {
-    const int l = idx / T;
-    const int t = idx - l * T;
+    const int l = idx >> a.log2T;
+    const int t = idx & (T - 1);
     float2 v = make_float2(0.f, 0.f);
     if (t < nr) {
       const int64_t off = base + (int64_t)l * lg.es + t;
@@ -82,14 +82,14 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
 
   if (MODE == LAT_FFT || MODE == LAT_ADJ_MEAS) {
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx / T, t = idx - l * T;
+      const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale);
     }
     return;
   }
   if (MODE == LAT_FWD_MEAS) {
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx / T, t = idx - l * T;
+      const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) {
         float yv = lds[t * rs + l].x * a.scale;
         if (a.mask && !mask_bit(a.mask, a.mask_words, latb + l, r0 + t)) yv = 0.f;
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   }
   if (MODE == LAT_UPDATE) {
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx / T, t = idx - l * T;
+      const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) {
         const int64_t off = base + (int64_t)l * lg.es + t;
         const float2 g = cscale(lds[t * rs + l], a.scale);
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   if (MODE == LAT_NORMAL) {
     double acc = 0.0;
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx / T, t = idx - l * T;
+      const int l = idx >> a.log2T, t = idx & (T - 1);
       float r = 0.f;
       if (t < nr) {
         const int64_t off = base + (int64_t)l * lg.es + t;
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     __syncthreads();
     fft_rows<R7, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx / T, t = idx - l * T;
+      const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
     }
     const double s = block_sum_d(acc, red);
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   if (MODE == LAT_UPDATE_L1) {
     double acc = 0.0;
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx / T, t = idx - l * T;
+      const int l = idx >> a.log2T, t = idx & (T - 1);
       float2 xn = make_float2(0.f, 0.f);
       if (t < nr) {
         const int64_t off = base + (int64_t)l * lg.es + t;
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     __syncthreads();
     fft_rows<R7, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx / T, t = idx - l * T;
+      const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = lds[t * rs + l];
     }
     const double s = block_sum_d(acc, red);

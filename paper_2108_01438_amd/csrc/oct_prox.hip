@@ -406,6 +406,19 @@ __global__ void tv_value_kernel(TvIdx d, const float2* __restrict__ z, double* p
 constexpr int TV_S = 6;
 constexpr int TV_WAVES = 16;
 
+// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1, zero filled at the
+// wave edge): lane i receives lane i-1 (shr) or lane i+1 (shl).
+__device__ __forceinline__ float lane_prev(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// The dual is kept zero wherever its component has no forward edge (last
+// index along that axis, and every sample outside the image).  The step of
+// such a component is zero too, so it stays zero, and the divergence needs
+// no boundary tests: (div p)_i = p_i - p_{i-1} along each axis.
 __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   __shared__ float2 xr[TV_WAVES][64];
   __shared__ float2 xd[TV_WAVES][64];
@@ -425,23 +438,27 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   const int n = cz0 - H + lane;
   const int l0 = cl0 - H + w * TV_S;
   const bool nin = (n >= 0 && n < Nz);
+  const bool zedge = (n >= 0 && n < Nz - 1);
   const int64_t ib = (int64_t)b * Nx * Nz;
   const int64_t N = a.n_total;
-  const bool zfwd = n < Nz - 1, zbwd = n > 0;
+  const float tau = a.tau, step = a.step;
+  const float sz = zedge ? step : 0.f;
 
   float2 v[TV_S], pz[TV_S], pl[TV_S], rz[TV_S], rl[TV_S];
+  float sl[TV_S];
 #pragma unroll
   for (int s = 0; s < TV_S; ++s) {
     const int l = l0 + s;
     const bool in = nin && l >= 0 && l < Nx;
+    const bool ledge = l >= 0 && l < Nx - 1;
+    sl[s] = ledge ? step : 0.f;
     const int64_t idx = ib + (int64_t)l * Nz + n;
     v[s] = in ? a.v[idx] : make_float2(0.f, 0.f);
-    pz[s] = (in && a.pin) ? a.pin[idx] : make_float2(0.f, 0.f);
-    pl[s] = (in && a.pin) ? a.pin[N + idx] : make_float2(0.f, 0.f);
+    pz[s] = (in && zedge && a.pin) ? a.pin[idx] : make_float2(0.f, 0.f);
+    pl[s] = (in && ledge && a.pin) ? a.pin[N + idx] : make_float2(0.f, 0.f);
     rz[s] = pz[s];
     rl[s] = pl[s];
   }
-  const float tau = a.tau, step = a.step;
   for (int k = 0; k < a.n_inner; ++k) {
     const float mom = a.mom[k];
     xr[w][lane] = rl[TV_S - 1];
@@ -449,37 +466,25 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
     float2 d[TV_S];
 #pragma unroll
     for (int s = 0; s < TV_S; ++s) {
-      const int l = l0 + s;
-      float2 up;
-      up.x = __shfl_up(rz[s].x, 1);
-      up.y = __shfl_up(rz[s].y, 1);
       const float2 lp = (s > 0) ? rl[s - 1] : (w > 0 ? xr[w - 1][lane] : make_float2(0.f, 0.f));
-      float dx = 0.f, dy = 0.f;
-      if (zfwd) { dx += rz[s].x; dy += rz[s].y; }
-      if (zbwd) { dx -= up.x; dy -= up.y; }
-      if (l < Nx - 1) { dx += rl[s].x; dy += rl[s].y; }
-      if (l > 0) { dx -= lp.x; dy -= lp.y; }
-      d[s] = make_float2(v[s].x + tau * dx, v[s].y + tau * dy);
+      const float dx = (rz[s].x - lane_prev(rz[s].x)) + (rl[s].x - lp.x);
+      const float dy = (rz[s].y - lane_prev(rz[s].y)) + (rl[s].y - lp.y);
+      d[s] = make_float2(fmaf(tau, dx, v[s].x), fmaf(tau, dy, v[s].y));
     }
     xd[w][lane] = d[0];
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < TV_S; ++s) {
-      const int l = l0 + s;
-      float2 dn;
-      dn.x = __shfl_down(d[s].x, 1);
-      dn.y = __shfl_down(d[s].y, 1);
       const float2 dl = (s < TV_S - 1) ? d[s + 1] : (w < TV_WAVES - 1 ? xd[w + 1][lane] : make_float2(0.f, 0.f));
-      const float2 gz = zfwd ? make_float2(dn.x - d[s].x, dn.y - d[s].y) : make_float2(0.f, 0.f);
-      const float2 gl = (l < Nx - 1) ? make_float2(dl.x - d[s].x, dl.y - d[s].y) : make_float2(0.f, 0.f);
-      float2 qz = make_float2(rz[s].x + step * gz.x, rz[s].y + step * gz.y);
-      float2 ql = make_float2(rl[s].x + step * gl.x, rl[s].y + step * gl.y);
+      float2 qz = make_float2(fmaf(sz, lane_next(d[s].x) - d[s].x, rz[s].x),
+                              fmaf(sz, lane_next(d[s].y) - d[s].y, rz[s].y));
+      float2 ql = make_float2(fmaf(sl[s], dl.x - d[s].x, rl[s].x), fmaf(sl[s], dl.y - d[s].y, rl[s].y));
       const float m2 = qz.x * qz.x + qz.y * qz.y + ql.x * ql.x + ql.y * ql.y;
       const float sc = m2 > 1.f ? rsqrtf(m2) : 1.f;
       qz = cscale(qz, sc);
       ql = cscale(ql, sc);
-      rz[s] = make_float2(qz.x + mom * (qz.x - pz[s].x), qz.y + mom * (qz.y - pz[s].y));
-      rl[s] = make_float2(ql.x + mom * (ql.x - pl[s].x), ql.y + mom * (ql.y - pl[s].y));
+      rz[s] = make_float2(fmaf(mom, qz.x - pz[s].x, qz.x), fmaf(mom, qz.y - pz[s].y, qz.y));
+      rl[s] = make_float2(fmaf(mom, ql.x - pl[s].x, ql.x), fmaf(mom, ql.y - pl[s].y, ql.y));
       pz[s] = qz;
       pl[s] = ql;
     }
@@ -490,17 +495,10 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   float2 z[TV_S];
 #pragma unroll
   for (int s = 0; s < TV_S; ++s) {
-    const int l = l0 + s;
-    float2 up;
-    up.x = __shfl_up(pz[s].x, 1);
-    up.y = __shfl_up(pz[s].y, 1);
     const float2 lp = (s > 0) ? pl[s - 1] : (w > 0 ? xr[w - 1][lane] : make_float2(0.f, 0.f));
-    float dx = 0.f, dy = 0.f;
-    if (zfwd) { dx += pz[s].x; dy += pz[s].y; }
-    if (zbwd) { dx -= up.x; dy -= up.y; }
-    if (l < Nx - 1) { dx += pl[s].x; dy += pl[s].y; }
-    if (l > 0) { dx -= lp.x; dy -= lp.y; }
-    z[s] = make_float2(v[s].x + tau * dx, v[s].y + tau * dy);
+    const float dx = (pz[s].x - lane_prev(pz[s].x)) + (pl[s].x - lp.x);
+    const float dy = (pz[s].y - lane_prev(pz[s].y)) + (pl[s].y - lp.y);
+    z[s] = make_float2(fmaf(tau, dx, v[s].x), fmaf(tau, dy, v[s].y));
   }
   xd[w][lane] = z[0];
   __syncthreads();
@@ -509,13 +507,11 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
 #pragma unroll
   for (int s = 0; s < TV_S; ++s) {
     const int l = l0 + s;
-    float2 dn;
-    dn.x = __shfl_down(z[s].x, 1);
-    dn.y = __shfl_down(z[s].y, 1);
+    const float dnx = lane_next(z[s].x), dny = lane_next(z[s].y);
     const float2 zl = (s < TV_S - 1) ? z[s + 1] : (w < TV_WAVES - 1 ? xd[w + 1][lane] : make_float2(0.f, 0.f));
     if (zcore && l >= cl0 && l < cl0 + a.CL && l < Nx) {
       float m2 = 0.f;
-      if (zfwd) m2 += (dn.x - z[s].x) * (dn.x - z[s].x) + (dn.y - z[s].y) * (dn.y - z[s].y);
+      if (zedge) m2 += (dnx - z[s].x) * (dnx - z[s].x) + (dny - z[s].y) * (dny - z[s].y);
       if (l < Nx - 1) m2 += (zl.x - z[s].x) * (zl.x - z[s].x) + (zl.y - z[s].y) * (zl.y - z[s].y);
       acc += (double)sqrtf(m2);
       const int64_t idx = ib + (int64_t)l * Nz + n;
