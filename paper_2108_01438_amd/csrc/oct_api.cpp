@@ -64,11 +64,14 @@ double kb0_ft(double f, int J, double b) {
 }
 
 // Tap j of the J-tap window as a polynomial in x = 2 f - 1, f = frac(t):
-// Chebyshev interpolation at KB_DEG+1 nodes, converted to monomials.
+// Chebyshev interpolation at KB_DEG+1 nodes, converted to monomials.  Only
+// taps j < J/2 are stored, split into even and odd parts in x^2: the window
+// is even, so tap J-1-j is the same polynomial at -x.
 void kb_pieces(int J, double b, std::vector<float>& out) {
   const int D = OCT_KB_DEG;
-  out.assign((size_t)J * (D + 1), 0.f);
-  for (int j = 0; j < J; ++j) {
+  const int Hh = (D + 1) / 2;
+  out.assign((size_t)(J / 2) * 2 * Hh, 0.f);
+  for (int j = 0; j < J / 2; ++j) {
     std::vector<double> c(D + 1, 0.0);
     for (int k = 0; k <= D; ++k) {
       double s = 0.0;
@@ -85,8 +88,7 @@ void kb_pieces(int J, double b, std::vector<float>& out) {
     tkm1[0] = 1.0;          // T0
     tk[1] = 1.0;            // T1
     for (int i = 0; i <= D; ++i) mono[i] += c[0] * tkm1[i];
-    if (D >= 1)
-      for (int i = 0; i <= D; ++i) mono[i] += c[1] * tk[i];
+    for (int i = 0; i <= D; ++i) mono[i] += c[1] * tk[i];
     for (int k = 2; k <= D; ++k) {
       std::fill(tkp1.begin(), tkp1.end(), 0.0);
       for (int i = 0; i < D; ++i) tkp1[i + 1] += 2.0 * tk[i];
@@ -95,7 +97,10 @@ void kb_pieces(int J, double b, std::vector<float>& out) {
       tkm1 = tk;
       tk = tkp1;
     }
-    for (int i = 0; i <= D; ++i) out[(size_t)j * (D + 1) + i] = (float)mono[i];
+    for (int i = 0; i < Hh; ++i) {
+      out[(size_t)j * 2 * Hh + i] = (float)mono[2 * i];
+      out[(size_t)j * 2 * Hh + Hh + i] = (float)mono[2 * i + 1];
+    }
   }
 }
 
@@ -134,11 +139,22 @@ bool factorize(int n, FftDesc& d) {
   return true;
 }
 
-std::vector<float2> twiddles(int n) {
-  std::vector<float2> t(n);
-  for (int j = 0; j < n; ++j) {
+// Two-level twiddle table of FftDesc: lo[j] = w^j (j < B), hi[h] = w^{h B}.
+std::vector<float2> twiddles(FftDesc& d) {
+  const int n = d.n;
+  int lb = 0;
+  while ((1 << lb) * (1 << lb) < n) ++lb;   // B = 2^lb >= sqrt(n)
+  d.tw_log2b = lb;
+  const int B = 1 << lb;
+  d.tw_nhi = (n + B - 1) / B;
+  std::vector<float2> t(B + d.tw_nhi);
+  for (int j = 0; j < B; ++j) {
     const double a = -2.0 * kPi * (double)j / (double)n;
     t[j] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  for (int h = 0; h < d.tw_nhi; ++h) {
+    const double a = -2.0 * kPi * (double)((int64_t)h * B) / (double)n;
+    t[B + h] = make_float2((float)std::cos(a), (float)std::sin(a));
   }
   return t;
 }
@@ -162,6 +178,7 @@ struct oct_plan {
   float* kbc = nullptr;
   uint32_t* mask = nullptr;
   int mask_words = 0;
+
   float2 *X1 = nullptr, *W = nullptr;
   double* partial = nullptr;
   int partial_cap = 0;
@@ -230,9 +247,15 @@ oct_status unsupported_sizes(const oct_geometry* g) {
   if (g->lateral_dims == 2 && (g->n_y > 4096 || !factorize((int)g->n_y, d)))
     return fail(OCT_E_UNSUPPORTED, "n_y must be 7-smooth and <= 4096");
   if (g->n_k > 8192) return fail(OCT_E_UNSUPPORTED, "n_k > 8192");
-  // adjoint column kernel keeps the grid and the samples in LDS
-  const size_t lds = (size_t)K * 8 + (size_t)g->n_k * 16;
+  // adjoint column kernel keeps the grid, the samples and the twiddles in LDS
+  const size_t lds = (size_t)K * 8 + (size_t)g->n_k * 14 + 8 * 512;
   if (lds > 160 * 1024 - 4096) return fail(OCT_E_UNSUPPORTED, "grid + samples exceed the LDS of one CU");
+  // base cells of one column are stored as 16-bit offsets: bound the span of t
+  const double dk = (g->k_max - g->k_min) / (double)(g->n_k - 1);
+  const double dz = g->dz > 0 ? g->dz : kPi / (2.0 * (double)g->n_depth * dk);
+  const double tmax = (double)K * dz / (2.0 * kPi) * 2.0 * g->k_max;
+  if (tmax + 2 * g->kb_width > 32000.0)
+    return fail(OCT_E_UNSUPPORTED, "oversampled-grid coordinates span more than 32000 cells");
   return OCT_OK;
 }
 
@@ -588,16 +611,16 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   }
   std::vector<float> kbc;
   kb_pieces(p->J, p->kbb, kbc);
-
-  if ((st = upload(p, &p->twK, twiddles((int)p->K))) != OCT_OK) return cleanup(st);
-  if ((st = upload(p, &p->twX, twiddles((int)p->Nx))) != OCT_OK) return cleanup(st);
-  if ((st = upload(p, &p->twY, twiddles((int)p->Ny))) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->twK, twiddles(p->fK))) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->twX, twiddles(p->fX))) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->twY, twiddles(p->fY))) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->k2x4, k2x4)) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->phase, ph)) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->q2, q2)) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->beam, beam)) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->deap, deap)) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->kbc, kbc)) != OCT_OK) return cleanup(st);
+
   if (mask) {
     p->mask_words = (int)((p->Mk + 31) / 32);
     std::vector<uint32_t> bits((size_t)p->Nlat * p->mask_words, 0u);

@@ -42,7 +42,14 @@ struct FftDesc {
   FastDiv div_nb[OCT_MAX_STAGES];  // by n / radix (butterflies per row)
   FastDiv div_ns[OCT_MAX_STAGES];  // by ns
   int min_radix;
+  // twiddles w^e = e^{-2 pi i e / n} as lo[e mod B] * hi[e div B], B = 2^tw_log2b:
+  // the table holds lo (B entries) then hi (tw_nhi entries)
+  int tw_log2b;
+  int tw_nhi;
 };
+
+// entries of the two-level twiddle table of a transform
+__host__ __device__ inline int fft_tw_entries(const FftDesc& d) { return (1 << d.tw_log2b) + d.tw_nhi; }
 
 // Lines of a lateral transform.  Element (line o, lateral index l, row i) of a
 // [.. ][lateral][rows] array lives at base(o) + l * es + i, with
@@ -70,7 +77,7 @@ enum LatMode {
 struct LatArgs {
   LineGeom lg;
   FftDesc fd;
-  const float2* tw;      // e^{-2 pi i j / L}, j < L
+  const float2* tw;      // two-level twiddle table of the lateral transform
   int T;                 // rows per tile (a power of two)
   int log2T;
   int n_tiles;
@@ -105,9 +112,9 @@ struct NufftArgs {
   const double* q2;      // [Nlat] |q|^2
   const float* beam;     // [Nlat] e^{-q^2 w0^2 / 8}
   const float* deap;     // [Nz] 1 / Psi0((n - n_c) / K)
-  const float* kbc;      // [J][OCT_KB_DEG + 1] polynomial pieces in x = 2f - 1
+  const float* kbc;      // [J/2][even, odd][(OCT_KB_DEG+1)/2] KB pieces in x = 2f - 1
   FftDesc fK;
-  const float2* twK;
+  const float2* twK;     // two-level twiddle table of the K-point transform
 };
 
 // Launchers (kernels in the .hip files; all asynchronous on `s`).

@@ -8,7 +8,9 @@
 // The transform runs in place in one LDS buffer: every thread first pulls
 // all of its butterflies into registers, a barrier separates the reads from
 // the writes, so the per-stage work must fit MAXB butterflies per thread.
-// Twiddles come from an FP64-built table e^{-2 pi i j / n} rounded to FP32.
+// Twiddles w^e = e^{-2 pi i e / n} come from a two-level table held in LDS,
+// lo[e mod B] * hi[e div B] (both FP64-built, rounded to FP32), which the
+// kernel stages next to its data.
 #pragma once
 #include "oct_common.h"
 
@@ -120,25 +122,40 @@ template <> struct Roots<7> {
   }
 };
 
+// Odd radix by the pair symmetry of the DFT: with t_r = a_r + a_{R-r} and
+// u_r = a_r - a_{R-r} (r = 1..(R-1)/2), X_0 = a_0 + sum t_r and, for
+// s = 1..(R-1)/2, X_s = A_s -+ i B_s, X_{R-s} = A_s +- i B_s with
+// A_s = a_0 + sum_r cos(2 pi r s / R) t_r, B_s = sum_r sin(2 pi r s / R) u_r.
 template <int R, bool INV> struct DftOdd {
   static __device__ __forceinline__ void run(float2* a) {
-    float2 out[R];
+    constexpr int h = (R - 1) / 2;
+    float2 t[h + 1], u[h + 1];
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-      float2 acc = a[0];
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const int k = (r * s) % R;
-        // e^{-+ 2 pi i k / R} = cos - + i sin
-        const float cr = Roots<R>::c(k);
-        const float si = INV ? Roots<R>::s(k) : -Roots<R>::s(k);
-        acc.x += a[r].x * cr - a[r].y * si;
-        acc.y += a[r].x * si + a[r].y * cr;
-      }
-      out[s] = acc;
+    for (int r = 1; r <= h; ++r) {
+      t[r] = cadd(a[r], a[R - r]);
+      u[r] = csub(a[r], a[R - r]);
     }
+    float2 x0 = a[0];
 #pragma unroll
-    for (int s = 0; s < R; ++s) a[s] = out[s];
+    for (int r = 1; r <= h; ++r) x0 = cadd(x0, t[r]);
+#pragma unroll
+    for (int s = 1; s <= h; ++s) {
+      float2 A = a[0], Bv = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int r = 1; r <= h; ++r) {
+        const int k = (r * s) % R;
+        const float cr = Roots<R>::c(k), sr = Roots<R>::s(k);
+        A.x = fmaf(cr, t[r].x, A.x);
+        A.y = fmaf(cr, t[r].y, A.y);
+        Bv.x = fmaf(sr, u[r].x, Bv.x);
+        Bv.y = fmaf(sr, u[r].y, Bv.y);
+      }
+      // -i B (forward) or +i B (inverse)
+      const float2 iB = rot90<INV>(Bv);
+      a[s] = cadd(A, iB);
+      a[R - s] = csub(A, iB);
+    }
+    a[0] = x0;
   }
 };
 template <bool INV> struct Dft<3, INV> : DftOdd<3, INV> {};
@@ -147,10 +164,21 @@ template <bool INV> struct Dft<7, INV> : DftOdd<7, INV> {};
 
 // One Stockham stage over `nrows` transforms of length n stored at
 // buf[row * rowstride + i].
+__device__ __forceinline__ float2 twiddle(const float2* tw, int lb, int e) {
+  return cmul(tw[e & ((1 << lb) - 1)], tw[(1 << lb) + (e >> lb)]);
+}
+
+// Copy the two-level twiddle table of a transform into LDS.
+__device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __restrict__ src, const FftDesc& d,
+                                               int tid, int nthr) {
+  const int n = (1 << d.tw_log2b) + d.tw_nhi;
+  for (int i = tid; i < n; i += nthr) dst[i] = src[i];
+}
+
 template <int R, int MAXB, bool INV>
 __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride, int n, int Ns,
-                                          const FastDiv& dnb, const FastDiv& dns,
-                                          const float2* __restrict__ tw, int tid, int nthr) {
+                                          const FastDiv& dnb, const FastDiv& dns, int lb,
+                                          const float2* tw, int tid, int nthr) {
   const int nb = n / R;
   const int total = nrows * nb;
   const int tws = n / (Ns * R);
@@ -179,7 +207,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride,
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * k * tws];
+          float2 w = twiddle(tw, lb, r * k * tws);
           if (INV) w.y = -w.y;
           v[b][r] = cmul(v[b][r], w);
         }
@@ -201,20 +229,21 @@ struct FftCfg {
   static constexpr int MAXB = R7 ? 1 : 2;
 };
 
+// tw: the LDS copy of the transform's two-level twiddle table.
 template <bool R7, bool INV>
 __device__ __forceinline__ void fft_rows(float2* buf, int nrows, int rowstride, const FftDesc& d,
-                                         const float2* __restrict__ tw, int tid, int nthr) {
+                                         const float2* tw, int tid, int nthr) {
   constexpr int MB = FftCfg<R7>::MAXB;
   for (int s = 0; s < d.nstages; ++s) {
     const int Ns = d.ns[s];
     switch (d.radix[s]) {
-      case 8: fft_stage<8, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
-      case 4: fft_stage<4, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
-      case 2: fft_stage<2, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
-      case 5: fft_stage<5, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
-      case 3: fft_stage<3, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr); break;
+      case 8: fft_stage<8, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
+      case 4: fft_stage<4, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
+      case 2: fft_stage<2, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
+      case 5: fft_stage<5, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
+      case 3: fft_stage<3, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
       default:
-        if (R7) fft_stage<7, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], tw, tid, nthr);
+        if (R7) fft_stage<7, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr);
         break;
     }
   }

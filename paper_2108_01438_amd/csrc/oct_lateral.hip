@@ -55,6 +55,8 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   const int latb = (line % lg.lat_lines) * L;
   const int n = L * T;
 
+  float2* twl = lds + T * rs;   // twiddle table after the tile
+  stage_twiddles(twl, a.tw, a.fd, tid, nthr);
   // ---- load the tile: element (row t, lateral l) -> lds[t * rs + l]
   for (int idx = tid; idx < n; idx += nthr) {
     const int l = idx >> a.log2T;
@@ -77,8 +79,8 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   }
   __syncthreads();
 
-  if (a.inverse) fft_rows<R7, true>(lds, T, rs, a.fd, a.tw, tid, nthr);
-  else fft_rows<R7, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
+  if (a.inverse) fft_rows<R7, true>(lds, T, rs, a.fd, twl, tid, nthr);
+  else fft_rows<R7, false>(lds, T, rs, a.fd, twl, tid, nthr);
 
   if (MODE == LAT_FFT || MODE == LAT_ADJ_MEAS) {
     for (int idx = tid; idx < n; idx += nthr) {
@@ -125,7 +127,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       lds[t * rs + l] = make_float2(r, 0.f);
     }
     __syncthreads();
-    fft_rows<R7, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
+    fft_rows<R7, false>(lds, T, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       lds[t * rs + l] = xn;
     }
     __syncthreads();
-    fft_rows<R7, false>(lds, T, rs, a.fd, a.tw, tid, nthr);
+    fft_rows<R7, false>(lds, T, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = lds[t * rs + l];
@@ -173,13 +175,14 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
 int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* rowstride) {
   const int rs = (lg.L % 2 == 0) ? lg.L + 1 : lg.L;  // odd stride spreads LDS banks
   const int mb = fft_maxb(fd);
+  const int64_t budget = 65280 - 8 * (int64_t)fft_tw_entries(fd);   // tile + twiddles within 64 KB
   int T = 32;
-  while (T > 1 && (int64_t)T * rs * 8 > 64512) T >>= 1;
+  while (T > 1 && (int64_t)T * rs * 8 > budget) T >>= 1;
   while (T > 1 && T > lg.rows) T >>= 1;
   for (; T >= 1; T >>= 1) {
     const int64_t bf = (int64_t)T * lg.L / fd.min_radix;
     for (int nt = 256; nt <= 1024; nt <<= 1) {
-      if (bf <= mb * nt && (int64_t)T * rs * 8 <= 64512) {
+      if (bf <= mb * nt && (int64_t)T * rs * 8 <= budget) {
         *nthr = nt;
         *rowstride = rs;
         return T;
@@ -191,7 +194,7 @@ int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* row
 
 template <bool R7>
 hipError_t launch_lateral_t(LatMode mode, const LatArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)a.T * a.rowstride * sizeof(float2);
+  const size_t lds = ((size_t)a.T * a.rowstride + fft_tw_entries(a.fd)) * sizeof(float2);
   const int grid = a.lg.n_lines * a.n_tiles;
   const int mb = FftCfg<R7>::MAXB;
   int nthr = 256;

@@ -20,11 +20,38 @@ namespace {
 
 constexpr int KBD = OCT_KB_DEG;
 
-__device__ __forceinline__ float kb_poly(const float* __restrict__ c, float x) {
-  float w = c[KBD];
+// Tap jj < J/2 is P(x) = E(x^2) + x O(x^2); the mirrored tap J-1-jj is
+// P(-x) = E(x^2) - x O(x^2) (the window is even).  c holds E then O, each
+// KBH coefficients in increasing powers of x^2.
+constexpr int KBH = (KBD + 1) / 2;
+
+__device__ __forceinline__ void kb_pair(const float* __restrict__ c, float x, float x2, float& wlo, float& whi) {
+  float e = c[KBH - 1], o = c[2 * KBH - 1];
 #pragma unroll
-  for (int d = KBD - 1; d >= 0; --d) w = fmaf(w, x, c[d]);
-  return w;
+  for (int d = KBH - 2; d >= 0; --d) {
+    e = fmaf(e, x2, c[d]);
+    o = fmaf(o, x2, c[KBH + d]);
+  }
+  const float xo = x * o;
+  wlo = e + xo;
+  whi = e - xo;
+}
+
+// weight of tap j (0..J-1) for fraction coordinate x
+template <int J>
+__device__ __forceinline__ float kb_tap(const float* __restrict__ kc, int j, float x) {
+  const bool lo = j < J / 2;
+  const int jj = lo ? j : J - 1 - j;
+  const float xs = lo ? x : -x;
+  const float* c = kc + jj * 2 * KBH;
+  const float x2 = xs * xs;
+  float e = c[KBH - 1], o = c[2 * KBH - 1];
+#pragma unroll
+  for (int d = KBH - 2; d >= 0; --d) {
+    e = fmaf(e, x2, c[d]);
+    o = fmaf(o, x2, c[KBH + d]);
+  }
+  return fmaf(xs, o, e);
 }
 
 // Filter H(m, q) = beam(q) e^{j(-2 k_m z_f + Omega_m)} e^{j beta (z_f - n_c dz)}.
@@ -49,6 +76,8 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
   const int lat = col % a.Nlat;
   const int K = a.K, Nz = a.Nz, nc = a.nc;
   const float2* __restrict__ src = X1 + (int64_t)col * Nz;
+  float2* twl = grid + K;
+  stage_twiddles(twl, a.twK, a.fK, tid, nthr);
 
   // n' = n - n_c placed at n' mod K; cells [Nz - nc, K - nc) stay zero.
   for (int i = tid; i < K - Nz; i += nthr) grid[Nz - nc + i] = make_float2(0.f, 0.f);
@@ -58,7 +87,7 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
     grid[idx] = cscale(src[n], a.deap[n]);
   }
   __syncthreads();
-  fft_rows<R7, false>(grid, 1, K, a.fK, a.twK, tid, nthr);
+  fft_rows<R7, false>(grid, 1, K, a.fK, twl, tid, nthr);
 
   const double q2 = a.q2[lat];
   const float bq = a.beam[lat];
@@ -74,14 +103,19 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
       int c0 = ((int)fl - J / 2 + 1) % K;
       if (c0 < 0) c0 += K;
       float2 acc = make_float2(0.f, 0.f);
+      const float x2 = x * x;
 #pragma unroll
-      for (int j = 0; j < J; ++j) {
-        const float w = kb_poly(a.kbc + j * (KBD + 1), x);
-        int idx = c0 + j;
-        if (idx >= K) idx -= K;
-        const float2 gv = grid[idx];
-        acc.x = fmaf(w, gv.x, acc.x);
-        acc.y = fmaf(w, gv.y, acc.y);
+      for (int jj = 0; jj < J / 2; ++jj) {
+        float wlo, whi;
+        kb_pair(a.kbc + jj * 2 * KBH, x, x2, wlo, whi);
+        int i0 = c0 + jj, i1 = c0 + J - 1 - jj;
+        if (i0 >= K) i0 -= K;
+        if (i1 >= K) i1 -= K;
+        const float2 g0 = grid[i0], g1 = grid[i1];
+        acc.x = fmaf(wlo, g0.x, acc.x);
+        acc.y = fmaf(wlo, g0.y, acc.y);
+        acc.x = fmaf(whi, g1.x, acc.x);
+        acc.y = fmaf(whi, g1.y, acc.y);
       }
       res = cmul(filter_h(a, m, bq, beta), acc);
     }
@@ -90,22 +124,32 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
 }
 
 constexpr int EVANESCENT = -(1 << 29);
+constexpr short EVANESCENT16 = -32768;
+
+// LDS layout of the adjoint: the sample arrays (filtered samples, tap
+// fractions, base cells) and, after the gather, the K-cell grid share one
+// region; each thread holds its cells in registers in between.
+constexpr int ADJ_MAXC = 8;   // grid cells per thread
 
 template <int J, bool R7>
-__global__ void __launch_bounds__(1024) nufft_adj_kernel(NufftArgs a, const float2* __restrict__ Rh,
-                                                         float2* __restrict__ X) {
+__global__ void __launch_bounds__(1024, 8) nufft_adj_kernel(NufftArgs a, const float2* __restrict__ Rh,
+                                                        float2* __restrict__ X) {
   extern __shared__ float4 smem4[];
-  __shared__ float kc[J * (KBD + 1)];
-  float2* grid = reinterpret_cast<float2*>(smem4);
-  float2* us = grid + a.K;
-  int* bm = reinterpret_cast<int*>(us + a.Mk);
-  float* xm = reinterpret_cast<float*>(bm + a.Mk);
+  __shared__ float kc[J * KBH];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int col = blockIdx.x;
   const int lat = col % a.Nlat;
   const int K = a.K, Mk = a.Mk, Nz = a.Nz, nc = a.nc;
+  float2* twl = reinterpret_cast<float2*>(smem4);
+  float2* region = twl + fft_tw_entries(a.fK);
+  float2* grid = region;                    // after the gather
+  float2* us = region;                      // before: [Mk] samples
+  float* xm = reinterpret_cast<float*>(us + Mk);
+  short* bm = reinterpret_cast<short*>(xm + Mk);
+  short* first = bm + Mk;                   // [K] first contributing sample of each cell
 
-  for (int i = tid; i < J * (KBD + 1); i += nthr) kc[i] = a.kbc[i];
+  stage_twiddles(twl, a.twK, a.fK, tid, nthr);
+  for (int i = tid; i < J * KBH; i += nthr) kc[i] = a.kbc[i];
   const double q2 = a.q2[lat];
   const float bq = a.beam[lat];
   const float2* __restrict__ rin = Rh + (int64_t)col * Mk;
@@ -115,11 +159,11 @@ __global__ void __launch_bounds__(1024) nufft_adj_kernel(NufftArgs a, const floa
       const double beta = sqrt(arg);
       const double t = a.ct * beta;
       const double fl = floor(t);
-      bm[m] = (int)fl;
+      bm[m] = (short)(int)fl;               // t < 32000 (checked at plan creation)
       xm[m] = (float)(2.0 * (t - fl) - 1.0);
       us[m] = cmul(cconj(filter_h(a, m, bq, beta)), rin[m]);
     } else {
-      bm[m] = EVANESCENT;
+      bm[m] = EVANESCENT16;
       xm[m] = 0.f;
       us[m] = make_float2(0.f, 0.f);
     }
@@ -130,7 +174,7 @@ __global__ void __launch_bounds__(1024) nufft_adj_kernel(NufftArgs a, const floa
   int lo = 0, hi = Mk;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (bm[mid] == EVANESCENT) lo = mid + 1; else hi = mid;
+    if (bm[mid] == EVANESCENT16) lo = mid + 1; else hi = mid;
   }
   const int mf = lo;
   int umin = 0, umax = -1;
@@ -140,44 +184,70 @@ __global__ void __launch_bounds__(1024) nufft_adj_kernel(NufftArgs a, const floa
   }
   const int span = umax - umin + 1;
   const int nph = span > K ? (span + K - 1) / K : 1;
-  const double q2c = q2;
+  // One phase (the usual case): the first contributor of cell u is the
+  // smallest m with bm[m] >= u - J/2, i.e. sample m is first exactly for
+  // u in (bm[m-1] + J/2, bm[m] + J/2]; scatter those ranges (they partition
+  // the cells, so every entry is written once).
+  if (nph == 1) {
+    for (int m = mf + tid; m < Mk; m += nthr) {
+      const int ulo = (m == mf) ? umin : bm[m - 1] + J / 2 + 1;
+      const int uhi = bm[m] + J / 2;
+      for (int u = ulo; u <= uhi; ++u) first[u - umin] = (short)m;
+    }
+    __syncthreads();
+  }
+  // thread's cells: u = umin + tid + i nthr (+ ph K), i < ADJ_MAXC; grid cell u mod K
+  float2 acc[ADJ_MAXC];
+#pragma unroll
+  for (int i = 0; i < ADJ_MAXC; ++i) acc[i] = make_float2(0.f, 0.f);
   for (int ph = 0; ph < nph; ++ph) {
     const int pbeg = umin + ph * K;
     int pend = pbeg + K;
     if (ph > 0) pend = min(pend, umax + 1);
-    // consecutive lanes take consecutive cells, so their samples are
-    // consecutive too (conflict-free LDS reads)
-    for (int u = pbeg + tid; u < pend; u += nthr) {
-      const int key = u - J / 2;   // first contributor: smallest m with bm[m] >= key
-      int p = mf;
-      if (mf < Mk) {
-        // invert t = ct sqrt(4 k^2 - q^2) for the starting sample, then walk
-        // to the exact boundary on the stored base cells
-        const double bta = fmax((double)key, 0.0) / a.ct;
-        const double km = 0.5 * sqrt(bta * bta + q2c);
-        double mstar = floor((km - a.k_min) / a.dk);
-        mstar = fmin(fmax(mstar, (double)mf), (double)Mk);
-        p = (int)mstar;
-        while (p > mf && bm[p - 1] >= key) --p;
-        while (p < Mk && bm[p] < key) ++p;
+#pragma unroll
+    for (int i = 0; i < ADJ_MAXC; ++i) {
+      const int u = pbeg + tid + i * nthr;
+      if (u < pend) {
+        const int key = u - J / 2;   // first contributor: smallest m with bm[m] >= key
+        int p = mf;
+        if (nph == 1) {
+          p = (u <= umax) ? (int)first[u - umin] : Mk;   // cells past umax have no samples
+        } else if (mf < Mk) {
+          // invert t = ct sqrt(4 k^2 - q^2) for the starting sample, then walk
+          // to the exact boundary on the stored base cells
+          const double bta = fmax((double)key, 0.0) / a.ct;
+          const double km = 0.5 * sqrt(bta * bta + q2);
+          double mstar = floor((km - a.k_min) / a.dk);
+          mstar = fmin(fmax(mstar, (double)mf), (double)Mk);
+          p = (int)mstar;
+          while (p > mf && bm[p - 1] >= key) --p;
+          while (p < Mk && bm[p] < key) ++p;
+        }
+        float2 s = acc[i];
+        for (int m = p; m < Mk && bm[m] <= u + J / 2 - 1; ++m) {
+          const int j = u - (bm[m] - J / 2 + 1);
+          const float w = kb_tap<J>(kc, j, xm[m]);
+          const float2 uv = us[m];
+          s.x = fmaf(w, uv.x, s.x);
+          s.y = fmaf(w, uv.y, s.y);
+        }
+        acc[i] = s;
       }
-      float2 acc = make_float2(0.f, 0.f);
-      for (int m = p; m < Mk && bm[m] <= u + J / 2 - 1; ++m) {
-        const int j = u - (bm[m] - J / 2 + 1);
-        const float w = kb_poly(kc + j * (KBD + 1), xm[m]);
-        const float2 uv = us[m];
-        acc.x = fmaf(w, uv.x, acc.x);
-        acc.y = fmaf(w, uv.y, acc.y);
-      }
+    }
+  }
+  __syncthreads();   // sample arrays are dead from here: the grid takes their place
+#pragma unroll
+  for (int i = 0; i < ADJ_MAXC; ++i) {
+    const int u = umin + tid + i * nthr;
+    if (tid + i * nthr < K) {
       int g = u % K;
       if (g < 0) g += K;
-      if (ph == 0) grid[g] = acc;
-      else grid[g] = cadd(grid[g], acc);
+      grid[g] = acc[i];
     }
-    __syncthreads();
   }
+  __syncthreads();
 
-  fft_rows<R7, true>(grid, 1, K, a.fK, a.twK, tid, nthr);
+  fft_rows<R7, true>(grid, 1, K, a.fK, twl, tid, nthr);
   float2* __restrict__ dst = X + (int64_t)col * Nz;
   for (int n = tid; n < Nz; n += nthr) {
     int idx = n - nc;
@@ -186,24 +256,35 @@ __global__ void __launch_bounds__(1024) nufft_adj_kernel(NufftArgs a, const floa
   }
 }
 
-int nufft_threads(const NufftArgs& a) {
+// Threads per column: enough for the FFT stages, and wide enough that the
+// per-column work is short (the column count of a B-scan is only ~1000).
+int nufft_threads(const NufftArgs& a, int want) {
   const int bf = a.K / a.fK.min_radix;
   const int mb = fft_maxb(a.fK);
   int nt = 256;
-  while (nt < 1024 && bf > mb * nt) nt <<= 1;
+  while (nt < 1024 && (bf > mb * nt || nt < want)) nt <<= 1;
   return nt;
 }
 
 }  // namespace
 
 size_t nufft_adj_lds_bytes(const NufftArgs& a) {
-  return (size_t)a.K * sizeof(float2) + (size_t)a.Mk * (sizeof(float2) + sizeof(int) + sizeof(float));
+  const size_t samples = (size_t)a.Mk * (sizeof(float2) + sizeof(float) + sizeof(short)) + (size_t)a.K * sizeof(short);
+  const size_t grid = (size_t)a.K * sizeof(float2);
+  return (size_t)fft_tw_entries(a.fK) * sizeof(float2) + (samples > grid ? samples : grid);
+}
+
+int nufft_adj_threads(const NufftArgs& a) {
+  // every thread keeps at most ADJ_MAXC grid cells in registers
+  int nt = nufft_threads(a, 512);
+  while (nt < 1024 && (a.K + nt - 1) / nt > ADJ_MAXC) nt <<= 1;
+  return nt;
 }
 
 template <int J, bool R7>
 hipError_t nufft_fwd_t(const NufftArgs& a, const float2* X1, float2* W, hipStream_t s) {
-  const size_t lds = (size_t)a.K * sizeof(float2);
-  hipLaunchKernelGGL((nufft_fwd_kernel<J, R7>), dim3(a.n_cols), dim3(nufft_threads(a)), lds, s, a, X1, W);
+  const size_t lds = ((size_t)a.K + fft_tw_entries(a.fK)) * sizeof(float2);
+  hipLaunchKernelGGL((nufft_fwd_kernel<J, R7>), dim3(a.n_cols), dim3(nufft_threads(a, 256)), lds, s, a, X1, W);
   return hipGetLastError();
 }
 
@@ -227,7 +308,7 @@ hipError_t nufft_adj_t(const NufftArgs& a, const float2* Rh, float2* X, hipStrea
       done = true;
     }
   }
-  hipLaunchKernelGGL((nufft_adj_kernel<J, R7>), dim3(a.n_cols), dim3(nufft_threads(a)), lds, s, a, Rh, X);
+  hipLaunchKernelGGL((nufft_adj_kernel<J, R7>), dim3(a.n_cols), dim3(nufft_adj_threads(a)), lds, s, a, Rh, X);
   return hipGetLastError();
 }
 

@@ -461,6 +461,7 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   }
   for (int k = 0; k < a.n_inner; ++k) {
     const float mom = a.mom[k];
+    const float mom1 = 1.f + mom;
     xr[w][lane] = rl[TV_S - 1];
     __syncthreads();
     float2 d[TV_S];
@@ -475,18 +476,19 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < TV_S; ++s) {
+      // momentum r = (1 + mom) q - mom p: the old dual is consumed first, so
+      // the new one can take its registers (no loop-carried copies)
+      const float2 mpz = cscale(pz[s], mom), mpl = cscale(pl[s], mom);
       const float2 dl = (s < TV_S - 1) ? d[s + 1] : (w < TV_WAVES - 1 ? xd[w + 1][lane] : make_float2(0.f, 0.f));
       float2 qz = make_float2(fmaf(sz, lane_next(d[s].x) - d[s].x, rz[s].x),
                               fmaf(sz, lane_next(d[s].y) - d[s].y, rz[s].y));
       float2 ql = make_float2(fmaf(sl[s], dl.x - d[s].x, rl[s].x), fmaf(sl[s], dl.y - d[s].y, rl[s].y));
       const float m2 = qz.x * qz.x + qz.y * qz.y + ql.x * ql.x + ql.y * ql.y;
       const float sc = m2 > 1.f ? rsqrtf(m2) : 1.f;
-      qz = cscale(qz, sc);
-      ql = cscale(ql, sc);
-      rz[s] = make_float2(fmaf(mom, qz.x - pz[s].x, qz.x), fmaf(mom, qz.y - pz[s].y, qz.y));
-      rl[s] = make_float2(fmaf(mom, ql.x - pl[s].x, ql.x), fmaf(mom, ql.y - pl[s].y, ql.y));
-      pz[s] = qz;
-      pl[s] = ql;
+      pz[s] = cscale(qz, sc);
+      pl[s] = cscale(ql, sc);
+      rz[s] = make_float2(fmaf(mom1, pz[s].x, -mpz.x), fmaf(mom1, pz[s].y, -mpz.y));
+      rl[s] = make_float2(fmaf(mom1, pl[s].x, -mpl.x), fmaf(mom1, pl[s].y, -mpl.y));
     }
   }
   // z = v + tau div p
