@@ -125,6 +125,78 @@ def cpu_baseline(pr, x_true, mask, noise, iters: int) -> dict:
                       f"{os.cpu_count()} visible host cores"}
 
 
+def serving_bench(n_req: int, seed: int = 4) -> dict:
+    """Serving mix (60% B-scans 1024-2048 px x 256-2000 A-scans, 30% volumes
+    1024 x 64^2..128^2, 10% 512 x 64 B-scans; random penalty, 50-100
+    iterations): sequential solves vs the continuous-batching server, closed
+    loop and Poisson arrivals at 0.8x the sequential rate."""
+    import numpy as np
+    import torch
+    import paper_2108_01438_amd as P
+    import synth
+    from paper_2108_01438_amd.serve import HipExecutor, Request, Server, run_sequential
+    rng = np.random.default_rng(seed)
+    mix = synth.serving_mix(rng, n_req)
+    reqs, Lcache = [], {}
+    for spec in mix:
+        r = np.random.default_rng(spec["seed"])
+        geo = dict(synth.OPTICS)
+        geo.update(spec["geom"])
+        g = P.Geometry.from_dict(geo)
+        plan = P.Plan(g)
+        x = synth.scatterers(r, g.img_shape, 20).astype(np.complex64)
+        y = plan.forward(torch.from_numpy(x).cuda())
+        y = (y + 0.01 * float(y.abs().max().item()) * torch.randn_like(y)).contiguous()
+        lam = spec["lam"] * float(plan.adjoint(y).abs().max().item())
+        key = tuple(sorted(spec["geom"].items()))
+        if key not in Lcache:
+            Lcache[key] = plan.lipschitz(50)
+        plan.close()
+        reqs.append(Request(geom=g, y=y.cpu().numpy(), penalty=spec["pen"], lam=lam, iters=spec["iters"],
+                            delta=1.0 / (1.05 * Lcache[key])))
+    print(f"[serving] {n_req} requests ready", file=sys.stderr, flush=True)
+    ex1 = HipExecutor(slots=1)
+    run_sequential(ex1, reqs[:2])               # plan and code warm-up
+    alone, t_seq = run_sequential(ex1, reqs)
+    ex1.shutdown()
+    C = n_req / t_seq
+    print(f"[serving] sequential {C:.2f} solves/s", file=sys.stderr, flush=True)
+    budget = 96 << 30
+    srv = Server(HipExecutor(slots=8), mem_budget=budget, slots=8)
+    t0 = time.perf_counter()
+    futs = [srv.submit(r) for r in reqs]
+    mix_out = [f.result(timeout=600) for f in futs]
+    t_closed = time.perf_counter() - t0
+    srv.close()
+    mism = sum(int(not np.array_equal(a.view(np.uint32), b.view(np.uint32))) for a, b in zip(alone, mix_out))
+    closed = srv.latency_stats()
+    print(f"[serving] closed loop {n_req / t_closed:.2f} solves/s", file=sys.stderr, flush=True)
+    rate = 0.8 * C
+    arr = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    srv = Server(HipExecutor(slots=8), mem_budget=budget, slots=8)
+    t0 = time.perf_counter()
+    futs = []
+    for r, ta in zip(reqs, arr):
+        dt = t0 + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        futs.append(srv.submit(r))
+    for f in futs:
+        f.result(timeout=600)
+    t_pois = time.perf_counter() - t0
+    srv.close()
+    pst = srv.latency_stats()
+    return {"metric": "serving solves/s with p50/p99 latency (continuous batching vs sequential solves)",
+            "requests": n_req, "sequential_solves_per_s": round(C, 3),
+            "closed_loop_solves_per_s": round(n_req / t_closed, 3),
+            "closed_loop_gain": round((n_req / t_closed) / C, 3),
+            "closed_loop_p50_ms": round(closed["p50_s"] * 1e3, 2), "closed_loop_p99_ms": round(closed["p99_s"] * 1e3, 2),
+            "poisson_rate_solves_per_s": round(rate, 3), "poisson_solves_per_s": round(n_req / t_pois, 3),
+            "poisson_p50_ms": round(pst["p50_s"] * 1e3, 2), "poisson_p99_ms": round(pst["p99_s"] * 1e3, 2),
+            "sequential_mean_ms": round(t_seq / n_req * 1e3, 2),
+            "alone_vs_mix_bitwise_mismatches": mism, "slots": 8, "mem_budget_GiB": budget >> 30}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +205,8 @@ def main() -> int:
     ap.add_argument("--stage-reps", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="only run the serving benchmark with this many requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (counter calibration)")
     args = ap.parse_args()
@@ -145,6 +219,11 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}))
+        return 0
+    if args.serving > 0:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(serving_bench(args.serving)), flush=True)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

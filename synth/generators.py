@@ -14,7 +14,7 @@ import numpy as np
 
 __all__ = [
     "OPTICS", "PRESETS", "preset", "complex_normal", "standard_normal",
-    "scatterers", "layers", "random_field", "mask_ones", "mask_random_exact",
+    "scatterers", "layers", "random_field", "smooth_field_coarse", "mask_ones", "mask_random_exact",
     "mask_bernoulli", "mask_equispaced", "mask_partial", "noisy", "is_smooth7",
     "serving_mix",
 ]
@@ -103,6 +103,20 @@ def random_field(rng: np.random.Generator, shape, sigma_px: float, rms: float) -
     from scipy.ndimage import gaussian_filter
     w = complex_normal(rng, shape)
     f = gaussian_filter(w.real, sigma_px, mode="wrap") + 1j * gaussian_filter(w.imag, sigma_px, mode="wrap")
+    return f * (rms / np.sqrt(np.mean(np.abs(f) ** 2)))
+
+
+def smooth_field_coarse(rng: np.random.Generator, shape, factor: int, rms: float) -> np.ndarray:
+    """Smooth complex random field for large volumes: CN(0,1) on a grid
+    `factor` times coarser along every axis, linearly upsampled, rescaled
+    to the given RMS amplitude."""
+    from scipy.ndimage import zoom
+    shape = tuple(shape)
+    coarse = tuple(max(2, s // factor) for s in shape)
+    w = complex_normal(rng, coarse)
+    zf = [s / c for s, c in zip(shape, coarse)]
+    f = zoom(w.real, zf, order=1) + 1j * zoom(w.imag, zf, order=1)
+    f = f[tuple(slice(0, s) for s in shape)]
     return f * (rms / np.sqrt(np.mean(np.abs(f) ** 2)))
 
 
