@@ -139,23 +139,25 @@ bool factorize(int n, FftDesc& d) {
   return true;
 }
 
-// Two-level twiddle table of FftDesc: lo[j] = w^j (j < B), hi[h] = w^{h B}.
+// Per-stage twiddle rows of FftDesc (layout in oct_common.h), built in FP64.
 std::vector<float2> twiddles(FftDesc& d) {
-  const int n = d.n;
-  int lb = 0;
-  while ((1 << lb) * (1 << lb) < n) ++lb;   // B = 2^lb >= sqrt(n)
-  d.tw_log2b = lb;
-  const int B = 1 << lb;
-  d.tw_nhi = (n + B - 1) / B;
-  std::vector<float2> t(B + d.tw_nhi);
-  for (int j = 0; j < B; ++j) {
-    const double a = -2.0 * kPi * (double)j / (double)n;
-    t[j] = make_float2((float)std::cos(a), (float)std::sin(a));
+  std::vector<float2> t;
+  for (int s = 0; s < d.nstages; ++s) {
+    const int R = d.radix[s], Ns = d.ns[s], P = fft_tw_pad(R);
+    d.tw_off[s] = (int)t.size();
+    if (Ns == 1) continue;   // first stage: all factors are 1
+    for (int k = 0; k < Ns; ++k)
+      for (int r = 1; r <= P; ++r) {
+        float2 w = make_float2(0.f, 0.f);
+        if (r < R) {
+          const double a = -2.0 * kPi * (double)(r * k) / (double)(Ns * R);
+          w = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+        t.push_back(w);
+      }
   }
-  for (int h = 0; h < d.tw_nhi; ++h) {
-    const double a = -2.0 * kPi * (double)((int64_t)h * B) / (double)n;
-    t[B + h] = make_float2((float)std::cos(a), (float)std::sin(a));
-  }
+  d.tw_total = (int)t.size();
+  if (t.empty()) t.push_back(make_float2(0.f, 0.f));   // keep the device table non-empty
   return t;
 }
 
@@ -247,8 +249,15 @@ oct_status unsupported_sizes(const oct_geometry* g) {
   if (g->lateral_dims == 2 && (g->n_y > 4096 || !factorize((int)g->n_y, d)))
     return fail(OCT_E_UNSUPPORTED, "n_y must be 7-smooth and <= 4096");
   if (g->n_k > 8192) return fail(OCT_E_UNSUPPORTED, "n_k > 8192");
-  // adjoint column kernel keeps the grid, the samples and the twiddles in LDS
-  const size_t lds = (size_t)K * 8 + (size_t)g->n_k * 14 + 8 * 512;
+  // every FFT stage must fit the butterflies-per-thread limit of a 1024-thread block
+  for (int64_t n : {K, g->n_x, g->lateral_dims == 2 ? g->n_y : (int64_t)1}) {
+    FftDesc f;
+    factorize((int)n, f);
+    if (f.nstages > 0 && n / f.min_radix > (int64_t)fft_maxb(f) * 1024)
+      return fail(OCT_E_UNSUPPORTED, "transform length has too many radix-2/3 butterflies per stage");
+  }
+  // adjoint column kernel keeps the grid or the samples in LDS
+  const size_t lds = (size_t)K * 8 + (size_t)g->n_k * 14 + 4096;
   if (lds > 160 * 1024 - 4096) return fail(OCT_E_UNSUPPORTED, "grid + samples exceed the LDS of one CU");
   // base cells of one column are stored as 16-bit offsets: bound the span of t
   const double dk = (g->k_max - g->k_min) / (double)(g->n_k - 1);

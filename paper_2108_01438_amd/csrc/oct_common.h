@@ -42,14 +42,28 @@ struct FftDesc {
   FastDiv div_nb[OCT_MAX_STAGES];  // by n / radix (butterflies per row)
   FastDiv div_ns[OCT_MAX_STAGES];  // by ns
   int min_radix;
-  // twiddles w^e = e^{-2 pi i e / n} as lo[e mod B] * hi[e div B], B = 2^tw_log2b:
-  // the table holds lo (B entries) then hi (tw_nhi entries)
-  int tw_log2b;
-  int tw_nhi;
+  // Per-stage twiddle rows: stage s (radix R, sub-transform size Ns > 1) owns
+  // Ns rows of fft_tw_pad(R) entries at tw_off[s]; row k holds
+  // e^{-2 pi i r k / (Ns R)} for r = 1..R-1, zero-padded to an even count.
+  int tw_off[OCT_MAX_STAGES];
+  int tw_total;
 };
 
-// entries of the two-level twiddle table of a transform
-__host__ __device__ inline int fft_tw_entries(const FftDesc& d) { return (1 << d.tw_log2b) + d.tw_nhi; }
+// entries per twiddle row of a radix-R stage: R - 1 rounded up to even (16-byte rows)
+__host__ __device__ constexpr int fft_tw_pad(int R) { return R & ~1; }
+
+// butterflies per thread the kernels may use for a transform of this shape
+inline int fft_maxb(const FftDesc& d) {
+  for (int s = 0; s < d.nstages; ++s)
+    if (d.radix[s] == 7) return 1;
+  return 2;
+}
+inline bool fft_has7(const FftDesc& d) { return fft_maxb(d) == 1; }
+// the one-butterfly variant serves radix 7 and every launch whose threads
+// cover a stage of the narrowest radix
+inline bool fft_one(const FftDesc& d, int64_t rows, int nthr) {
+  return fft_has7(d) || rows * (d.n / d.min_radix) <= nthr;
+}
 
 // Lines of a lateral transform.  Element (line o, lateral index l, row i) of a
 // [.. ][lateral][rows] array lives at base(o) + l * es + i, with
@@ -77,7 +91,7 @@ enum LatMode {
 struct LatArgs {
   LineGeom lg;
   FftDesc fd;
-  const float2* tw;      // two-level twiddle table of the lateral transform
+  const float2* tw;      // per-stage twiddle rows of the lateral transform
   int T;                 // rows per tile (a power of two)
   int log2T;
   int n_tiles;

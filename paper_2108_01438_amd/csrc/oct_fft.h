@@ -8,9 +8,11 @@
 // The transform runs in place in one LDS buffer: every thread first pulls
 // all of its butterflies into registers, a barrier separates the reads from
 // the writes, so the per-stage work must fit MAXB butterflies per thread.
-// Twiddles w^e = e^{-2 pi i e / n} come from a two-level table held in LDS,
-// lo[e mod B] * hi[e div B] (both FP64-built, rounded to FP32), which the
-// kernel stages next to its data.
+// Twiddles come from per-stage rows in global memory (FP64-built, rounded
+// once to FP32): row k of a stage holds w^{r k} for r = 1..R-1, so a
+// butterfly fetches its R-1 factors with 16-byte loads through the vector
+// cache, issued before the stage's LDS reads so that their latency overlaps
+// the barrier.
 #pragma once
 #include "oct_common.h"
 
@@ -163,38 +165,35 @@ template <bool INV> struct Dft<5, INV> : DftOdd<5, INV> {};
 template <bool INV> struct Dft<7, INV> : DftOdd<7, INV> {};
 
 // One Stockham stage over `nrows` transforms of length n stored at
-// buf[row * rowstride + i].
-__device__ __forceinline__ float2 twiddle(const float2* tw, int lb, int e) {
-  return cmul(tw[e & ((1 << lb) - 1)], tw[(1 << lb) + (e >> lb)]);
-}
-
-// Copy the two-level twiddle table of a transform into LDS.
-__device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __restrict__ src, const FftDesc& d,
-                                               int tid, int nthr) {
-  const int n = (1 << d.tw_log2b) + d.tw_nhi;
-  for (int i = tid; i < n; i += nthr) dst[i] = src[i];
-}
-
+// buf[row * rowstride + i]; tw: this stage's twiddle rows (global memory).
 template <int R, int MAXB, bool INV>
 __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride, int n, int Ns,
-                                          const FastDiv& dnb, const FastDiv& dns, int lb,
-                                          const float2* tw, int tid, int nthr) {
+                                          const FastDiv& dnb, const FastDiv& dns,
+                                          const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr int NQ = fft_tw_pad(R) / 2;   // 16-byte loads per butterfly
   const int nb = n / R;
   const int total = nrows * nb;
-  const int tws = n / (Ns * R);
   float2 v[MAXB][R];
-  int off[MAXB], jj[MAXB];
+  float4 wq[MAXB][NQ];
+  int off[MAXB], jj[MAXB], kk[MAXB];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int item = tid + b * nthr;
     if (item < total) {
       const int row = (int)fdiv((uint32_t)item, dnb);
       const int j = item - row * nb;
+      const int k = j - (int)fdiv((uint32_t)j, dns) * Ns;
+      if (Ns > 1) {
+        const float4* tp = reinterpret_cast<const float4*>(tw) + k * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) wq[b][q] = tp[q];
+      }
       const float2* src = buf + row * rowstride + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = src[r * nb];
       off[b] = row * rowstride;
       jj[b] = j;
+      kk[b] = k;
     }
   }
   __syncthreads();
@@ -202,12 +201,12 @@ __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride,
   for (int b = 0; b < MAXB; ++b) {
     const int item = tid + b * nthr;
     if (item < total) {
-      const int j = jj[b];
-      const int k = j - (int)fdiv((uint32_t)j, dns) * Ns;
+      const int j = jj[b], k = kk[b];
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = twiddle(tw, lb, r * k * tws);
+          const float4 q = wq[b][(r - 1) >> 1];
+          float2 w = ((r - 1) & 1) ? make_float2(q.z, q.w) : make_float2(q.x, q.y);
           if (INV) w.y = -w.y;
           v[b][r] = cmul(v[b][r], w);
         }
@@ -222,37 +221,30 @@ __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride,
 }
 
 // Full transform of `nrows` rows in LDS; all threads of the block participate.
-// R7 selects the code path with radix-7 stages (compiled separately: its
-// register footprint is larger, so it runs one butterfly per thread).
-template <bool R7>
+// ONE selects the variant with one butterfly per thread and stage, which
+// also carries the radix-7 stages (their register footprint is larger); the
+// other variant runs up to two butterflies per thread.
+template <bool ONE>
 struct FftCfg {
-  static constexpr int MAXB = R7 ? 1 : 2;
+  static constexpr int MAXB = ONE ? 1 : 2;
 };
 
-// tw: the LDS copy of the transform's two-level twiddle table.
-template <bool R7, bool INV>
+template <bool ONE, bool INV>
 __device__ __forceinline__ void fft_rows(float2* buf, int nrows, int rowstride, const FftDesc& d,
-                                         const float2* tw, int tid, int nthr) {
-  constexpr int MB = FftCfg<R7>::MAXB;
+                                         const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr int MB = FftCfg<ONE>::MAXB;
   for (int s = 0; s < d.nstages; ++s) {
     const int Ns = d.ns[s];
+    const float2* t = tw + d.tw_off[s];
     switch (d.radix[s]) {
-      case 8: fft_stage<8, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
-      case 4: fft_stage<4, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
-      case 2: fft_stage<2, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
-      case 5: fft_stage<5, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
-      case 3: fft_stage<3, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr); break;
+      case 8: fft_stage<8, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr); break;
+      case 4: fft_stage<4, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr); break;
+      case 2: fft_stage<2, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr); break;
+      case 5: fft_stage<5, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr); break;
+      case 3: fft_stage<3, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr); break;
       default:
-        if (R7) fft_stage<7, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], d.tw_log2b, tw, tid, nthr);
+        if (ONE) fft_stage<7, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr);
         break;
     }
   }
 }
-
-// butterflies per thread the kernels may use for a transform of this shape
-inline int fft_maxb(const FftDesc& d) {
-  for (int s = 0; s < d.nstages; ++s)
-    if (d.radix[s] == 7) return 1;
-  return 2;
-}
-inline bool fft_has7(const FftDesc& d) { return fft_maxb(d) == 1; }

@@ -34,7 +34,38 @@ __device__ double block_sum_d(double v, double* sh) {
   return s;
 }
 
-template <int MODE, bool R7>
+// Real-part pairing.  Only Re ifft(W) of a spectrum row W is ever used, and
+// Re ifft(W) = ifft(W_h) with the Hermitian part W_h(q) = (W(q) + conj W(-q)) / 2.
+// Row p (p < H = T/2) is replaced by W_h[p] + j W_h[p + H], so one complex
+// inverse transform yields the real parts of two rows (in .x and .y).
+__device__ __forceinline__ void pack_real_pairs(float2* lds, int H, int rs, int L, int tid, int nthr) {
+  const int hl = L / 2 + 1;
+  for (int p = 0; p < H; ++p) {
+    float2* ra = lds + p * rs;
+    const float2* rb = lds + (p + H) * rs;
+    for (int q = tid; q < hl; q += nthr) {
+      const int mq = q == 0 ? 0 : L - q;
+      const float2 a0 = ra[q], a1 = ra[mq], b0 = rb[q], b1 = rb[mq];
+      const float2 ha = make_float2(0.5f * (a0.x + a1.x), 0.5f * (a0.y - a1.y));   // W_h[p](q)
+      const float2 hb = make_float2(0.5f * (b0.x + b1.x), 0.5f * (b0.y - b1.y));   // W_h[p+H](q)
+      ra[q] = make_float2(ha.x - hb.y, ha.y + hb.x);
+      ra[mq] = make_float2(ha.x + hb.y, hb.x - ha.y);   // conj ha + j conj hb
+    }
+  }
+}
+
+// After a forward transform of rows holding r_p + j r_{p+H} (both real), the
+// spectrum of tile row t: Z = fft(row t mod H), R_p = (Z(q) + conj Z(-q)) / 2,
+// R_{p+H} = (Z(q) - conj Z(-q)) / 2j.
+__device__ __forceinline__ float2 unpack_real_pair(const float2* lds, int rs, int L, int H, int t, int l) {
+  const bool second = t >= H;
+  const float2* row = lds + (second ? t - H : t) * rs;
+  const float2 z0 = row[l], z1 = row[l == 0 ? 0 : L - l];
+  return second ? make_float2(0.5f * (z0.y + z1.y), 0.5f * (z1.x - z0.x))
+                : make_float2(0.5f * (z0.x + z1.x), 0.5f * (z0.y - z1.y));
+}
+
+template <int MODE, bool ONE>
 __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   extern __shared__ float2 lds[];
   __shared__ double red[16];
@@ -55,10 +86,28 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   const int latb = (line % lg.lat_lines) * L;
   const int n = L * T;
 
-  float2* twl = lds + T * rs;   // twiddle table after the tile
-  stage_twiddles(twl, a.tw, a.fd, tid, nthr);
+  const float2* __restrict__ twl = a.tw;
+  // modes that need only real parts (or transform real rows) pair rows p and p + H
+  constexpr bool REAL_PAIRS = MODE == LAT_FWD_MEAS || MODE == LAT_ADJ_MEAS || MODE == LAT_NORMAL;
+  const bool pair = REAL_PAIRS && T >= 2;
+  const int H = T >> 1;
+  const int nrow_t = pair ? H : T;   // rows that go through the transforms
+
   // ---- load the tile: element (row t, lateral l) -> lds[t * rs + l]
-  for (int idx = tid; idx < n; idx += nthr) {
+  if (MODE == LAT_ADJ_MEAS && pair) {
+    // real rows straight into the packed layout: row t -> component t >= H of row t mod H
+    float* ldsf = reinterpret_cast<float*>(lds);
+    for (int idx = tid; idx < n; idx += nthr) {
+      const int l = idx >> a.log2T;
+      const int t = idx & (T - 1);
+      float r = 0.f;
+      if (t < nr) {
+        r = a.srcf[base + (int64_t)l * lg.es + t];
+        if (a.mask && !mask_bit(a.mask, a.mask_words, latb + l, r0 + t)) r = 0.f;
+      }
+      ldsf[2 * ((t < H ? t : t - H) * rs + l) + (t < H ? 0 : 1)] = r;
+    }
+  } else for (int idx = tid; idx < n; idx += nthr) {
     const int l = idx >> a.log2T;
     const int t = idx & (T - 1);
     float2 v = make_float2(0.f, 0.f);
@@ -78,14 +127,21 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     lds[t * rs + l] = v;
   }
   __syncthreads();
+  if ((MODE == LAT_FWD_MEAS || MODE == LAT_NORMAL) && pair) {
+    pack_real_pairs(lds, H, rs, L, tid, nthr);
+    __syncthreads();
+  }
 
-  if (a.inverse) fft_rows<R7, true>(lds, T, rs, a.fd, twl, tid, nthr);
-  else fft_rows<R7, false>(lds, T, rs, a.fd, twl, tid, nthr);
+  if (a.inverse) fft_rows<ONE, true>(lds, nrow_t, rs, a.fd, twl, tid, nthr);
+  else fft_rows<ONE, false>(lds, nrow_t, rs, a.fd, twl, tid, nthr);
 
   if (MODE == LAT_FFT || MODE == LAT_ADJ_MEAS) {
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx >> a.log2T, t = idx & (T - 1);
-      if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale);
+      if (t < nr) {
+        const float2 v = (MODE == LAT_ADJ_MEAS && pair) ? unpack_real_pair(lds, rs, L, H, t, l) : lds[t * rs + l];
+        a.dst[base + (int64_t)l * lg.es + t] = cscale(v, a.scale);
+      }
     }
     return;
   }
@@ -93,7 +149,8 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) {
-        float yv = lds[t * rs + l].x * a.scale;
+        const float re = !pair ? lds[t * rs + l].x : (t < H ? lds[t * rs + l].x : lds[(t - H) * rs + l].y);
+        float yv = re * a.scale;
         if (a.mask && !mask_bit(a.mask, a.mask_words, latb + l, r0 + t)) yv = 0.f;
         a.dstf[base + (int64_t)l * lg.es + t] = yv;
       }
@@ -113,6 +170,33 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     }
     return;
   }
+  if (MODE == LAT_NORMAL && pair) {
+    // residual of rows p and p + H from the real and imaginary parts of row p
+    double acc = 0.0;
+    const int log2H = a.log2T - 1;
+    for (int idx = tid; idx < (n >> 1); idx += nthr) {
+      const int l = idx >> log2H, p = idx & (H - 1);
+      const float2 vv = lds[p * rs + l];
+      float ra = 0.f, rb = 0.f;
+      const int64_t off = base + (int64_t)l * lg.es + p;
+      if (p < nr && (!a.mask || mask_bit(a.mask, a.mask_words, latb + l, r0 + p)))
+        ra = vv.x * a.scale - (a.y ? a.y[off] : 0.f);
+      if (p + H < nr && (!a.mask || mask_bit(a.mask, a.mask_words, latb + l, r0 + p + H)))
+        rb = vv.y * a.scale - (a.y ? a.y[off + H] : 0.f);
+      acc += (double)ra * (double)ra;
+      acc += (double)rb * (double)rb;
+      lds[p * rs + l] = make_float2(ra, rb);
+    }
+    __syncthreads();
+    fft_rows<ONE, false>(lds, H, rs, a.fd, twl, tid, nthr);
+    for (int idx = tid; idx < n; idx += nthr) {
+      const int l = idx >> a.log2T, t = idx & (T - 1);
+      if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(unpack_real_pair(lds, rs, L, H, t, l), a.scale2);
+    }
+    const double s = block_sum_d(acc, red);
+    if (tid == 0 && a.partial) a.partial[bid] = s;
+    return;
+  }
   if (MODE == LAT_NORMAL) {
     double acc = 0.0;
     for (int idx = tid; idx < n; idx += nthr) {
@@ -127,7 +211,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       lds[t * rs + l] = make_float2(r, 0.f);
     }
     __syncthreads();
-    fft_rows<R7, false>(lds, T, rs, a.fd, twl, tid, nthr);
+    fft_rows<ONE, false>(lds, T, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
@@ -157,7 +241,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       lds[t * rs + l] = xn;
     }
     __syncthreads();
-    fft_rows<R7, false>(lds, T, rs, a.fd, twl, tid, nthr);
+    fft_rows<ONE, false>(lds, T, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx >> a.log2T, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = lds[t * rs + l];
@@ -175,7 +259,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
 int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* rowstride) {
   const int rs = (lg.L % 2 == 0) ? lg.L + 1 : lg.L;  // odd stride spreads LDS banks
   const int mb = fft_maxb(fd);
-  const int64_t budget = 65280 - 8 * (int64_t)fft_tw_entries(fd);   // tile + twiddles within 64 KB
+  const int64_t budget = 65280;   // tile within 64 KB
   int T = 32;
   while (T > 1 && (int64_t)T * rs * 8 > budget) T >>= 1;
   while (T > 1 && T > lg.rows) T >>= 1;
@@ -192,28 +276,27 @@ int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* row
   return 0;
 }
 
-template <bool R7>
-hipError_t launch_lateral_t(LatMode mode, const LatArgs& a, hipStream_t s) {
-  const size_t lds = ((size_t)a.T * a.rowstride + fft_tw_entries(a.fd)) * sizeof(float2);
+template <bool ONE>
+hipError_t launch_lateral_t(LatMode mode, const LatArgs& a, int nthr, hipStream_t s) {
+  const size_t lds = (size_t)a.T * a.rowstride * sizeof(float2);
   const int grid = a.lg.n_lines * a.n_tiles;
-  const int mb = FftCfg<R7>::MAXB;
-  int nthr = 256;
-  {
-    const int64_t bf = (int64_t)a.T * a.lg.L / a.fd.min_radix;
-    while (nthr < 1024 && bf > (int64_t)mb * nthr) nthr <<= 1;
-    if (bf > (int64_t)mb * nthr) return hipErrorInvalidConfiguration;
-  }
   switch (mode) {
-    case LAT_FFT: hipLaunchKernelGGL((lat_kernel<LAT_FFT, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_FWD_MEAS: hipLaunchKernelGGL((lat_kernel<LAT_FWD_MEAS, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_ADJ_MEAS: hipLaunchKernelGGL((lat_kernel<LAT_ADJ_MEAS, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_NORMAL: hipLaunchKernelGGL((lat_kernel<LAT_NORMAL, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_UPDATE: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_UPDATE_L1: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE_L1, R7>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_FFT: hipLaunchKernelGGL((lat_kernel<LAT_FFT, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_FWD_MEAS: hipLaunchKernelGGL((lat_kernel<LAT_FWD_MEAS, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_ADJ_MEAS: hipLaunchKernelGGL((lat_kernel<LAT_ADJ_MEAS, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_NORMAL: hipLaunchKernelGGL((lat_kernel<LAT_NORMAL, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_UPDATE: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_UPDATE_L1: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE_L1, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_lateral(LatMode mode, const LatArgs& a, hipStream_t s) {
-  return fft_has7(a.fd) ? launch_lateral_t<true>(mode, a, s) : launch_lateral_t<false>(mode, a, s);
+  const int64_t bf = (int64_t)a.T * (a.fd.n / a.fd.min_radix);
+  const int mb = fft_maxb(a.fd);
+  int nthr = 256;
+  while (nthr < 1024 && bf > (int64_t)mb * nthr) nthr <<= 1;
+  if (bf > (int64_t)mb * nthr) return hipErrorInvalidConfiguration;
+  return fft_one(a.fd, a.T, nthr) ? launch_lateral_t<true>(mode, a, nthr, s)
+                                  : launch_lateral_t<false>(mode, a, nthr, s);
 }

@@ -67,7 +67,7 @@ __device__ __forceinline__ float2 filter_h(const NufftArgs& a, int m, float bq, 
   return h;
 }
 
-template <int J, bool R7>
+template <int J, bool ONE>
 __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const float2* __restrict__ X1,
                                                          float2* __restrict__ W) {
   extern __shared__ float2 grid[];
@@ -76,8 +76,7 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
   const int lat = col % a.Nlat;
   const int K = a.K, Nz = a.Nz, nc = a.nc;
   const float2* __restrict__ src = X1 + (int64_t)col * Nz;
-  float2* twl = grid + K;
-  stage_twiddles(twl, a.twK, a.fK, tid, nthr);
+  const float2* __restrict__ twl = a.twK;
 
   // n' = n - n_c placed at n' mod K; cells [Nz - nc, K - nc) stay zero.
   for (int i = tid; i < K - Nz; i += nthr) grid[Nz - nc + i] = make_float2(0.f, 0.f);
@@ -87,7 +86,7 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
     grid[idx] = cscale(src[n], a.deap[n]);
   }
   __syncthreads();
-  fft_rows<R7, false>(grid, 1, K, a.fK, twl, tid, nthr);
+  fft_rows<ONE, false>(grid, 1, K, a.fK, twl, tid, nthr);
 
   const double q2 = a.q2[lat];
   const float bq = a.beam[lat];
@@ -131,8 +130,8 @@ constexpr short EVANESCENT16 = -32768;
 // region; each thread holds its cells in registers in between.
 constexpr int ADJ_MAXC = 8;   // grid cells per thread
 
-template <int J, bool R7>
-__global__ void __launch_bounds__(1024, 8) nufft_adj_kernel(NufftArgs a, const float2* __restrict__ Rh,
+template <int J, bool ONE>
+__global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs a, const float2* __restrict__ Rh,
                                                         float2* __restrict__ X) {
   extern __shared__ float4 smem4[];
   __shared__ float kc[J * KBH];
@@ -140,15 +139,14 @@ __global__ void __launch_bounds__(1024, 8) nufft_adj_kernel(NufftArgs a, const f
   const int col = blockIdx.x;
   const int lat = col % a.Nlat;
   const int K = a.K, Mk = a.Mk, Nz = a.Nz, nc = a.nc;
-  float2* twl = reinterpret_cast<float2*>(smem4);
-  float2* region = twl + fft_tw_entries(a.fK);
+  const float2* __restrict__ twl = a.twK;
+  float2* region = reinterpret_cast<float2*>(smem4);
   float2* grid = region;                    // after the gather
   float2* us = region;                      // before: [Mk] samples
   float* xm = reinterpret_cast<float*>(us + Mk);
   short* bm = reinterpret_cast<short*>(xm + Mk);
   short* first = bm + Mk;                   // [K] first contributing sample of each cell
 
-  stage_twiddles(twl, a.twK, a.fK, tid, nthr);
   for (int i = tid; i < J * KBH; i += nthr) kc[i] = a.kbc[i];
   const double q2 = a.q2[lat];
   const float bq = a.beam[lat];
@@ -247,7 +245,7 @@ __global__ void __launch_bounds__(1024, 8) nufft_adj_kernel(NufftArgs a, const f
   }
   __syncthreads();
 
-  fft_rows<R7, true>(grid, 1, K, a.fK, twl, tid, nthr);
+  fft_rows<ONE, true>(grid, 1, K, a.fK, twl, tid, nthr);
   float2* __restrict__ dst = X + (int64_t)col * Nz;
   for (int n = tid; n < Nz; n += nthr) {
     int idx = n - nc;
@@ -271,7 +269,7 @@ int nufft_threads(const NufftArgs& a, int want) {
 size_t nufft_adj_lds_bytes(const NufftArgs& a) {
   const size_t samples = (size_t)a.Mk * (sizeof(float2) + sizeof(float) + sizeof(short)) + (size_t)a.K * sizeof(short);
   const size_t grid = (size_t)a.K * sizeof(float2);
-  return (size_t)fft_tw_entries(a.fK) * sizeof(float2) + (samples > grid ? samples : grid);
+  return samples > grid ? samples : grid;
 }
 
 int nufft_adj_threads(const NufftArgs& a) {
@@ -281,42 +279,44 @@ int nufft_adj_threads(const NufftArgs& a) {
   return nt;
 }
 
-template <int J, bool R7>
-hipError_t nufft_fwd_t(const NufftArgs& a, const float2* X1, float2* W, hipStream_t s) {
-  const size_t lds = ((size_t)a.K + fft_tw_entries(a.fK)) * sizeof(float2);
-  hipLaunchKernelGGL((nufft_fwd_kernel<J, R7>), dim3(a.n_cols), dim3(nufft_threads(a, 256)), lds, s, a, X1, W);
+template <int J, bool ONE>
+hipError_t nufft_fwd_t(const NufftArgs& a, const float2* X1, float2* W, int nthr, hipStream_t s) {
+  const size_t lds = (size_t)a.K * sizeof(float2);
+  hipLaunchKernelGGL((nufft_fwd_kernel<J, ONE>), dim3(a.n_cols), dim3(nthr), lds, s, a, X1, W);
   return hipGetLastError();
 }
 
 hipError_t launch_nufft_fwd(const NufftArgs& a, const float2* X1, float2* W, hipStream_t s) {
-  const bool r7 = fft_has7(a.fK);
+  const int nt = nufft_threads(a, 256);
+  const bool one = fft_one(a.fK, 1, nt);
   switch (a.J) {
-    case 4: return r7 ? nufft_fwd_t<4, true>(a, X1, W, s) : nufft_fwd_t<4, false>(a, X1, W, s);
-    case 6: return r7 ? nufft_fwd_t<6, true>(a, X1, W, s) : nufft_fwd_t<6, false>(a, X1, W, s);
-    default: return r7 ? nufft_fwd_t<8, true>(a, X1, W, s) : nufft_fwd_t<8, false>(a, X1, W, s);
+    case 4: return one ? nufft_fwd_t<4, true>(a, X1, W, nt, s) : nufft_fwd_t<4, false>(a, X1, W, nt, s);
+    case 6: return one ? nufft_fwd_t<6, true>(a, X1, W, nt, s) : nufft_fwd_t<6, false>(a, X1, W, nt, s);
+    default: return one ? nufft_fwd_t<8, true>(a, X1, W, nt, s) : nufft_fwd_t<8, false>(a, X1, W, nt, s);
   }
 }
 
-template <int J, bool R7>
-hipError_t nufft_adj_t(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s) {
+template <int J, bool ONE>
+hipError_t nufft_adj_t(const NufftArgs& a, const float2* Rh, float2* X, int nthr, hipStream_t s) {
   const size_t lds = nufft_adj_lds_bytes(a);
   if (lds > 64 * 1024 - 1024) {
     static bool done = false;
     if (!done) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_adj_kernel<J, R7>),
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_adj_kernel<J, ONE>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
       done = true;
     }
   }
-  hipLaunchKernelGGL((nufft_adj_kernel<J, R7>), dim3(a.n_cols), dim3(nufft_adj_threads(a)), lds, s, a, Rh, X);
+  hipLaunchKernelGGL((nufft_adj_kernel<J, ONE>), dim3(a.n_cols), dim3(nthr), lds, s, a, Rh, X);
   return hipGetLastError();
 }
 
 hipError_t launch_nufft_adj(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s) {
-  const bool r7 = fft_has7(a.fK);
+  const int nt = nufft_adj_threads(a);
+  const bool one = fft_one(a.fK, 1, nt);
   switch (a.J) {
-    case 4: return r7 ? nufft_adj_t<4, true>(a, Rh, X, s) : nufft_adj_t<4, false>(a, Rh, X, s);
-    case 6: return r7 ? nufft_adj_t<6, true>(a, Rh, X, s) : nufft_adj_t<6, false>(a, Rh, X, s);
-    default: return r7 ? nufft_adj_t<8, true>(a, Rh, X, s) : nufft_adj_t<8, false>(a, Rh, X, s);
+    case 4: return one ? nufft_adj_t<4, true>(a, Rh, X, nt, s) : nufft_adj_t<4, false>(a, Rh, X, nt, s);
+    case 6: return one ? nufft_adj_t<6, true>(a, Rh, X, nt, s) : nufft_adj_t<6, false>(a, Rh, X, nt, s);
+    default: return one ? nufft_adj_t<8, true>(a, Rh, X, nt, s) : nufft_adj_t<8, false>(a, Rh, X, nt, s);
   }
 }

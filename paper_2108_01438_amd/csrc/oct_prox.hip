@@ -420,8 +420,11 @@ __device__ __forceinline__ float lane_next(float v) {
 // such a component is zero too, so it stays zero, and the divergence needs
 // no boundary tests: (div p)_i = p_i - p_{i-1} along each axis.
 __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
-  __shared__ float2 xr[TV_WAVES][64];
-  __shared__ float2 xd[TV_WAVES][64];
+  // strip-edge exchange rows: wave w publishes its last column in xr[w + 1]
+  // and its first in xd[w]; xr[0] and xd[TV_WAVES] stay zero, so every read
+  // is unconditional
+  __shared__ float2 xr[TV_WAVES + 1][64];
+  __shared__ float2 xd[TV_WAVES + 1][64];
   __shared__ double sh[16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int bid = blockIdx.x;
@@ -443,9 +446,16 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   const int64_t N = a.n_total;
   const float tau = a.tau, step = a.step;
   const float sz = zedge ? step : 0.f;
+  if (w == 0) xr[0][lane] = make_float2(0.f, 0.f);
+  if (w == TV_WAVES - 1) xd[TV_WAVES][lane] = make_float2(0.f, 0.f);
 
-  float2 v[TV_S], pz[TV_S], pl[TV_S], rz[TV_S], rl[TV_S];
+  // FGP state per pixel: the extrapolated dual r and the previous dual P,
+  // kept pre-multiplied by the momentum of the step that consumes it, so that
+  // r = (1 + mom_k) p_k - mom_k p_{k-1} is one fused multiply-add per
+  // component (mom after the last step is 1: P ends as the plain dual).
+  float2 v[TV_S], Pz[TV_S], Pl[TV_S], rz[TV_S], rl[TV_S];
   float sl[TV_S];
+  const float mom0 = a.mom[0];
 #pragma unroll
   for (int s = 0; s < TV_S; ++s) {
     const int l = l0 + s;
@@ -454,20 +464,24 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
     sl[s] = ledge ? step : 0.f;
     const int64_t idx = ib + (int64_t)l * Nz + n;
     v[s] = in ? a.v[idx] : make_float2(0.f, 0.f);
-    pz[s] = (in && zedge && a.pin) ? a.pin[idx] : make_float2(0.f, 0.f);
-    pl[s] = (in && ledge && a.pin) ? a.pin[N + idx] : make_float2(0.f, 0.f);
-    rz[s] = pz[s];
-    rl[s] = pl[s];
+    rz[s] = (in && zedge && a.pin) ? a.pin[idx] : make_float2(0.f, 0.f);
+    rl[s] = (in && ledge && a.pin) ? a.pin[N + idx] : make_float2(0.f, 0.f);
+    Pz[s] = cscale(rz[s], mom0);
+    Pl[s] = cscale(rl[s], mom0);
   }
-  for (int k = 0; k < a.n_inner; ++k) {
-    const float mom = a.mom[k];
-    const float mom1 = 1.f + mom;
-    xr[w][lane] = rl[TV_S - 1];
+  // One FGP step from the previous dual Pi into Po.  The loop below runs the
+  // steps in pairs with the two dual sets swapping roles, so that no
+  // register copies are carried around the loop.
+  auto fgp_step = [&](int k, float2 (&Piz)[TV_S], float2 (&Pil)[TV_S], float2 (&Poz)[TV_S],
+                      float2 (&Pol)[TV_S]) __attribute__((always_inline)) {
+    const float mom1 = 1.f + a.mom[k];
+    const float mnext = a.mom[k + 1];
+    xr[w + 1][lane] = rl[TV_S - 1];
     __syncthreads();
     float2 d[TV_S];
 #pragma unroll
     for (int s = 0; s < TV_S; ++s) {
-      const float2 lp = (s > 0) ? rl[s - 1] : (w > 0 ? xr[w - 1][lane] : make_float2(0.f, 0.f));
+      const float2 lp = (s > 0) ? rl[s - 1] : xr[w][lane];
       const float dx = (rz[s].x - lane_prev(rz[s].x)) + (rl[s].x - lp.x);
       const float dy = (rz[s].y - lane_prev(rz[s].y)) + (rl[s].y - lp.y);
       d[s] = make_float2(fmaf(tau, dx, v[s].x), fmaf(tau, dy, v[s].y));
@@ -476,30 +490,43 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < TV_S; ++s) {
-      // momentum r = (1 + mom) q - mom p: the old dual is consumed first, so
-      // the new one can take its registers (no loop-carried copies)
-      const float2 mpz = cscale(pz[s], mom), mpl = cscale(pl[s], mom);
-      const float2 dl = (s < TV_S - 1) ? d[s + 1] : (w < TV_WAVES - 1 ? xd[w + 1][lane] : make_float2(0.f, 0.f));
-      float2 qz = make_float2(fmaf(sz, lane_next(d[s].x) - d[s].x, rz[s].x),
-                              fmaf(sz, lane_next(d[s].y) - d[s].y, rz[s].y));
-      float2 ql = make_float2(fmaf(sl[s], dl.x - d[s].x, rl[s].x), fmaf(sl[s], dl.y - d[s].y, rl[s].y));
+      const float2 dl = (s < TV_S - 1) ? d[s + 1] : xd[w + 1][lane];
+      const float2 qz = make_float2(fmaf(sz, lane_next(d[s].x) - d[s].x, rz[s].x),
+                                    fmaf(sz, lane_next(d[s].y) - d[s].y, rz[s].y));
+      const float2 ql = make_float2(fmaf(sl[s], dl.x - d[s].x, rl[s].x), fmaf(sl[s], dl.y - d[s].y, rl[s].y));
       const float m2 = qz.x * qz.x + qz.y * qz.y + ql.x * ql.x + ql.y * ql.y;
-      const float sc = m2 > 1.f ? rsqrtf(m2) : 1.f;
-      pz[s] = cscale(qz, sc);
-      pl[s] = cscale(ql, sc);
-      rz[s] = make_float2(fmaf(mom1, pz[s].x, -mpz.x), fmaf(mom1, pz[s].y, -mpz.y));
-      rl[s] = make_float2(fmaf(mom1, pl[s].x, -mpl.x), fmaf(mom1, pl[s].y, -mpl.y));
+      // projection onto |p| <= 1: 1/sqrt(m2) when m2 > 1, else 1 (m2 = 0 included)
+      const float sc = fminf(1.f, __builtin_amdgcn_rsqf(m2));
+      const float ca = mom1 * sc, cb = mnext * sc;
+      rz[s] = make_float2(fmaf(ca, qz.x, -Piz[s].x), fmaf(ca, qz.y, -Piz[s].y));
+      rl[s] = make_float2(fmaf(ca, ql.x, -Pil[s].x), fmaf(ca, ql.y, -Pil[s].y));
+      Poz[s] = cscale(qz, cb);
+      Pol[s] = cscale(ql, cb);
+    }
+  };
+  float2 Qz[TV_S], Ql[TV_S];
+  int k = 0;
+  for (; k + 1 < a.n_inner; k += 2) {
+    fgp_step(k, Pz, Pl, Qz, Ql);
+    fgp_step(k + 1, Qz, Ql, Pz, Pl);
+  }
+  if (k < a.n_inner) {
+    fgp_step(k, Pz, Pl, Qz, Ql);
+#pragma unroll
+    for (int s = 0; s < TV_S; ++s) {
+      Pz[s] = Qz[s];
+      Pl[s] = Ql[s];
     }
   }
-  // z = v + tau div p
-  xr[w][lane] = pl[TV_S - 1];
+  // z = v + tau div p  (P holds p after the last step)
+  xr[w + 1][lane] = Pl[TV_S - 1];
   __syncthreads();
   float2 z[TV_S];
 #pragma unroll
   for (int s = 0; s < TV_S; ++s) {
-    const float2 lp = (s > 0) ? pl[s - 1] : (w > 0 ? xr[w - 1][lane] : make_float2(0.f, 0.f));
-    const float dx = (pz[s].x - lane_prev(pz[s].x)) + (pl[s].x - lp.x);
-    const float dy = (pz[s].y - lane_prev(pz[s].y)) + (pl[s].y - lp.y);
+    const float2 lp = (s > 0) ? Pl[s - 1] : xr[w][lane];
+    const float dx = (Pz[s].x - lane_prev(Pz[s].x)) + (Pl[s].x - lp.x);
+    const float dy = (Pz[s].y - lane_prev(Pz[s].y)) + (Pl[s].y - lp.y);
     z[s] = make_float2(fmaf(tau, dx, v[s].x), fmaf(tau, dy, v[s].y));
   }
   xd[w][lane] = z[0];
@@ -510,7 +537,7 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   for (int s = 0; s < TV_S; ++s) {
     const int l = l0 + s;
     const float dnx = lane_next(z[s].x), dny = lane_next(z[s].y);
-    const float2 zl = (s < TV_S - 1) ? z[s + 1] : (w < TV_WAVES - 1 ? xd[w + 1][lane] : make_float2(0.f, 0.f));
+    const float2 zl = (s < TV_S - 1) ? z[s + 1] : xd[w + 1][lane];
     if (zcore && l >= cl0 && l < cl0 + a.CL && l < Nx) {
       float m2 = 0.f;
       if (zedge) m2 += (dnx - z[s].x) * (dnx - z[s].x) + (dny - z[s].y) * (dny - z[s].y);
@@ -518,8 +545,8 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
       acc += (double)sqrtf(m2);
       const int64_t idx = ib + (int64_t)l * Nz + n;
       a.z[idx] = z[s];
-      a.pout[idx] = pz[s];
-      a.pout[N + idx] = pl[s];
+      a.pout[idx] = Pz[s];
+      a.pout[N + idx] = Pl[s];
     }
   }
   const double sum = block_sum(acc, sh);
@@ -665,6 +692,7 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
     a.tau = tau;
     a.step = 1.0f / (8.0f * tau);
     for (int k = 0; k < n_inner; ++k) a.mom[k] = mom[k];
+    a.mom[n_inner] = 1.f;   // the last step leaves the plain dual in the kernel's P
     a.v = v;
     a.z = z;
     a.pin = p_in;
