@@ -70,10 +70,66 @@ def prox_flops(g, n_inner: int) -> float:
 
 def grad_bytes(g, masked: bool) -> float:
     """Phi + Phi^H (oct_grad): x in, lateral FFT, NUFFT, residual seam,
-    adjoint NUFFT, inverse lateral FFT, g out."""
+    adjoint NUFFT, inverse lateral FFT, g out.  A volume's 2-D lateral
+    transform takes two passes (a plane does not fit on chip), which adds a
+    read and a write of the image twice on each side and of the spectrum
+    twice in the seam."""
     N = g.batch * g.n_y * g.n_x * g.n_depth
     M = g.batch * g.n_y * g.n_x * g.n_k
-    return 48.0 * N + 36.0 * M + (M / 8.0 if masked else 0.0)
+    mbits = M / 8.0 if masked else 0.0
+    if g.lateral_dims == 2:
+        return 80.0 * N + 68.0 * M + mbits
+    return 48.0 * N + 36.0 * M + mbits
+
+
+def phi_sizes_bench() -> dict:
+    """Phi + Phi^H (oct_grad) at the batch (32 x 1024 x 512) and volume
+    (2048 x 256 x 256) sizes, random x and y resident on the device, and a
+    plain 1 GiB device copy for the attainable bandwidth."""
+    import torch
+    import paper_2108_01438_amd as P
+    import synth
+    torch.cuda.set_device(0)
+    res = {"metric": "Phi+Phi^H applications/s and algorithmic HBM GB/s", "peak_GBps": HBM_PEAK_GBPS}
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(10):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    res["copy_GBps"] = round(2 * n * 4 / (a.elapsed_time(b) / 10 * 1e-3) / 1e9, 1)
+    del src, dst
+    for name, reps in (("batch32_1024x512_grad", 20), ("volume_2048x256x256_haar", 5)):
+        g = P.Geometry.from_dict(synth.preset(name)["geom"])
+        plan = P.Plan(g)
+        gen = torch.Generator(device="cuda").manual_seed(5)
+        x = torch.randn(g.img_shape, dtype=torch.complex64, device="cuda", generator=gen)
+        y = torch.randn(g.meas_shape, dtype=torch.float32, device="cuda", generator=gen)
+        gb = torch.empty_like(x)
+        rb = torch.empty((), dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            plan.grad(x, y, gb, rb)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            plan.grad(x, y, gb, rb)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        byt = grad_bytes(g, False)
+        res[name] = {"ms": round(ms, 4), "applications_per_s": round(1000.0 / ms, 2),
+                     "algorithmic_GB": round(byt / 1e9, 3), "GBps": round(byt / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_peak": round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        print(f"[bench] {name}: {ms:.3f} ms", file=sys.stderr, flush=True)
+        plan.close()
+        del x, y, gb
+    return res
 
 
 STAGE_KERNEL = {
@@ -225,6 +281,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=0,
                     help="only run the serving benchmark with this many requests")
+    ap.add_argument("--phi-sizes", action="store_true",
+                    help="only time Phi + Phi^H at the batch and volume sizes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (counter calibration)")
     args = ap.parse_args()
@@ -237,6 +295,9 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}))
+        return 0
+    if args.phi_sizes:
+        print(json.dumps(phi_sizes_bench()), flush=True)
         return 0
     if args.serving > 0:
         import torch
