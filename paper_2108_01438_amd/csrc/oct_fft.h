@@ -35,6 +35,23 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) {
   return (t + ((x - t) >> 1)) >> f.s;
 }
 
+// Element loop with batched loads: every thread first issues the loads of U
+// elements (indices clamped to a valid element, so each load is in bounds
+// and none waits on another), then consumes them in order.  A plain loop
+// would wait for each element's load before issuing the next.
+template <int U = 8, class Load, class Use>
+__device__ __forceinline__ void batched_for(int n, int tid, int nthr, Load load, Use use) {
+  using R = decltype(load(0));
+  for (int i0 = tid; i0 < n; i0 += U * nthr) {
+    R r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = load(min(i0 + u * nthr, n - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * nthr < n) use(i0 + u * nthr, r[u]);
+  }
+}
+
 template <int R, bool INV> struct Dft;
 
 template <bool INV> struct Dft<2, INV> {

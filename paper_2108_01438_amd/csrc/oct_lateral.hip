@@ -65,6 +65,18 @@ __device__ __forceinline__ float2 unpack_real_pair(const float2* lds, int rs, in
                 : make_float2(0.5f * (z0.x + z1.x), 0.5f * (z0.y - z1.y));
 }
 
+struct Z2 {
+  float2 a, b;
+};
+struct FM {
+  float f;
+  uint32_t m;
+};
+struct YM {
+  float ya, yb;
+  uint32_t ma, mb;
+};
+
 template <int MODE, bool ONE>
 __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   extern __shared__ float2 lds[];
@@ -85,6 +97,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   const int L = lg.L, T = a.T, rs = a.rowstride;
   const int latb = (line % lg.lat_lines) * L;
   const int n = L * T;
+  const int lt = a.log2T;
 
   const float2* __restrict__ twl = a.tw;
   // modes that need only real parts (or transform real rows) pair rows p and p + H
@@ -92,39 +105,44 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   const bool pair = REAL_PAIRS && T >= 2;
   const int H = T >> 1;
   const int nrow_t = pair ? H : T;   // rows that go through the transforms
+  // global offset of tile element idx (row t = idx mod T, lateral l = idx / T); rows past the
+  // image (ragged last tile) are clamped to a valid row and masked by the caller
+  auto goff = [&](int idx) -> int64_t {
+    const int l = idx >> lt, t = min(idx & (T - 1), nr - 1);
+    return base + (int64_t)l * lg.es + t;
+  };
+  auto mword = [&](int l, int row) -> uint32_t {
+    return a.mask ? a.mask[(int64_t)(latb + l) * a.mask_words + (row >> 5)] : ~0u;
+  };
 
   // ---- load the tile: element (row t, lateral l) -> lds[t * rs + l]
-  if (MODE == LAT_ADJ_MEAS && pair) {
-    // real rows straight into the packed layout: row t -> component t >= H of row t mod H
+  if (MODE == LAT_ADJ_MEAS) {
+    // real rows; paired: row t -> component t >= H of row t mod H
     float* ldsf = reinterpret_cast<float*>(lds);
-    for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> a.log2T;
-      const int t = idx & (T - 1);
-      float r = 0.f;
-      if (t < nr) {
-        r = a.srcf[base + (int64_t)l * lg.es + t];
-        if (a.mask && !mask_bit(a.mask, a.mask_words, latb + l, r0 + t)) r = 0.f;
-      }
-      ldsf[2 * ((t < H ? t : t - H) * rs + l) + (t < H ? 0 : 1)] = r;
-    }
-  } else for (int idx = tid; idx < n; idx += nthr) {
-    const int l = idx >> a.log2T;
-    const int t = idx & (T - 1);
-    float2 v = make_float2(0.f, 0.f);
-    if (t < nr) {
-      const int64_t off = base + (int64_t)l * lg.es + t;
-      if (MODE == LAT_ADJ_MEAS) {
-        float r = a.srcf[off];
-        if (a.mask && !mask_bit(a.mask, a.mask_words, latb + l, r0 + t)) r = 0.f;
-        v = make_float2(r, 0.f);
-      } else if (MODE == LAT_FFT && a.z != nullptr) {
-        const float2 z = a.z[off], zo = a.zo[off];
-        v = make_float2(z.x + a.mu * (z.x - zo.x), z.y + a.mu * (z.y - zo.y));
-      } else {
-        v = a.src[off];
-      }
-    }
-    lds[t * rs + l] = v;
+    batched_for(n, tid, nthr,
+      [&](int idx) { const int l = idx >> lt, t = min(idx & (T - 1), nr - 1);
+                     return FM{a.srcf[goff(idx)], mword(l, r0 + t)}; },
+      [&](int idx, FM v) {
+        const int l = idx >> lt, t = idx & (T - 1);
+        const float r = (t < nr && ((v.m >> ((r0 + t) & 31)) & 1u)) ? v.f : 0.f;
+        if (pair) ldsf[2 * ((t < H ? t : t - H) * rs + l) + (t < H ? 0 : 1)] = r;
+        else lds[t * rs + l] = make_float2(r, 0.f);
+      });
+  } else if (MODE == LAT_FFT && a.z != nullptr) {
+    batched_for(n, tid, nthr,
+      [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; },
+      [&](int idx, Z2 v) {
+        const int l = idx >> lt, t = idx & (T - 1);
+        lds[t * rs + l] = t < nr ? make_float2(v.a.x + a.mu * (v.a.x - v.b.x), v.a.y + a.mu * (v.a.y - v.b.y))
+                                 : make_float2(0.f, 0.f);
+      });
+  } else {
+    batched_for(n, tid, nthr,
+      [&](int idx) { return a.src[goff(idx)]; },
+      [&](int idx, float2 v) {
+        const int l = idx >> lt, t = idx & (T - 1);
+        lds[t * rs + l] = t < nr ? v : make_float2(0.f, 0.f);
+      });
   }
   __syncthreads();
   if ((MODE == LAT_FWD_MEAS || MODE == LAT_NORMAL) && pair) {
@@ -137,7 +155,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
 
   if (MODE == LAT_FFT || MODE == LAT_ADJ_MEAS) {
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> a.log2T, t = idx & (T - 1);
+      const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) {
         const float2 v = (MODE == LAT_ADJ_MEAS && pair) ? unpack_real_pair(lds, rs, L, H, t, l) : lds[t * rs + l];
         a.dst[base + (int64_t)l * lg.es + t] = cscale(v, a.scale);
@@ -146,51 +164,56 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     return;
   }
   if (MODE == LAT_FWD_MEAS) {
-    for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> a.log2T, t = idx & (T - 1);
-      if (t < nr) {
-        const float re = !pair ? lds[t * rs + l].x : (t < H ? lds[t * rs + l].x : lds[(t - H) * rs + l].y);
-        float yv = re * a.scale;
-        if (a.mask && !mask_bit(a.mask, a.mask_words, latb + l, r0 + t)) yv = 0.f;
-        a.dstf[base + (int64_t)l * lg.es + t] = yv;
-      }
-    }
+    batched_for(n, tid, nthr,
+      [&](int idx) { const int l = idx >> lt, t = min(idx & (T - 1), nr - 1); return mword(l, r0 + t); },
+      [&](int idx, uint32_t m) {
+        const int l = idx >> lt, t = idx & (T - 1);
+        if (t < nr) {
+          const float re = !pair ? lds[t * rs + l].x : (t < H ? lds[t * rs + l].x : lds[(t - H) * rs + l].y);
+          const float yv = ((m >> ((r0 + t) & 31)) & 1u) ? re * a.scale : 0.f;
+          a.dstf[base + (int64_t)l * lg.es + t] = yv;
+        }
+      });
     return;
   }
   if (MODE == LAT_UPDATE) {
-    for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> a.log2T, t = idx & (T - 1);
-      if (t < nr) {
-        const int64_t off = base + (int64_t)l * lg.es + t;
-        const float2 g = cscale(lds[t * rs + l], a.scale);
-        const float2 z = a.z[off], zo = a.zo[off];
-        const float xr = z.x + a.mu * (z.x - zo.x), xi = z.y + a.mu * (z.y - zo.y);
-        a.dst[off] = make_float2(xr - a.delta * g.x, xi - a.delta * g.y);
-      }
-    }
+    batched_for(n, tid, nthr,
+      [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; },
+      [&](int idx, Z2 v) {
+        const int l = idx >> lt, t = idx & (T - 1);
+        if (t < nr) {
+          const float2 g = cscale(lds[t * rs + l], a.scale);
+          const float xr = v.a.x + a.mu * (v.a.x - v.b.x), xi = v.a.y + a.mu * (v.a.y - v.b.y);
+          a.dst[base + (int64_t)l * lg.es + t] = make_float2(xr - a.delta * g.x, xi - a.delta * g.y);
+        }
+      });
     return;
   }
   if (MODE == LAT_NORMAL && pair) {
     // residual of rows p and p + H from the real and imaginary parts of row p
     double acc = 0.0;
-    const int log2H = a.log2T - 1;
-    for (int idx = tid; idx < (n >> 1); idx += nthr) {
-      const int l = idx >> log2H, p = idx & (H - 1);
-      const float2 vv = lds[p * rs + l];
-      float ra = 0.f, rb = 0.f;
-      const int64_t off = base + (int64_t)l * lg.es + p;
-      if (p < nr && (!a.mask || mask_bit(a.mask, a.mask_words, latb + l, r0 + p)))
-        ra = vv.x * a.scale - (a.y ? a.y[off] : 0.f);
-      if (p + H < nr && (!a.mask || mask_bit(a.mask, a.mask_words, latb + l, r0 + p + H)))
-        rb = vv.y * a.scale - (a.y ? a.y[off + H] : 0.f);
-      acc += (double)ra * (double)ra;
-      acc += (double)rb * (double)rb;
-      lds[p * rs + l] = make_float2(ra, rb);
-    }
+    const int log2H = lt - 1;
+    batched_for(n >> 1, tid, nthr,
+      [&](int idx) {
+        const int l = idx >> log2H, p = idx & (H - 1);
+        const int pa = min(p, nr - 1), pb = min(p + H, nr - 1);
+        const int64_t oa = base + (int64_t)l * lg.es + pa, ob = base + (int64_t)l * lg.es + pb;
+        return YM{a.y ? a.y[oa] : 0.f, a.y ? a.y[ob] : 0.f, mword(l, r0 + pa), mword(l, r0 + pb)};
+      },
+      [&](int idx, YM v) {
+        const int l = idx >> log2H, p = idx & (H - 1);
+        const float2 vv = lds[p * rs + l];
+        float ra = 0.f, rb = 0.f;
+        if (p < nr && ((v.ma >> ((r0 + p) & 31)) & 1u)) ra = vv.x * a.scale - v.ya;
+        if (p + H < nr && ((v.mb >> ((r0 + p + H) & 31)) & 1u)) rb = vv.y * a.scale - v.yb;
+        acc += (double)ra * (double)ra;
+        acc += (double)rb * (double)rb;
+        lds[p * rs + l] = make_float2(ra, rb);
+      });
     __syncthreads();
     fft_rows<ONE, false>(lds, H, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> a.log2T, t = idx & (T - 1);
+      const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(unpack_real_pair(lds, rs, L, H, t, l), a.scale2);
     }
     const double s = block_sum_d(acc, red);
@@ -199,21 +222,20 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   }
   if (MODE == LAT_NORMAL) {
     double acc = 0.0;
-    for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> a.log2T, t = idx & (T - 1);
-      float r = 0.f;
-      if (t < nr) {
-        const int64_t off = base + (int64_t)l * lg.es + t;
-        const bool on = !a.mask || mask_bit(a.mask, a.mask_words, latb + l, r0 + t);
-        if (on) r = lds[t * rs + l].x * a.scale - (a.y ? a.y[off] : 0.f);
-      }
-      acc += (double)r * (double)r;
-      lds[t * rs + l] = make_float2(r, 0.f);
-    }
+    batched_for(n, tid, nthr,
+      [&](int idx) { const int l = idx >> lt, t = min(idx & (T - 1), nr - 1);
+                     return FM{a.y ? a.y[goff(idx)] : 0.f, mword(l, r0 + t)}; },
+      [&](int idx, FM v) {
+        const int l = idx >> lt, t = idx & (T - 1);
+        float r = 0.f;
+        if (t < nr && ((v.m >> ((r0 + t) & 31)) & 1u)) r = lds[t * rs + l].x * a.scale - v.f;
+        acc += (double)r * (double)r;
+        lds[t * rs + l] = make_float2(r, 0.f);
+      });
     __syncthreads();
     fft_rows<ONE, false>(lds, T, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> a.log2T, t = idx & (T - 1);
+      const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
     }
     const double s = block_sum_d(acc, red);
@@ -222,28 +244,30 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   }
   if (MODE == LAT_UPDATE_L1) {
     double acc = 0.0;
-    for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> a.log2T, t = idx & (T - 1);
-      float2 xn = make_float2(0.f, 0.f);
-      if (t < nr) {
-        const int64_t off = base + (int64_t)l * lg.es + t;
-        const float2 g = cscale(lds[t * rs + l], a.scale);
-        const float2 z = a.z[off], zo = a.zo[off];
-        const float vr = z.x + a.mu * (z.x - zo.x) - a.delta * g.x;
-        const float vi = z.y + a.mu * (z.y - zo.y) - a.delta * g.y;
-        const float mag = sqrtf(vr * vr + vi * vi);
-        const float sc = mag > a.tau ? 1.f - a.tau / mag : 0.f;
-        const float2 zn = make_float2(vr * sc, vi * sc);
-        acc += (double)sqrtf(zn.x * zn.x + zn.y * zn.y);
-        a.zo[off] = zn;
-        xn = make_float2(zn.x + a.mu_next * (zn.x - z.x), zn.y + a.mu_next * (zn.y - z.y));
-      }
-      lds[t * rs + l] = xn;
-    }
+    batched_for(n, tid, nthr,
+      [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; },
+      [&](int idx, Z2 v) {
+        const int l = idx >> lt, t = idx & (T - 1);
+        float2 xn = make_float2(0.f, 0.f);
+        if (t < nr) {
+          const int64_t off = base + (int64_t)l * lg.es + t;
+          const float2 g = cscale(lds[t * rs + l], a.scale);
+          const float2 z = v.a, zo = v.b;
+          const float vr = z.x + a.mu * (z.x - zo.x) - a.delta * g.x;
+          const float vi = z.y + a.mu * (z.y - zo.y) - a.delta * g.y;
+          const float mag = sqrtf(vr * vr + vi * vi);
+          const float sc = mag > a.tau ? 1.f - a.tau / mag : 0.f;
+          const float2 zn = make_float2(vr * sc, vi * sc);
+          acc += (double)sqrtf(zn.x * zn.x + zn.y * zn.y);
+          a.zo[off] = zn;
+          xn = make_float2(zn.x + a.mu_next * (zn.x - z.x), zn.y + a.mu_next * (zn.y - z.y));
+        }
+        lds[t * rs + l] = xn;
+      });
     __syncthreads();
     fft_rows<ONE, false>(lds, T, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> a.log2T, t = idx & (T - 1);
+      const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = lds[t * rs + l];
     }
     const double s = block_sum_d(acc, red);

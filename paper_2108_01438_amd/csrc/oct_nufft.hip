@@ -55,8 +55,9 @@ __device__ __forceinline__ float kb_tap(const float* __restrict__ kc, int j, flo
 }
 
 // Filter H(m, q) = beam(q) e^{j(-2 k_m z_f + Omega_m)} e^{j beta (z_f - n_c dz)}.
-__device__ __forceinline__ float2 filter_h(const NufftArgs& a, int m, float bq, double beta) {
-  float2 h = a.phase[m];
+// ph = a.phase[m] (read by the caller, batched with the sample's other loads)
+__device__ __forceinline__ float2 filter_h(const NufftArgs& a, float2 ph, float bq, double beta) {
+  float2 h = ph;
   h.x *= bq;
   h.y *= bq;
   if (a.df != 0.0) {
@@ -66,6 +67,22 @@ __device__ __forceinline__ float2 filter_h(const NufftArgs& a, int m, float bq, 
   }
   return h;
 }
+
+// per-element loads gathered for batched_for (grid loads and stores; the
+// sample loops are not batched: their bodies are long, other waves cover the
+// table loads, and batching them would cost registers)
+struct VD {
+  float2 v;
+  float d;
+};
+struct KP {
+  double k2;
+  float2 ph;
+};
+struct KPR {
+  double k2;
+  float2 ph, r;
+};
 
 template <int J, bool ONE>
 __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const float2* __restrict__ X1,
@@ -80,11 +97,12 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
 
   // n' = n - n_c placed at n' mod K; cells [Nz - nc, K - nc) stay zero.
   for (int i = tid; i < K - Nz; i += nthr) grid[Nz - nc + i] = make_float2(0.f, 0.f);
-  for (int n = tid; n < Nz; n += nthr) {
-    int idx = n - nc;
-    if (idx < 0) idx += K;
-    grid[idx] = cscale(src[n], a.deap[n]);
-  }
+  batched_for(Nz, tid, nthr, [&](int n) { return VD{src[n], a.deap[n]}; },
+              [&](int n, VD v) {
+                int idx = n - nc;
+                if (idx < 0) idx += K;
+                grid[idx] = cscale(v.v, v.d);
+              });
   __syncthreads();
   fft_rows<ONE, false>(grid, 1, K, a.fK, twl, tid, nthr);
 
@@ -92,7 +110,8 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
   const float bq = a.beam[lat];
   float2* __restrict__ out = W + (int64_t)col * a.Mk;
   for (int m = tid; m < a.Mk; m += nthr) {
-    const double arg = a.k2x4[m] - q2;
+    const KP kp{a.k2x4[m], a.phase[m]};
+    const double arg = kp.k2 - q2;
     float2 res = make_float2(0.f, 0.f);
     if (arg > 0.0) {
       const double beta = sqrt(arg);
@@ -116,7 +135,7 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
         acc.x = fmaf(whi, g1.x, acc.x);
         acc.y = fmaf(whi, g1.y, acc.y);
       }
-      res = cmul(filter_h(a, m, bq, beta), acc);
+      res = cmul(filter_h(a, kp.ph, bq, beta), acc);
     }
     out[m] = res;
   }
@@ -152,14 +171,15 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
   const float bq = a.beam[lat];
   const float2* __restrict__ rin = Rh + (int64_t)col * Mk;
   for (int m = tid; m < Mk; m += nthr) {
-    const double arg = a.k2x4[m] - q2;
+    const KPR v{a.k2x4[m], a.phase[m], rin[m]};
+    const double arg = v.k2 - q2;
     if (arg > 0.0) {
       const double beta = sqrt(arg);
       const double t = a.ct * beta;
       const double fl = floor(t);
       bm[m] = (short)(int)fl;               // t < 32000 (checked at plan creation)
       xm[m] = (float)(2.0 * (t - fl) - 1.0);
-      us[m] = cmul(cconj(filter_h(a, m, bq, beta)), rin[m]);
+      us[m] = cmul(cconj(filter_h(a, v.ph, bq, beta)), v.r);
     } else {
       bm[m] = EVANESCENT16;
       xm[m] = 0.f;
@@ -247,11 +267,11 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
 
   fft_rows<ONE, true>(grid, 1, K, a.fK, twl, tid, nthr);
   float2* __restrict__ dst = X + (int64_t)col * Nz;
-  for (int n = tid; n < Nz; n += nthr) {
+  batched_for(Nz, tid, nthr, [&](int n) { return a.deap[n]; }, [&](int n, float d) {
     int idx = n - nc;
     if (idx < 0) idx += K;
-    dst[n] = cscale(grid[idx], a.deap[n]);
-  }
+    dst[n] = cscale(grid[idx], d);
+  });
 }
 
 // Threads per column: enough for the FFT stages, and wide enough that the
