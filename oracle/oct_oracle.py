@@ -63,7 +63,8 @@ __all__ = [
     "prox_tv", "tv_value", "haar_forward", "haar_inverse", "haar_detail_mask",
     "prox_haar", "haar_value", "penalty_value", "splitmix64", "counter_uniform",
     "power_start", "lipschitz", "step_size", "fista_momenta", "fista",
-    "lambda_max", "paper_backward_nx1", "ncc", "PEN_L1", "PEN_TV", "PEN_HAAR",
+    "lambda_max", "paper_backward_nx1", "ncc", "direct_axial", "direct_isam", "interp_fill",
+    "interp_isam", "PEN_L1", "PEN_TV", "PEN_HAAR",
 ]
 
 PEN_L1, PEN_TV, PEN_HAAR = 0, 1, 2
@@ -661,6 +662,62 @@ def paper_backward_nx1(r: np.ndarray, g: Geometry) -> np.ndarray:
     xq = back[: g.n_depth]                      # Q^T
     zn = np.arange(g.n_depth) * d.dz
     return xq * np.exp(1j * 2.0 * g.k_min * zn)
+
+
+# ----------------------------------------------------------------------------
+# Direct reconstructions (Sec. 3.1, Figure 1) and the interpolated-ISAM
+# baseline of the sub-sampling study (Sec. 3.1)
+# ----------------------------------------------------------------------------
+def direct_axial(y, g: Geometry, mask=None, dispersion: bool = True, exact: bool = False,
+                 chunk: int = 256) -> np.ndarray:
+    """Per-A-scan depth transform without the ISAM resampling ("IFFT", and with
+    dispersion=True "dispersion corrected" in Figure 1).
+
+    Reading: every A-scan is taken as the lateral-frequency-zero column of the
+    model (beta = 2k, no beam term, no lateral transforms), and the
+    reconstruction is the adjoint of that axial model applied to s . y; with
+    dispersion=False the dispersion phase Omega is left out.  In the exact mode
+    this is sum_m s_m y_m e^{-j Omega_m} e^{+j 2 k_m z_n}: the paper's zero-pad
+    and 2N-point inverse DFT of the (dispersion-compensated) spectrum."""
+    y = np.asarray(y, dtype=np.float64).reshape(meas_shape(g))
+    if mask is not None:
+        y = y * np.asarray(mask, dtype=np.float64)[None]
+    ga = g.with_(beam_waist=0.0) if dispersion else g.with_(beam_waist=0.0, disp_a=0.0, disp_b=0.0)
+    rows = y.reshape(-1, g.n_k).astype(np.complex128)
+    X = np.empty((rows.shape[0], g.n_depth), dtype=np.complex128)
+    zero = np.zeros(rows.shape[0])
+    for a, b in _chunks(rows.shape[0], chunk):
+        X[a:b] = nufft_cols_adjoint(rows[a:b], zero[a:b], ga, exact=exact)
+    return X.reshape(img_shape(g))
+
+
+def direct_isam(y, g: Geometry, mask=None) -> np.ndarray:
+    """ISAM reconstruction of Figure 1 (dispersion compensation and the ISAM
+    resampling): the adjoint of the full model applied to s . y."""
+    return adjoint(y, g, mask)
+
+
+def interp_fill(y, g: Geometry, mask) -> np.ndarray:
+    """Fill the unobserved spectral samples of every A-scan by linear
+    interpolation in k from its observed samples (k is linear in the pixel
+    index); outside the first and last observed sample the nearest observed
+    value is held; an A-scan with no observed sample stays zero."""
+    y = np.asarray(y, dtype=np.float64).reshape(meas_shape(g))
+    m = np.broadcast_to(np.asarray(mask, dtype=bool)[None], y.shape)
+    rows, mrow = y.reshape(-1, g.n_k), m.reshape(-1, g.n_k)
+    out = np.zeros_like(rows)
+    grid = np.arange(g.n_k, dtype=np.float64)
+    for i in range(rows.shape[0]):
+        obs = np.nonzero(mrow[i])[0]
+        if obs.size:
+            out[i] = np.interp(grid, obs.astype(np.float64), rows[i, obs])
+    return out.reshape(y.shape)
+
+
+def interp_isam(y, g: Geometry, mask) -> np.ndarray:
+    """Baseline of the sub-sampling study: direct ISAM on the linearly
+    interpolated measurements."""
+    return adjoint(interp_fill(y, g, mask), g, None)
 
 
 # ----------------------------------------------------------------------------
