@@ -179,6 +179,41 @@ typedef enum {
  * steps, Haar with 3 levels).  Asynchronous. */
 oct_status oct_run_stage(oct_plan_t plan, int32_t stage, int32_t penalty, const float* y, void* stream);
 
+/* Direct (non-iterative) reconstructions of Sec. 3.1: the three images of
+ * Figure 1 and the baseline of the sub-sampling study. */
+typedef enum {
+  OCT_DIRECT_AXIAL = 0,       /* "IFFT": per-A-scan depth transform, no dispersion
+                                 compensation: the adjoint of the model restricted
+                                 to lateral frequency zero (beta = 2k, no beam term),
+                                 Omega = 0, applied to s . y                          */
+  OCT_DIRECT_DISPERSION = 1,  /* the same with the dispersion phase of eq. (9)
+                                 removed ("dispersion corrected")                    */
+  OCT_DIRECT_ISAM = 2,        /* Phi^H (s . y): dispersion compensation and the ISAM
+                                 resampling (eq. (5)); same as oct_adjoint            */
+  OCT_DIRECT_INTERP_ISAM = 3  /* baseline: each A-scan's unobserved samples linearly
+                                 interpolated in k from its observed ones (nearest
+                                 observed value outside their range, zero if none),
+                                 then Phi^H with every sample observed               */
+} oct_direct_kind;
+
+/* x = the direct reconstruction `kind` of the measurement y.
+ * y: device float32 [batch][n_y][n_x][n_k] (read); x: device complex64
+ * [batch][n_y][n_x][n_depth] (written).  Uses the plan's workspace (and, for
+ * OCT_DIRECT_INTERP_ISAM, a filled-spectrum buffer the plan allocates on
+ * first use: n_k * n_x * n_y * batch floats).  Asynchronous on `stream`.
+ * Errors: OCT_E_INVALID (null pointer, unknown kind), OCT_E_NOMEM,
+ * OCT_E_DEVICE. */
+oct_status oct_direct(oct_plan_t plan, int32_t kind, const float* y, void* x, void* stream);
+
+/* Normalised cross-correlation of magnitudes, eq. (17):
+ *   r = sum (|x_i| - mean|x|)(|z_i| - mean|z|) / sqrt(sum (|x_i| - mean|x|)^2 sum (|z_i| - mean|z|)^2)
+ * over the plan's image size, z the reference ("ground truth").  x, z: device
+ * complex64 images (read).  Sums in FP64 on the device (two passes: means,
+ * then centred sums, deterministic order); r_out: HOST double (written).
+ * Synchronizes `stream`.  Errors: OCT_E_INVALID (null pointer; also when
+ * either image has zero magnitude variance), OCT_E_DEVICE. */
+oct_status oct_ncc(oct_plan_t plan, const void* x, const void* z, double* r_out, void* stream);
+
 /* Message for the last non-OK status returned to the calling thread. */
 const char* oct_last_error(void);
 

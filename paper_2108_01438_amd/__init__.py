@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "liboct.so")
 OCT_OK, OCT_E_INVALID, OCT_E_NOMEM, OCT_E_DEVICE, OCT_E_UNSUPPORTED = range(5)
 PEN_L1, PEN_TV, PEN_HAAR = 0, 1, 2
 PENALTIES = {"l1": PEN_L1, "tv": PEN_TV, "haar": PEN_HAAR}
+# direct reconstructions of Sec. 3.1 (oct_direct_kind)
+DIRECT = {"axial": 0, "dispersion": 1, "isam": 2, "interp_isam": 3}
 
 
 class OctError(RuntimeError):
@@ -71,6 +73,8 @@ def _load():
         "oct_mbir_solve": ([P, P, ctypes.POINTER(_CSolveParams), P, ctypes.POINTER(_CSolveReport), P],
                            ctypes.c_int),
         "oct_run_stage": ([P, ctypes.c_int32, ctypes.c_int32, P, P], ctypes.c_int),
+        "oct_direct": ([P, ctypes.c_int32, P, P, P], ctypes.c_int),
+        "oct_ncc": ([P, P, P, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
         "oct_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -206,6 +210,29 @@ class Plan:
                                 _dev(x, torch.complex64, g.img_shape, "x"), ctypes.c_void_p(_stream_ptr(stream))))
         return x
 
+    def direct(self, y, kind: str, x=None, stream=None):
+        """Direct reconstruction of the measurement y: "axial" (IFFT),
+        "dispersion" (dispersion corrected), "isam" or "interp_isam"."""
+        import torch
+        g = self.geom
+        if kind not in DIRECT:
+            raise ValueError(f"unknown direct reconstruction {kind!r}; one of {sorted(DIRECT)}")
+        if x is None:
+            x = torch.empty(g.img_shape, dtype=torch.complex64, device=y.device)
+        _check(_lib.oct_direct(self._h, DIRECT[kind], _dev(y, torch.float32, g.meas_shape, "y"),
+                               _dev(x, torch.complex64, g.img_shape, "x"), ctypes.c_void_p(_stream_ptr(stream))))
+        return x
+
+    def ncc(self, x, z, stream=None) -> float:
+        """Normalised cross-correlation of magnitudes of x against the reference z (eq. (17))."""
+        import torch
+        g = self.geom
+        r = ctypes.c_double(0.0)
+        _check(_lib.oct_ncc(self._h, _dev(x, torch.complex64, g.img_shape, "x"),
+                            _dev(z, torch.complex64, g.img_shape, "z"), ctypes.byref(r),
+                            ctypes.c_void_p(_stream_ptr(stream))))
+        return float(r.value)
+
     def grad(self, x, y, g_out=None, resid=None, stream=None):
         """Returns (g, half_resid_sq) with half_resid_sq a float64 device scalar tensor."""
         import torch
@@ -272,4 +299,4 @@ class Plan:
 
 
 __all__ = ["Geometry", "Plan", "OctError", "footprint_bytes", "last_error", "LIB_PATH",
-           "PEN_L1", "PEN_TV", "PEN_HAAR", "PENALTIES"]
+           "PEN_L1", "PEN_TV", "PEN_HAAR", "PENALTIES", "DIRECT"]

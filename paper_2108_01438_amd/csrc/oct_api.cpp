@@ -185,6 +185,11 @@ struct oct_plan {
   double* partial = nullptr;
   int partial_cap = 0;
   double* dscal = nullptr;       // device scalars
+  // direct reconstructions: lateral-frequency-zero tables and the filled spectrum
+  double* q2zero = nullptr;      // [Nlat] zeros
+  float* beamone = nullptr;      // [Nlat] ones
+  float2* phase_nd = nullptr;    // [Mk] e^{-j 2 k_m z_f} (no dispersion phase)
+  float* yfill = nullptr;        // [batch][lat][Mk], allocated on first use
   // solver state, allocated on first use
   float2 *za = nullptr, *zb = nullptr;
   float2 *p0 = nullptr, *p1 = nullptr, *tvwork = nullptr;
@@ -378,8 +383,9 @@ oct_status run_meas_forward(oct_plan* p, float* y, hipStream_t s) {
 }
 
 // r -> W = F_lat(s . r) / N_lat
-oct_status run_meas_adjoint(oct_plan* p, const float* r, hipStream_t s) {
+oct_status run_meas_adjoint(oct_plan* p, const float* r, hipStream_t s, bool use_mask = true) {
   LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+  if (!use_mask) a.mask = nullptr;
   a.srcf = r;
   a.dst = p->W;
   a.scale = 1.f / (float)p->Nx;
@@ -539,7 +545,7 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   const int nd = g->lateral_dims + 1;
   size_t b = 0;
   b += (size_t)(K + g->n_x + g->n_y) * 8 + (size_t)g->n_depth * 4 + (size_t)g->n_k * (8 + 8) +
-       (size_t)Nlat * (8 + 4) + (size_t)Nlat * ((g->n_k + 31) / 32) * 4;
+       (size_t)Nlat * (8 + 4) * 2 + (size_t)g->n_k * 8 + (size_t)Nlat * ((g->n_k + 31) / 32) * 4;
   b += (size_t)N * 8 + (size_t)M * 8;            // workspace X1, W
   b += (size_t)N * 8 * 2;                        // FISTA iterates
   if (penalty == OCT_PEN_TV) b += (size_t)N * 8 * (2 * nd + 1 + nd);
@@ -597,6 +603,11 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
     const double a = -2.0 * k[m] * p->zf + om;
     ph[m] = make_float2((float)std::cos(a), (float)std::sin(a));
   }
+  std::vector<float2> ph_nd(p->Mk);
+  for (int64_t m = 0; m < p->Mk; ++m) {
+    const double a = -2.0 * k[m] * p->zf;
+    ph_nd[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
   std::vector<double> q2(p->Nlat);
   std::vector<float> beam(p->Nlat);
   auto fftfreq = [](int64_t i, int64_t n, double d) {
@@ -629,6 +640,9 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   if ((st = upload(p, &p->beam, beam)) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->deap, deap)) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->kbc, kbc)) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->phase_nd, ph_nd)) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->q2zero, std::vector<double>(p->Nlat, 0.0))) != OCT_OK) return cleanup(st);
+  if ((st = upload(p, &p->beamone, std::vector<float>(p->Nlat, 1.f))) != OCT_OK) return cleanup(st);
 
   if (mask) {
     p->mask_words = (int)((p->Mk + 31) / 32);
@@ -674,6 +688,50 @@ oct_status oct_adjoint(oct_plan_t p, const float* r, void* x, void* stream) {
   OCTCHK(run_meas_adjoint(p, r, s));
   HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
   OCTCHK(run_lat_adjoint(p, (float2*)x, s));
+  return OCT_OK;
+}
+
+oct_status oct_direct(oct_plan_t p, int32_t kind, const float* y, void* x, void* stream) {
+  if (!p || !y || !x) return fail(OCT_E_INVALID, "null argument");
+  hipStream_t s = S(stream);
+  switch (kind) {
+    case OCT_DIRECT_AXIAL:
+    case OCT_DIRECT_DISPERSION: {
+      // every A-scan as the lateral-frequency-zero column; no lateral transforms
+      HIPCHK(launch_meas_to_complex(y, p->mask, p->mask_words, (int)p->Mk, (int)p->Nlat, p->n_meas(), p->W, s));
+      NufftArgs a = nufft_args(p);
+      a.q2 = p->q2zero;
+      a.beam = p->beamone;
+      a.phase = (kind == OCT_DIRECT_AXIAL) ? p->phase_nd : p->phase;
+      HIPCHK(launch_nufft_adj(a, p->W, (float2*)x, s));
+      return OCT_OK;
+    }
+    case OCT_DIRECT_ISAM:
+      return oct_adjoint(p, y, x, stream);
+    case OCT_DIRECT_INTERP_ISAM: {
+      if (!p->yfill) OCTCHK(dev_alloc(p, &p->yfill, (size_t)p->n_meas()));
+      HIPCHK(launch_interp_fill(y, p->mask, p->mask_words, (int)p->Mk, (int)p->Nlat, p->B * p->Nlat, p->yfill, s));
+      OCTCHK(run_meas_adjoint(p, p->yfill, s, false));
+      HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+      return run_lat_adjoint(p, (float2*)x, s);
+    }
+    default:
+      return fail(OCT_E_INVALID, "unknown direct reconstruction kind");
+  }
+}
+
+oct_status oct_ncc(oct_plan_t p, const void* x, const void* z, double* r_out, void* stream) {
+  if (!p || !x || !z || !r_out) return fail(OCT_E_INVALID, "null argument");
+  hipStream_t s = S(stream);
+  const int64_t n = p->n_img();
+  const int nb = ncc_blocks(n, 2 * p->partial_cap);
+  HIPCHK(launch_ncc_sums((const float2*)x, (const float2*)z, n, p->partial, nb, p->dscal, s));
+  double h[5];
+  HIPCHK(hipMemcpyAsync(h, p->dscal, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double sxz = h[2], sxx = h[3], szz = h[4];
+  if (!(sxx > 0.0) || !(szz > 0.0)) return fail(OCT_E_INVALID, "an image has constant magnitude: NCC undefined");
+  *r_out = sxz / (std::sqrt(sxx) * std::sqrt(szz));
   return OCT_OK;
 }
 

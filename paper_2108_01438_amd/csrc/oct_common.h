@@ -128,7 +128,7 @@ struct NufftArgs {
   const float* deap;     // [Nz] 1 / Psi0((n - n_c) / K)
   const float* kbc;      // [J/2][even, odd][(OCT_KB_DEG+1)/2] KB pieces in x = 2f - 1
   FftDesc fK;
-  const float2* twK;     // two-level twiddle table of the K-point transform
+  const float2* twK;     // per-stage twiddle rows of the K-point transform
 };
 
 // Launchers (kernels in the .hip files; all asynchronous on `s`).
@@ -150,6 +150,16 @@ hipError_t launch_copy(const float2* x, float2* y, int64_t n, hipStream_t s);
 hipError_t launch_zero(float2* x, int64_t n, hipStream_t s);
 hipError_t launch_objective(const double* res_partial, int nres, const double* pen_partial,
                             int npen, double lambda, double* out, hipStream_t s);
+
+// Direct reconstructions and the NCC metric.
+hipError_t launch_meas_to_complex(const float* y, const uint32_t* mask, int words, int Mk, int Nlat, int64_t n,
+                                  float2* W, hipStream_t s);
+hipError_t launch_interp_fill(const float* y, const uint32_t* mask, int words, int Mk, int Nlat, int64_t rows,
+                              float* out, hipStream_t s);
+int ncc_blocks(int64_t n, int cap);
+// means -> dsc[0..1], centred sums (xz, xx, zz) -> dsc[2..4]; partial holds 3 * nb doubles
+hipError_t launch_ncc_sums(const float2* x, const float2* z, int64_t n, double* partial, int nb, double* dsc,
+                           hipStream_t s);
 
 // Proximal operators.
 struct ProxGeom {

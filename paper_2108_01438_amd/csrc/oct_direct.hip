@@ -1,0 +1,178 @@
+// Direct (non-iterative) reconstructions of Sec. 3.1 and the evaluation
+// metric of eq. (17).
+//
+// * The axial ("IFFT") and dispersion-corrected reconstructions of Figure 1
+//   run the adjoint column kernel on every A-scan as a lateral-frequency-zero
+//   column (beta = 2k, no beam term, no lateral transforms); this file
+//   provides the spectrum-to-complex conversion in front of it.
+// * The interpolated-ISAM baseline fills each A-scan's unobserved spectral
+//   samples by linear interpolation in k before the ISAM adjoint.
+// * NCC of magnitudes (eq. (17)) in FP64, two passes (means, then centred
+//   sums), deterministic block partials.
+#include "oct_fft.h"
+
+namespace {
+
+__device__ __forceinline__ bool observed(const uint32_t* __restrict__ mask, int words, int64_t lat, int m) {
+  return !mask || ((mask[lat * words + (m >> 5)] >> (m & 31)) & 1u);
+}
+
+// W[i] = (s_i y_i, 0) over [batch][lat][Mk]
+__global__ void meas_to_complex_kernel(const float* __restrict__ y, const uint32_t* __restrict__ mask, int words,
+                                       int Mk, int Nlat, int64_t n, float2* __restrict__ W) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t row = i / Mk;
+    const int m = (int)(i - row * Mk);
+    W[i] = make_float2(observed(mask, words, row % Nlat, m) ? y[i] : 0.f, 0.f);
+  }
+}
+
+// One block per A-scan: for every spectral pixel the last observed pixel at
+// or before it and the first at or after it (two-level scans over per-thread
+// chunks of at most 32 pixels: Mk <= 8192), then linear interpolation between
+// them; the nearest observed value outside the observed range; zero when
+// nothing is observed.
+constexpr int INTERP_MAX_MK = 8192;
+__global__ void __launch_bounds__(256) interp_fill_kernel(const float* __restrict__ y,
+                                                          const uint32_t* __restrict__ mask, int words,
+                                                          int Mk, int Nlat, float* __restrict__ out) {
+  __shared__ int lastc[256], firstc[256];
+  __shared__ short ridx[INTERP_MAX_MK];   // first observed pixel at or after m (Mk if none)
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t row = blockIdx.x;
+  const int64_t lat = row % Nlat;
+  const float* yr = y + row * Mk;
+  float* orow = out + row * Mk;
+  const int Q = (Mk + nt - 1) / nt;
+  const int c0 = min(tid * Q, Mk), c1 = min(c0 + Q, Mk);
+  int lastobs = -1, firstobs = Mk;
+  for (int m = c0; m < c1; ++m)
+    if (observed(mask, words, lat, m)) {
+      lastobs = m;
+      if (firstobs == Mk) firstobs = m;
+    }
+  lastc[tid] = lastobs;
+  firstc[tid] = firstobs;
+  __syncthreads();
+  // inclusive max-scan of lastc (left to right) and min-scan of firstc (right to left)
+  for (int off = 1; off < nt; off <<= 1) {
+    const int a = tid >= off ? lastc[tid - off] : -1;
+    const int b = tid + off < nt ? firstc[tid + off] : Mk;
+    __syncthreads();
+    lastc[tid] = max(lastc[tid], a);
+    firstc[tid] = min(firstc[tid], b);
+    __syncthreads();
+  }
+  int right = tid + 1 < nt ? firstc[tid + 1] : Mk;   // first observed after this chunk
+  for (int m = c1 - 1; m >= c0; --m) {
+    if (observed(mask, words, lat, m)) right = m;
+    ridx[m] = (short)right;
+  }
+  int left = tid > 0 ? lastc[tid - 1] : -1;          // last observed before this chunk
+  for (int m = c0; m < c1; ++m) {
+    if (observed(mask, words, lat, m)) left = m;
+    const int R = ridx[m];
+    float v;
+    if (left == m) v = yr[m];
+    else if (left < 0 && R >= Mk) v = 0.f;
+    else if (left < 0) v = yr[R];
+    else if (R >= Mk) v = yr[left];
+    else {
+      const float yl = yr[left], yh = yr[R];
+      v = fmaf((yh - yl) / (float)(R - left), (float)(m - left), yl);
+    }
+    orow[m] = v;
+  }
+}
+
+__device__ double block_sum_direct(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += sh[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double cabs_d(float2 v) {
+  return sqrt((double)v.x * (double)v.x + (double)v.y * (double)v.y);
+}
+
+// pass 0: sum |x|, sum |z|; pass 1 (means in mean[0..1]): centred products
+__global__ void __launch_bounds__(256) ncc_partial_kernel(const float2* __restrict__ x, const float2* __restrict__ z,
+                                                          int64_t n, int pass, const double* __restrict__ mean,
+                                                          double* __restrict__ partial) {
+  __shared__ double sh[8];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const double mx = pass ? mean[0] : 0.0, mz = pass ? mean[1] : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = cabs_d(x[i]) - mx, b = cabs_d(z[i]) - mz;
+    if (pass == 0) {
+      s0 += a;
+      s1 += b;
+    } else {
+      s0 += a * b;
+      s1 += a * a;
+      s2 += b * b;
+    }
+  }
+  const int nb = gridDim.x;
+  const double t0 = block_sum_direct(s0, sh), t1 = block_sum_direct(s1, sh), t2 = block_sum_direct(s2, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = t0;
+    partial[nb + blockIdx.x] = t1;
+    partial[2 * nb + blockIdx.x] = t2;
+  }
+}
+
+// out[k] = scale * sum_b partial[k * nb + b], k < 3, in block order
+__global__ void __launch_bounds__(256) ncc_reduce_kernel(const double* __restrict__ partial, int nb, double scale,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[8];
+  for (int k = 0; k < 3; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[k * nb + i];
+    const double t = block_sum_direct(s, sh);
+    if (threadIdx.x == 0) out[k] = scale * t;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_meas_to_complex(const float* y, const uint32_t* mask, int words, int Mk, int Nlat, int64_t n,
+                                  float2* W, hipStream_t s) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(meas_to_complex_kernel, dim3((int)nb), dim3(256), 0, s, y, mask, words, Mk, Nlat, n, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_fill(const float* y, const uint32_t* mask, int words, int Mk, int Nlat, int64_t rows,
+                              float* out, hipStream_t s) {
+  hipLaunchKernelGGL(interp_fill_kernel, dim3((unsigned)rows), dim3(256), 0, s, y, mask, words, Mk, Nlat, out);
+  return hipGetLastError();
+}
+
+int ncc_blocks(int64_t n, int cap) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  if (nb > cap / 3) nb = cap / 3;
+  return nb < 1 ? 1 : (int)nb;
+}
+
+hipError_t launch_ncc_sums(const float2* x, const float2* z, int64_t n, double* partial, int nb, double* dsc,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(ncc_partial_kernel, dim3(nb), dim3(256), 0, s, x, z, n, 0, (const double*)nullptr, partial);
+  hipLaunchKernelGGL(ncc_reduce_kernel, dim3(1), dim3(256), 0, s, (const double*)partial, nb, 1.0 / (double)n, dsc);
+  hipLaunchKernelGGL(ncc_partial_kernel, dim3(nb), dim3(256), 0, s, x, z, n, 1, (const double*)dsc, partial);
+  hipLaunchKernelGGL(ncc_reduce_kernel, dim3(1), dim3(256), 0, s, (const double*)partial, nb, 1.0, dsc + 2);
+  return hipGetLastError();
+}

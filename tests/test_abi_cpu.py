@@ -20,7 +20,8 @@ def _declared():
 def test_header_declares_the_entry_points():
     names = _declared()
     for n in ["oct_plan_create", "oct_plan_destroy", "oct_forward", "oct_adjoint", "oct_grad", "oct_prox",
-              "oct_mbir_solve", "oct_lipschitz", "oct_last_error", "oct_plan_footprint_bytes"]:
+              "oct_mbir_solve", "oct_lipschitz", "oct_last_error", "oct_plan_footprint_bytes", "oct_direct",
+              "oct_ncc"]:
         assert n in names
 
 
