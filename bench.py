@@ -271,6 +271,107 @@ def serving_bench(n_req: int, seed: int = 4) -> dict:
             "alone_vs_mix_bitwise_mismatches": mism, "slots": 8, "mem_budget_GiB": budget >> 30}
 
 
+def table1_bench(search_iters: int = 10, u_range=(-6.0, -0.5), coarse: int = 8) -> dict:
+    """Synthetic analogue of Table 1 (Sec. 3.2): NCC (eq. (17)) against the
+    fully sampled ISAM image for the direct reconstructions of Figure 1 and, for
+    the random / equispaced / partial sub-sampling of Sec. 3.1, the
+    interpolated-ISAM baseline and MBIR with TV and with 3-level Haar (the
+    substitute for the DT-CWT), each lambda chosen by a golden-section search
+    on the NCC, 100 FISTA iterations.  Specimens on the 2048 x 1000 B-scan:
+    sparse point scatterers (bead-like) and layered speckle (tissue-like), 1%
+    noise; measurements are synthesised with the library's own forward
+    operator.  The twelve lambda searches of a specimen run concurrently, one
+    plan and stream each."""
+    import concurrent.futures as cf
+    import numpy as np
+    import torch
+    import paper_2108_01438_amd as P
+    from paper_2108_01438_amd.tune import tune_lambda
+    import synth
+    torch.cuda.set_device(0)
+    pr = synth.preset(WORKLOAD)
+    geom = P.Geometry.from_dict(pr["geom"])
+    out = {"metric": "NCC vs fully sampled ISAM (eq. (17)); synthetic analogue of Table 1",
+           "workload": "B-scan 2048 spectral px x 1000 A-scans, 1% noise, 100 FISTA iterations, "
+                       f"lambda = 10^u lambda_max, u in [{u_range[0]}, {u_range[1]}]: {coarse}-point scan, "
+                       f"then golden-section search on NCC between the best point's neighbours "
+                       f"({search_iters} reductions)",
+           "specimens": {}}
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for spec in ("beads", "tissue"):
+        rng = np.random.default_rng({"beads": 11, "tissue": 12}[spec])
+        if spec == "beads":
+            x_true = synth.scatterers(rng, geom.img_shape, 500)
+        else:
+            x_true = np.zeros(geom.img_shape, dtype=np.complex128)
+            x_true[0, 0] = synth.layers(rng, geom.n_depth, geom.n_x, 3)
+        full = P.Plan(geom)
+        xd = torch.from_numpy(x_true.astype(np.complex64)).cuda()
+        y_clean = full.forward(xd)
+        sigma = pr["noise"] * float(y_clean.abs().max())
+        noise = torch.from_numpy(rng.standard_normal(geom.meas_shape).astype(np.float32)).cuda()
+        y_full = y_clean + sigma * noise
+        ref = full.direct(y_full, "isam")
+        row = {"fully_sampled": {k: round(full.ncc(full.direct(y_full, k), ref), 4)
+                                 for k in ("axial", "dispersion", "isam")}}
+        row["fully_sampled_vs_true"] = {k: round(full.ncc(full.direct(y_full, k), xd), 4)
+                                        for k in ("axial", "dispersion", "isam")}
+        if spec == "beads":   # kernel times of the direct reconstructions and NCC at this size
+            times = {}
+            for k in ("axial", "dispersion", "isam", "interp_isam"):
+                xo = full.direct(y_full, k)
+                torch.cuda.synchronize()
+                a.record()
+                for _ in range(20):
+                    full.direct(y_full, k, x=xo)
+                b.record()
+                torch.cuda.synchronize()
+                times[k] = round(a.elapsed_time(b) / 20, 4)
+            t0 = time.perf_counter()
+            for _ in range(20):
+                full.ncc(ref, ref)
+            times["ncc_incl_sync"] = round((time.perf_counter() - t0) / 20 * 1e3, 4)
+            out["direct_ms"] = times
+        masks = {"random": synth.mask_bernoulli(rng, (1, geom.n_x), geom.n_k, 0.5),
+                 "equispaced": synth.mask_equispaced((1, geom.n_x), geom.n_k),
+                 "partial": synth.mask_partial((1, geom.n_x), geom.n_k)}
+        jobs = []
+        for mname, mask in masks.items():
+            md = torch.from_numpy(mask.astype(np.float32)[None]).cuda()
+            y_m = y_full * md
+            pm = P.Plan(geom, mask)
+            interp = round(pm.ncc(pm.direct(y_m, "interp_isam"), ref), 4)
+            L = pm.lipschitz(50)
+            lam_max = float(pm.adjoint(y_m).abs().max())
+            row[mname] = {"interp_isam": interp}
+            for pen in ("tv", "haar"):
+                jobs.append((mname, pen, mask, y_m, 1.0 / (1.05 * L), lam_max))
+            pm.close()
+
+        def run(job):
+            mname, pen, mask, y_m, delta, lam_max = job
+            st = torch.cuda.Stream()
+            plan = P.Plan(geom, mask)
+            with torch.cuda.stream(st):
+                r = tune_lambda(plan, y_m, ref, pen, lam_max, delta, iters=100, u_range=u_range,
+                                search_iters=search_iters, coarse=coarse, stream=st)
+            st.synchronize()
+            plan.close()
+            return mname, pen, r
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+            for mname, pen, r in ex.map(run, jobs):
+                row[mname]["mbir_" + pen] = round(r["ncc"], 4)
+                row[mname]["lambda_frac_" + pen] = float("%.3g" % (10.0 ** r["u"]))
+        row["search_seconds"] = round(time.perf_counter() - t0, 2)
+        row["solves"] = len(jobs) * (coarse + search_iters + 3)
+        out["specimens"][spec] = row
+        full.close()
+        print(f"[bench] table1 {spec}: {json.dumps(row)}", file=sys.stderr, flush=True)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +382,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=0,
                     help="only run the serving benchmark with this many requests")
+    ap.add_argument("--table1", action="store_true",
+                    help="only run the synthetic analogue of Table 1 (NCC of direct, interpolated and MBIR images)")
     ap.add_argument("--phi-sizes", action="store_true",
                     help="only time Phi + Phi^H at the batch and volume sizes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -295,6 +398,9 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}))
+        return 0
+    if args.table1:
+        print(json.dumps(table1_bench()), flush=True)
         return 0
     if args.phi_sizes:
         print(json.dumps(phi_sizes_bench()), flush=True)

@@ -110,3 +110,31 @@ def test_ncc_matches_oracle():
     assert abs(plan.ncc(to_dev(z32), to_dev(z32)) - 1.0) <= 1e-12
     with pytest.raises(P.OctError):
         plan.ncc(to_dev(np.ones(O.img_shape(og), np.complex64)), to_dev(z32))
+
+
+def test_lambda_search_on_device():
+    """Golden-section search of lambda on NCC (Sec. 3.2) through oct_mbir_solve
+    and oct_ncc: the returned lambda is the best evaluated one, inside the
+    range, and its NCC is reproduced by a fresh solve."""
+    import torch
+    import paper_2108_01438_amd as P
+    from paper_2108_01438_amd.tune import tune_lambda
+    og, pg = both_geoms(n_depth=128, n_x=48, n_k=128)
+    rng = np.random.default_rng(43)
+    x_true = synth.scatterers(rng, O.img_shape(og), 15)
+    full = P.Plan(pg)
+    y = full.forward(to_dev(x_true.astype(np.complex64)))
+    ref = full.direct(y, "isam")
+    mask = synth.mask_equispaced((1, og.n_x), og.n_k)
+    plan = P.Plan(pg, mask)
+    ym = y * to_dev(mask.astype(np.float32)[None])
+    lam_max = float(plan.adjoint(ym).abs().max())
+    delta = 1.0 / (1.05 * plan.lipschitz(30))
+    flush("[tune] golden-section search, 6 reductions")
+    r = tune_lambda(plan, ym, ref, "l1", lam_max, delta, iters=30, u_range=(-4.0, -0.5), search_iters=6)
+    assert len(r["evaluations"]) == 8
+    assert -4.0 <= r["u"] <= -0.5
+    assert r["ncc"] == max(v for _, v in r["evaluations"])
+    z, _ = plan.mbir_solve(ym, "l1", r["lam"], 30, delta=delta)
+    assert abs(plan.ncc(z, ref) - r["ncc"]) <= 1e-12
+    torch.cuda.synchronize()
