@@ -2,6 +2,7 @@
 // and the orchestration of the kernels behind the C ABI in include/oct.h.
 #include "../../include/oct.h"
 #include "oct_common.h"
+#include "oct_fft.h"
 
 #include <cmath>
 #include <cstdio>
@@ -254,6 +255,18 @@ oct_status unsupported_sizes(const oct_geometry* g) {
   if (g->lateral_dims == 2 && (g->n_y > 4096 || !factorize((int)g->n_y, d)))
     return fail(OCT_E_UNSUPPORTED, "n_y must be 7-smooth and <= 4096");
   if (g->n_k > 8192) return fail(OCT_E_UNSUPPORTED, "n_k > 8192");
+  // the kernels' compile-time FFT paths must use the radix plan of factorize
+  {
+    constexpr int sizes[] = {OCT_CT_K_SIZES, OCT_CT_LAT_SIZES};
+    for (int n : sizes) {
+      FftDesc f;
+      factorize(n, f);
+      const CtPlan c = ct_plan(n);
+      bool same = c.ns == f.nstages;
+      for (int s = 0; same && s < c.ns; ++s) same = c.r[s] == f.radix[s];
+      if (!same) return fail(OCT_E_UNSUPPORTED, "internal: compile-time FFT plan differs from the host plan");
+    }
+  }
   // every FFT stage must fit the butterflies-per-thread limit of a 1024-thread block
   for (int64_t n : {K, g->n_x, g->lateral_dims == 2 ? g->n_y : (int64_t)1}) {
     FftDesc f;

@@ -7,6 +7,10 @@
 #define OCT_MAX_STAGES 16
 #define OCT_KB_DEG 9             // degree of each KB polynomial piece
 #define OCT_MAX_J 8
+// transform lengths with compile-time FFT code: oversampled grids (sigma = 2
+// on 512 .. 4096 depth samples) and lateral lengths of the common scan sizes
+#define OCT_CT_K_SIZES 1024, 2048, 4096, 8192
+#define OCT_CT_LAT_SIZES 64, 128, 256, 512, 1000, 1024
 
 // Division of a 32-bit unsigned by a runtime constant d >= 1 through a
 // multiply-high (Granlund-Montgomery round-up method): with l = ceil(log2 d),

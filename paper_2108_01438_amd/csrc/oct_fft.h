@@ -265,3 +265,117 @@ __device__ __forceinline__ void fft_rows(float2* buf, int nrows, int rowstride, 
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Compile-time transform lengths.  For the lengths a kernel instantiates, the
+// radix plan, every stride, the butterfly counts and the k = j mod Ns
+// divisions are constants: LDS offsets fold into the instructions (paired
+// reads and writes), and the index arithmetic of the generic path disappears.
+// The radix plan is the host's (factorize in oct_api.cpp): radix 8 with a 4
+// (or 4 x 4) instead of a trailing 2, then 5, 3, 7; the twiddle rows are the
+// host's too (offsets from the descriptor).
+// ---------------------------------------------------------------------------
+struct CtPlan {
+  int ns;
+  int r[OCT_MAX_STAGES];
+};
+constexpr CtPlan ct_plan(int n) {
+  CtPlan p{};
+  int m = n, a = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  const int q = a / 3, rem = a % 3;
+  if (rem == 1 && q >= 1) {
+    for (int i = 0; i < q - 1; ++i) p.r[p.ns++] = 8;
+    p.r[p.ns++] = 4;
+    p.r[p.ns++] = 4;
+  } else {
+    for (int i = 0; i < q; ++i) p.r[p.ns++] = 8;
+    if (rem == 1) p.r[p.ns++] = 2;
+    if (rem == 2) p.r[p.ns++] = 4;
+  }
+  const int odd[3] = {5, 3, 7};
+  for (int i = 0; i < 3; ++i)
+    while (m % odd[i] == 0) { m /= odd[i]; p.r[p.ns++] = odd[i]; }
+  return p;
+}
+constexpr int ct_ns_before(const CtPlan& p, int s) {
+  int v = 1;
+  for (int i = 0; i < s; ++i) v *= p.r[i];
+  return v;
+}
+
+template <int R, int N, int NS, int MAXB, bool INV>
+__device__ __forceinline__ void fft_stage_ct(float2* buf, int nrows, int rowstride,
+                                             const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr int NQ = fft_tw_pad(R) / 2;
+  constexpr int nb = N / R;
+  const int total = nrows * nb;
+  float2 v[MAXB][R];
+  float4 wq[MAXB][NQ];
+  int base[MAXB], jj[MAXB];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int item = tid + b * nthr;
+    if (item < total) {
+      const int row = item / nb;
+      const int j = item - row * nb;
+      if (NS > 1) {
+        const int k = j % NS;
+        const float4* tp = reinterpret_cast<const float4*>(tw) + k * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) wq[b][q] = tp[q];
+      }
+      base[b] = row * rowstride;
+      const float2* src = buf + base[b] + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = src[r * nb];
+      jj[b] = j;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int item = tid + b * nthr;
+    if (item < total) {
+      const int j = jj[b], k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float4 q = wq[b][(r - 1) >> 1];
+          float2 w = ((r - 1) & 1) ? make_float2(q.z, q.w) : make_float2(q.x, q.y);
+          if (INV) w.y = -w.y;
+          v[b][r] = cmul(v[b][r], w);
+        }
+      }
+      Dft<R, INV>::run(v[b]);
+      float2* dst = buf + base[b] + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * NS] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int S, int MAXB, bool INV>
+__device__ __forceinline__ void fft_ct_stages(float2* buf, int nrows, int rowstride, const FftDesc& d,
+                                              const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr CtPlan P = ct_plan(N);
+  if constexpr (S < P.ns) {
+    fft_stage_ct<P.r[S], N, ct_ns_before(P, S), MAXB, INV>(buf, nrows, rowstride, tw + d.tw_off[S], tid, nthr);
+    fft_ct_stages<N, S + 1, MAXB, INV>(buf, nrows, rowstride, d, tw, tid, nthr);
+  }
+}
+
+// fft_rows with a compile-time path for each length in SIZES (the generic
+// path serves every other length).
+template <bool ONE, bool INV, int... SIZES>
+__device__ __forceinline__ void fft_rows_sized(float2* buf, int nrows, int rowstride, const FftDesc& d,
+                                               const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr int MB = FftCfg<ONE>::MAXB;
+  bool done = false;
+  ((!done && d.n == SIZES ? (fft_ct_stages<SIZES, 0, MB, INV>(buf, nrows, rowstride, d, tw, tid, nthr),
+                              done = true)
+                          : false), ...);
+  if (!done) fft_rows<ONE, INV>(buf, nrows, rowstride, d, tw, tid, nthr);
+}
+

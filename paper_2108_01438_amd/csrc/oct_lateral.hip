@@ -150,8 +150,8 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     __syncthreads();
   }
 
-  if (a.inverse) fft_rows<ONE, true>(lds, nrow_t, rs, a.fd, twl, tid, nthr);
-  else fft_rows<ONE, false>(lds, nrow_t, rs, a.fd, twl, tid, nthr);
+  if (a.inverse) fft_rows_sized<ONE, true, OCT_CT_LAT_SIZES>(lds, nrow_t, rs, a.fd, twl, tid, nthr);
+  else fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, nrow_t, rs, a.fd, twl, tid, nthr);
 
   if (MODE == LAT_FFT || MODE == LAT_ADJ_MEAS) {
     for (int idx = tid; idx < n; idx += nthr) {
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
         lds[p * rs + l] = make_float2(ra, rb);
       });
     __syncthreads();
-    fft_rows<ONE, false>(lds, H, rs, a.fd, twl, tid, nthr);
+    fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, H, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(unpack_real_pair(lds, rs, L, H, t, l), a.scale2);
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
         lds[t * rs + l] = make_float2(r, 0.f);
       });
     __syncthreads();
-    fft_rows<ONE, false>(lds, T, rs, a.fd, twl, tid, nthr);
+    fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, T, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
         lds[t * rs + l] = xn;
       });
     __syncthreads();
-    fft_rows<ONE, false>(lds, T, rs, a.fd, twl, tid, nthr);
+    fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, T, rs, a.fd, twl, tid, nthr);
     for (int idx = tid; idx < n; idx += nthr) {
       const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = lds[t * rs + l];

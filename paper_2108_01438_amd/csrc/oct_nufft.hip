@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
                 grid[idx] = cscale(v.v, v.d);
               });
   __syncthreads();
-  fft_rows<ONE, false>(grid, 1, K, a.fK, twl, tid, nthr);
+  fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(grid, 1, K, a.fK, twl, tid, nthr);
 
   const double q2 = a.q2[lat];
   const float bq = a.beam[lat];
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
   }
   __syncthreads();
 
-  fft_rows<ONE, true>(grid, 1, K, a.fK, twl, tid, nthr);
+  fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(grid, 1, K, a.fK, twl, tid, nthr);
   float2* __restrict__ dst = X + (int64_t)col * Nz;
   batched_for(Nz, tid, nthr, [&](int n) { return a.deap[n]; }, [&](int n, float d) {
     int idx = n - nc;
