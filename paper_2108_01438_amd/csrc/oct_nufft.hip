@@ -54,6 +54,43 @@ __device__ __forceinline__ float kb_tap(const float* __restrict__ kc, int j, flo
   return fmaf(xs, o, e);
 }
 
+// weight of a compile-time tap j for fraction coordinate x; the coefficients
+// are uniform (read once into scalar registers)
+template <int J, int j>
+__device__ __forceinline__ float kb_tap_ct(const float* __restrict__ kbc, float x) {
+  constexpr bool lo = j < J / 2;
+  constexpr int jj = lo ? j : J - 1 - j;
+  const float xs = lo ? x : -x;
+  const float* c = kbc + jj * 2 * KBH;
+  const float x2 = xs * xs;
+  float e = c[KBH - 1], o = c[2 * KBH - 1];
+#pragma unroll
+  for (int d = KBH - 2; d >= 0; --d) {
+    e = fmaf(e, x2, c[d]);
+    o = fmaf(o, x2, c[KBH + d]);
+  }
+  return fmaf(xs, o, e);
+}
+
+// Cell u's sum over its samples, tap-major: the samples whose tap j covers u
+// are those with floor(t) = u + J/2 - 1 - j, a run [F_i, F_{i+1}) of the
+// first-contributor table (i = J - 1 - j, F_i = first[u - umin + i]); the
+// taps go from j = J - 1 down to 0, i.e. the samples in increasing m.
+template <int J, int I>
+__device__ __forceinline__ void adj_cell_taps(const float* __restrict__ kbc, const short* F, const float* xm,
+                                              const float2* us, float2& s) {
+  if constexpr (I < J) {
+    constexpr int j = J - 1 - I;
+    for (int m = F[I]; m < F[I + 1]; ++m) {   // one sample, rarely two
+      const float w = kb_tap_ct<J, j>(kbc, xm[m]);
+      const float2 uv = us[m];
+      s.x = fmaf(w, uv.x, s.x);
+      s.y = fmaf(w, uv.y, s.y);
+    }
+    adj_cell_taps<J, I + 1>(kbc, F, xm, us, s);
+  }
+}
+
 // Filter H(m, q) = beam(q) e^{j(-2 k_m z_f + Omega_m)} e^{j beta (z_f - n_c dz)}.
 // ph = a.phase[m] (read by the caller, batched with the sample's other loads)
 __device__ __forceinline__ float2 filter_h(const NufftArgs& a, float2 ph, float bq, double beta) {
@@ -227,10 +264,20 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
       const int u = pbeg + tid + i * nthr;
       if (u < pend) {
         const int key = u - J / 2;   // first contributor: smallest m with bm[m] >= key
-        int p = mf;
         if (nph == 1) {
-          p = (u <= umax) ? (int)first[u - umin] : Mk;   // cells past umax have no samples
-        } else if (mf < Mk) {
+          if (u <= umax) {   // cells past umax have no samples
+            const int c = u - umin;
+            short F[J + 1];
+#pragma unroll
+            for (int q = 0; q <= J; ++q) F[q] = (c + q < span) ? first[c + q] : (short)Mk;
+            float2 sacc = acc[i];
+            adj_cell_taps<J, 0>(a.kbc, F, xm, us, sacc);
+            acc[i] = sacc;
+          }
+          continue;
+        }
+        int p = mf;
+        if (mf < Mk) {
           // invert t = ct sqrt(4 k^2 - q^2) for the starting sample, then walk
           // to the exact boundary on the stored base cells
           const double bta = fmax((double)key, 0.0) / a.ct;
