@@ -63,7 +63,7 @@ __all__ = [
     "prox_tv", "tv_value", "haar_forward", "haar_inverse", "haar_detail_mask",
     "prox_haar", "haar_value", "penalty_value", "splitmix64", "counter_uniform",
     "power_start", "lipschitz", "step_size", "fista_momenta", "fista",
-    "lambda_max", "paper_backward_nx1", "ncc", "direct_axial", "direct_isam", "interp_fill",
+    "lambda_max", "paper_backward_nx1", "paper_backward", "adjoint_complex", "ncc", "direct_axial", "direct_isam", "interp_fill",
     "interp_isam", "PEN_L1", "PEN_TV", "PEN_HAAR",
 ]
 
@@ -345,7 +345,14 @@ def adjoint(r: np.ndarray, g: Geometry, mask=None, exact: bool = False,
     r = np.asarray(r, dtype=np.float64).reshape(meas_shape(g))
     if mask is not None:
         r = r * np.asarray(mask, dtype=np.float64)[None]
-    Rh = sfft.fftn(r.astype(np.complex128), axes=_lat_axes(g)) / _n_lat(g)
+    return adjoint_complex(r.astype(np.complex128), g, exact=exact, chunk=chunk)
+
+
+def adjoint_complex(R: np.ndarray, g: Geometry, exact: bool = False, chunk: int = 256) -> np.ndarray:
+    """Adjoint of the model before its real part, K^H (D Q)^H diag(e^{-j Omega}),
+    applied to complex spectra R (shape of the measurement)."""
+    R = np.asarray(R, dtype=np.complex128).reshape(meas_shape(g))
+    Rh = sfft.fftn(R, axes=_lat_axes(g)) / _n_lat(g)
     rows = Rh.reshape(-1, g.n_k)
     q2 = np.broadcast_to(q_squared(g)[None], img_shape(g)[:3]).reshape(-1)
     X = np.empty((rows.shape[0], g.n_depth), dtype=np.complex128)
@@ -611,9 +618,11 @@ def fista_momenta(iters: int) -> np.ndarray:
 
 
 def fista(y, g: Geometry, mask, pen: int, lam: float, delta: float, iters: int,
-          tv_inner: int = 10, haar_levels: int = 3, x0=None):
+          tv_inner: int = 10, haar_levels: int = 3, x0=None, backward: str = "exact"):
     """FISTA of eq. (15): z^k = prox_{lam delta R}(x^k - delta grad D(x^k)),
     t update, x^{k+1} = z^k + (t^k - 1)/t^{k+1} (z^k - z^{k-1}).
+    backward="paper" takes the gradient with the paper's backward operator
+    (eq. (10)-(11)) in place of the exact adjoint.
     Returns (z^K, history) with history[k] = 1/2 ||Phi x^k - y||^2 + lam R(z^k)."""
     x = np.zeros(img_shape(g), dtype=np.complex128) if x0 is None \
         else np.array(x0, dtype=np.complex128).reshape(img_shape(g))
@@ -624,7 +633,14 @@ def fista(y, g: Geometry, mask, pen: int, lam: float, delta: float, iters: int,
     axes = _img_axes(g)
     hist = np.empty(iters)
     for k in range(iters):
-        gr, res = grad(x, y, g, mask)
+        if backward == "paper":
+            yy = np.asarray(y, dtype=np.float64).reshape(meas_shape(g))
+            if mask is not None:
+                yy = yy * np.asarray(mask, dtype=np.float64)[None]
+            res = forward(x, g, mask) - yy
+            gr = paper_backward(res, g, mask)
+        else:
+            gr, res = grad(x, y, g, mask)
         v = x - delta * gr
         if pen == PEN_L1:
             z = prox_l1(v, tau)
@@ -638,6 +654,19 @@ def fista(y, g: Geometry, mask, pen: int, lam: float, delta: float, iters: int,
         x = z + mu[k] * (z - z_prev)
         z_prev = z
     return z_prev, hist
+
+
+def paper_backward(r: np.ndarray, g: Geometry, mask=None, exact: bool = False) -> np.ndarray:
+    """The paper's backward operator, eq. (10)-(11): K^H D^H Q^T diag(e^{-j Omega})
+    A(s . y) with A(z) = Re z - j H(z), the conjugate analytic signal; the
+    Hilbert transform runs along the spectral axis of every A-scan (reading:
+    the discrete analytic signal, FFT with the negative frequencies removed and
+    the positive ones doubled)."""
+    from scipy.signal import hilbert
+    r = np.asarray(r, dtype=np.float64).reshape(meas_shape(g))
+    if mask is not None:
+        r = r * np.asarray(mask, dtype=np.float64)[None]
+    return adjoint_complex(np.conj(hilbert(r, axis=-1)), g, exact=exact)
 
 
 def lambda_max(y, g: Geometry, mask=None) -> float:
