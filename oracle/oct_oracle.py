@@ -33,7 +33,8 @@ design notes of the repository):
   m_c = (M_k-1)/2.
 * The adjoint is the exact transpose of Phi under <a,b> = Re(a^H b); the
   paper's Hilbert-transform backward operator (eq. (10)-(11)) is provided
-  separately (``paper_backward_nx1``) to quantify how it differs.
+  separately (``paper_backward``, and its literal single-A-scan chain
+  ``paper_backward_nx1``), with a FISTA and a power iteration that use it.
 * Regularisers (Sec. 2.2, eq. (12)-(14)): l1 (Psi = I), isotropic TV (complex,
   Neumann forward differences, FGP inner solver with a fixed inner count and a
   warm-started dual), 3-level orthonormal Haar on the detail bands (the
@@ -584,14 +585,21 @@ def power_start(g: Geometry, seed: int = 0) -> np.ndarray:
     return (re + 1j * im).reshape(img_shape(g))
 
 
-def lipschitz(g: Geometry, mask=None, iters: int = 50, seed: int = 0, start=None) -> float:
+def lipschitz(g: Geometry, mask=None, iters: int = 50, seed: int = 0, start=None,
+              backward: str = "exact") -> float:
     """Power iteration on Phi^H Phi: x_0 = s/||s||, w = Phi^H Phi x_{i-1},
-    L_i = ||w||, x_i = w / L_i; returns L_iters."""
+    L_i = ||w||, x_i = w / L_i; returns L_iters.  backward="paper" iterates
+    the operator the paper's gradient uses, Phi* Phi with Phi* of eq. (10)-(11)
+    (not self-adjoint: L_iters then tends to its spectral radius), so that the
+    step size of Sec. 2.3 bounds the steps actually taken."""
     x = power_start(g, seed) if start is None else np.asarray(start, dtype=np.complex128)
     x = x / np.linalg.norm(x)
     L = 0.0
     for _ in range(iters):
-        w = adjoint(forward(x, g, mask), g, mask)
+        if backward == "paper":
+            w = paper_backward(forward(x, g, mask), g, mask)
+        else:
+            w = adjoint(forward(x, g, mask), g, mask)
         L = float(np.linalg.norm(w))
         x = w / L
     return L

@@ -157,6 +157,26 @@ def test_dense_matrix_transpose_and_lipschitz():
     assert L50 <= L * (1 + 1e-12)
 
 
+def test_paper_power_iteration_is_the_spectral_radius():
+    """With backward="paper" the power iteration tends to the spectral radius of
+    the real-linear map Phi* Phi (dense 2N x 2N matrix, eigenvalues by LAPACK),
+    which on a masked B-scan exceeds the exact L = sigma_max(Phi)^2."""
+    g = O.Geometry(n_depth=8, n_x=4, n_k=12)
+    rng = np.random.default_rng(7)
+    mask = (rng.random((1, 4, 12)) < 0.7).astype(np.uint8)
+    n = int(np.prod(O.img_shape(g)))
+    cols = []
+    for j in range(2 * n):
+        e = np.zeros(n, dtype=complex)
+        e[j % n] = 1.0 if j < n else 1j
+        w = O.paper_backward(O.forward(e.reshape(O.img_shape(g)), g, mask), g, mask).ravel()
+        cols.append(np.concatenate([w.real, w.imag]))
+    rho = float(np.max(np.abs(np.linalg.eigvals(np.array(cols).T))))
+    Lp = O.lipschitz(g, mask, iters=2000, backward="paper")
+    assert abs(Lp - rho) / rho < 1e-9
+    assert rho > 1.2 * O.lipschitz(g, mask, iters=2000)
+
+
 # --- the paper's literal D Q chain at a single A-scan --------------------------
 @pytest.mark.parametrize("nz,mk", [(32, 32), (32, 64), (64, 48)])
 def test_single_ascan_equals_literal_DQ_chain(nz, mk):
