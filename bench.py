@@ -372,6 +372,64 @@ def table1_bench(search_iters: int = 10, u_range=(-6.0, -0.5), coarse: int = 8) 
     return out
 
 
+def paper_backward_bench(steps: int = 100, reps: int = 50) -> dict:
+    """The paper's backward operator (eq. (10)-(11)) against the exact adjoint on
+    the full B-scan: one application each, a FISTA-TV solve of `steps`
+    iterations each (each with the step size of its own normal operator), the
+    two power-iteration constants and the NCC of each solution with the
+    specimen."""
+    import numpy as np
+    import torch
+    import paper_2108_01438_amd as P
+    import synth
+    torch.cuda.set_device(0)
+    geom, pr, x_true, mask, noise = make_workload(P, synth, torch)
+    plan = P.Plan(geom, mask)
+    mask_d = torch.from_numpy(mask.astype(np.float32)[None]).cuda()
+    xt = torch.from_numpy(x_true.astype(np.complex64)).cuda()
+    y_clean = plan.forward(xt)
+    sigma = pr["noise"] * float(y_clean.abs().max().item())
+    y = ((y_clean + sigma * torch.from_numpy(noise.astype(np.float32)).cuda()) * mask_d).contiguous()
+    lam = pr["lam"] * float(plan.adjoint(y).abs().max().item())
+    xbuf = torch.empty(geom.img_shape, dtype=torch.complex64, device="cuda")
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    out = {"workload": "B-scan 2048 spectral px x 1000 A-scans, 50% random mask, TV lambda=0.005 lambda_max, "
+                       "10 FGP steps"}
+    out["adjoint_ms"] = round(timed(lambda: plan.adjoint(y, xbuf), reps), 5)
+    out["adjoint_paper_ms"] = round(timed(lambda: plan.adjoint_paper(y, xbuf), reps), 5)
+    for name, pb in (("exact", False), ("paper", True)):
+        L = plan.lipschitz(50, seed=0, paper_backward=pb)
+        delta = 1.0 / (1.05 * L)
+        plan.mbir_solve(y, "tv", lam, 5, delta=delta, tv_inner=10, paper_backward=pb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        z, info = plan.mbir_solve(y, "tv", lam, steps, delta=delta, tv_inner=10, paper_backward=pb,
+                                  objective=True)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = {"L": round(L, 4), "ms_per_iteration": round(e0.elapsed_time(e1) / steps, 5),
+                     "objective_first": round(float(info["objective"][0]), 4),
+                     "objective_last": round(float(info["objective"][-1]), 4),
+                     "ncc_vs_specimen": round(plan.ncc(z, xt), 5)}
+        out[name + "_z"] = z
+    ze, zp = out.pop("exact_z"), out.pop("paper_z")
+    out["rel_diff_solutions"] = round(float((zp - ze).abs().pow(2).sum().sqrt() / ze.abs().pow(2).sum().sqrt()), 5)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +444,8 @@ def main() -> int:
                     help="only run the synthetic analogue of Table 1 (NCC of direct, interpolated and MBIR images)")
     ap.add_argument("--phi-sizes", action="store_true",
                     help="only time Phi + Phi^H at the batch and volume sizes")
+    ap.add_argument("--paper-backward", action="store_true",
+                    help="only compare the paper's backward operator with the exact adjoint (cost and solutions)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (counter calibration)")
     args = ap.parse_args()
@@ -404,6 +464,9 @@ def main() -> int:
         return 0
     if args.phi_sizes:
         print(json.dumps(phi_sizes_bench()), flush=True)
+        return 0
+    if args.paper_backward:
+        print(json.dumps(paper_backward_bench(args.steps)), flush=True)
         return 0
     if args.serving > 0:
         import torch

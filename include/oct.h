@@ -104,6 +104,17 @@ oct_status oct_forward(oct_plan_t plan, const void* x, float* y, void* stream);
  * masked on use), x: image (written). */
 oct_status oct_adjoint(oct_plan_t plan, const float* r, void* x, void* stream);
 
+/* x = Phi* r, the backward operator of eq. (10)-(11):
+ * K^H D^H Q^T diag(e^{-j Omega}) A(s . r) with A(z) = Re z - j H(z), H the
+ * Hilbert transform along the spectral axis of every A-scan, taken as the
+ * discrete analytic signal (DFT over the n_k samples, negative frequencies
+ * removed, positive ones below the Nyquist bin doubled, inverse DFT).  The
+ * lateral and NUFFT parts are those of oct_adjoint.  Phi* is not the adjoint
+ * of oct_forward: the two differ by the spectral-edge leakage of the
+ * analytic signal.  r: measurement (read, masked on use), x: image (written).
+ * OCT_E_UNSUPPORTED when n_k has a prime factor above 7. */
+oct_status oct_adjoint_paper(oct_plan_t plan, const float* r, void* x, void* stream);
+
 /* g = Phi^H (Phi x - y), the gradient of eq. (2)-(3).  half_resid_sq: device
  * double, receives 1/2 ||diag(s)(Phi x - y)||^2 summed over the batch;
  * may be NULL. */
@@ -128,9 +139,17 @@ oct_status oct_prox(oct_plan_t plan, int32_t penalty, double lambda, double delt
  * Sec. 2.3): x_0 = u / ||u|| with u from the SplitMix64 counter generator
  * (element e: real part u(2e), imaginary part u(2e+1), u uniform in [-1,1)
  * from the top 53 bits), then iters steps of x <- w / ||w||, w = Phi^H Phi x.
- * Writes the last ||w|| to *L_out (host).  Synchronous. */
-oct_status oct_lipschitz(oct_plan_t plan, int32_t iters, uint64_t seed, double* L_out,
-                         void* stream);
+ * flags = OCT_SOLVE_PAPER_BACKWARD iterates Phi* Phi instead (Phi* of
+ * oct_adjoint_paper; not self-adjoint, ||w|| then tends to its spectral
+ * radius); 0 otherwise.  Writes the last ||w|| to *L_out (host).  Synchronous. */
+oct_status oct_lipschitz(oct_plan_t plan, int32_t iters, uint64_t seed, int32_t flags,
+                         double* L_out, void* stream);
+
+typedef enum {
+  /* gradient step with the backward operator of eq. (10)-(11) (oct_adjoint_paper)
+   * in place of the exact adjoint Phi^H */
+  OCT_SOLVE_PAPER_BACKWARD = 1
+} oct_solve_flags;
 
 typedef struct {
   int32_t penalty;        /* oct_penalty                                          */
@@ -138,10 +157,11 @@ typedef struct {
   int32_t tv_inner;       /* inner FGP steps for TV (>= 1)                        */
   int32_t haar_levels;    /* Haar levels (>= 1)                                   */
   int32_t power_iters;    /* power-iteration steps when delta <= 0               */
-  int32_t reserved;
+  int32_t flags;          /* OR of oct_solve_flags (0: exact adjoint gradient)    */
   uint64_t seed;          /* power-iteration start vector seed                    */
   double lambda;          /* regularisation weight (absolute)                     */
-  double delta;           /* step size; <= 0 selects 1 / (1.05 L_power)          */
+  double delta;           /* step size; <= 0 selects 1 / (1.05 L_power), L_power
+                             from oct_lipschitz with these flags                  */
   const void* x0;         /* device image, start point; NULL = zero               */
 } oct_solve_params;
 
@@ -153,7 +173,8 @@ typedef struct {
 } oct_solve_report;
 
 /* FISTA (Sec. 2.3, eq. (15)): x^1 = x0, z^0 = x^1, t^1 = 1;
- * z^k = prox(x^k - delta Phi^H(Phi x^k - y)); t^{k+1} = (1 + sqrt(1 + 4 t_k^2))/2;
+ * z^k = prox(x^k - delta Phi^H(Phi x^k - y)) (with OCT_SOLVE_PAPER_BACKWARD:
+ * Phi*(Phi x^k - y), the operator of oct_adjoint_paper); t^{k+1} = (1 + sqrt(1 + 4 t_k^2))/2;
  * x^{k+1} = z^k + (t^k - 1)/t^{k+1} (z^k - z^{k-1}).  Writes z^K to x_out.
  * y: measurement (read), x_out: image (written).  Synchronous when a report
  * with an objective array or a power iteration is requested, otherwise

@@ -21,6 +21,8 @@ PEN_L1, PEN_TV, PEN_HAAR = 0, 1, 2
 PENALTIES = {"l1": PEN_L1, "tv": PEN_TV, "haar": PEN_HAAR}
 # direct reconstructions of Sec. 3.1 (oct_direct_kind)
 DIRECT = {"axial": 0, "dispersion": 1, "isam": 2, "interp_isam": 3}
+# oct_solve_flags
+SOLVE_PAPER_BACKWARD = 1
 
 
 class OctError(RuntimeError):
@@ -43,7 +45,7 @@ class _CGeometry(ctypes.Structure):
 class _CSolveParams(ctypes.Structure):
     _fields_ = [("penalty", ctypes.c_int32), ("iters", ctypes.c_int32), ("tv_inner", ctypes.c_int32),
                 ("haar_levels", ctypes.c_int32), ("power_iters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64), ("lambda_", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("seed", ctypes.c_uint64), ("lambda_", ctypes.c_double),
                 ("delta", ctypes.c_double), ("x0", ctypes.c_void_p)]
 
 
@@ -66,10 +68,12 @@ def _load():
         "oct_plan_footprint_bytes": ([ctypes.POINTER(_CGeometry), ctypes.c_int32], ctypes.c_size_t),
         "oct_forward": ([P, P, P, P], ctypes.c_int),
         "oct_adjoint": ([P, P, P, P], ctypes.c_int),
+        "oct_adjoint_paper": ([P, P, P, P], ctypes.c_int),
         "oct_grad": ([P, P, P, P, P, P], ctypes.c_int),
         "oct_prox": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                       P, P, P, P], ctypes.c_int),
-        "oct_lipschitz": ([P, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
+        "oct_lipschitz": ([P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), P],
+                          ctypes.c_int),
         "oct_mbir_solve": ([P, P, ctypes.POINTER(_CSolveParams), P, ctypes.POINTER(_CSolveReport), P],
                            ctypes.c_int),
         "oct_run_stage": ([P, ctypes.c_int32, ctypes.c_int32, P, P], ctypes.c_int),
@@ -210,6 +214,18 @@ class Plan:
                                 _dev(x, torch.complex64, g.img_shape, "x"), ctypes.c_void_p(_stream_ptr(stream))))
         return x
 
+    def adjoint_paper(self, r, x=None, stream=None):
+        """x = Phi* r, the backward operator of eq. (10)-(11) (conjugate analytic
+        signal along k in place of the real part's adjoint)."""
+        import torch
+        g = self.geom
+        if x is None:
+            x = torch.empty(g.img_shape, dtype=torch.complex64, device=r.device)
+        _check(_lib.oct_adjoint_paper(self._h, _dev(r, torch.float32, g.meas_shape, "r"),
+                                      _dev(x, torch.complex64, g.img_shape, "x"),
+                                      ctypes.c_void_p(_stream_ptr(stream))))
+        return x
+
     def direct(self, y, kind: str, x=None, stream=None):
         """Direct reconstruction of the measurement y: "axial" (IFFT),
         "dispersion" (dispersion corrected), "isam" or "interp_isam"."""
@@ -272,22 +288,27 @@ class Plan:
         yp = None if y is None else _dev(y, torch.float32, self.geom.meas_shape, "y")
         _check(_lib.oct_run_stage(self._h, st, pen, yp, ctypes.c_void_p(_stream_ptr(stream))))
 
-    def lipschitz(self, iters: int = 50, seed: int = 0, stream=None) -> float:
+    def lipschitz(self, iters: int = 50, seed: int = 0, paper_backward: bool = False, stream=None) -> float:
+        """Power iteration on Phi^H Phi (on Phi* Phi with paper_backward=True)."""
         out = ctypes.c_double()
-        _check(_lib.oct_lipschitz(self._h, int(iters), ctypes.c_uint64(seed), ctypes.byref(out),
+        flags = SOLVE_PAPER_BACKWARD if paper_backward else 0
+        _check(_lib.oct_lipschitz(self._h, int(iters), ctypes.c_uint64(seed), flags, ctypes.byref(out),
                                   ctypes.c_void_p(_stream_ptr(stream))))
         return out.value
 
     def mbir_solve(self, y, penalty, lam: float, iters: int, delta: float = 0.0, tv_inner: int = 10,
                    haar_levels: int = 3, power_iters: int = 50, seed: int = 0, x0=None, x_out=None,
-                   objective: bool = False, stream=None):
-        """FISTA; returns (z^K, info) with info = {delta, lipschitz, objective (np.ndarray or None)}."""
+                   objective: bool = False, paper_backward: bool = False, stream=None):
+        """FISTA; returns (z^K, info) with info = {delta, lipschitz, objective (np.ndarray or None)}.
+        paper_backward=True takes each gradient with the backward operator of
+        eq. (10)-(11) (adjoint_paper) instead of the exact adjoint."""
         import torch
         g = self.geom
         pen = PENALTIES[penalty] if isinstance(penalty, str) else int(penalty)
         if x_out is None:
             x_out = torch.empty(g.img_shape, dtype=torch.complex64, device=y.device)
-        prm = _CSolveParams(pen, int(iters), int(tv_inner), int(haar_levels), int(power_iters), 0,
+        prm = _CSolveParams(pen, int(iters), int(tv_inner), int(haar_levels), int(power_iters),
+                            SOLVE_PAPER_BACKWARD if paper_backward else 0,
                             int(seed), float(lam), float(delta),
                             None if x0 is None else _dev(x0, torch.complex64, g.img_shape, "x0").value)
         obj = np.zeros(iters, dtype=np.float64) if objective else None
@@ -299,4 +320,4 @@ class Plan:
 
 
 __all__ = ["Geometry", "Plan", "OctError", "footprint_bytes", "last_error", "LIB_PATH",
-           "PEN_L1", "PEN_TV", "PEN_HAAR", "PENALTIES", "DIRECT"]
+           "PEN_L1", "PEN_TV", "PEN_HAAR", "PENALTIES", "DIRECT", "SOLVE_PAPER_BACKWARD"]

@@ -171,8 +171,9 @@ struct oct_plan {
   int64_t Nz = 0, Nx = 0, Ny = 1, Mk = 0, B = 1, Nlat = 0, K = 0;
   int nc = 0, J = 6;
   double dk = 0, dz = 0, zf = 0, kbb = 0, ct = 0, df = 0;
-  FftDesc fK{}, fX{}, fY{};
+  FftDesc fK{}, fX{}, fY{}, fM{};
   float2 *twK = nullptr, *twX = nullptr, *twY = nullptr;
+  float2* twM = nullptr;         // spectral-axis transform of the analytic signal, built on first use
   float* deap = nullptr;
   double* k2x4 = nullptr;
   float2* phase = nullptr;
@@ -190,7 +191,7 @@ struct oct_plan {
   double* q2zero = nullptr;      // [Nlat] zeros
   float* beamone = nullptr;      // [Nlat] ones
   float2* phase_nd = nullptr;    // [Mk] e^{-j 2 k_m z_f} (no dispersion phase)
-  float* yfill = nullptr;        // [batch][lat][Mk], allocated on first use
+  float* yfill = nullptr;        // [batch][lat][Mk] real spectra (filled / residual), allocated on first use
   // solver state, allocated on first use
   float2 *za = nullptr, *zb = nullptr;
   float2 *p0 = nullptr, *p1 = nullptr, *tvwork = nullptr;
@@ -411,6 +412,62 @@ oct_status run_meas_adjoint(oct_plan* p, const float* r, hipStream_t s, bool use
     HIPCHK(launch_lateral(LAT_FFT, b, s));
   }
   return OCT_OK;
+}
+
+// r -> W = F_lat A(s . r) / N_lat, A(z) = conj of the analytic signal along k (eq. (10)-(11))
+oct_status ensure_analytic(oct_plan* p) {
+  if (p->twM) return OCT_OK;
+  FftDesc f;
+  if (p->Mk > 8192 || !factorize((int)p->Mk, f))
+    return fail(OCT_E_UNSUPPORTED, "the analytic signal needs a 7-smooth n_k <= 8192");
+  if (p->Mk / f.min_radix > (int64_t)fft_maxb(f) * 1024)
+    return fail(OCT_E_UNSUPPORTED, "n_k has too many radix-2/3 butterflies per stage");
+  OCTCHK(upload(p, &p->twM, twiddles(f)));
+  p->fM = f;
+  return OCT_OK;
+}
+
+oct_status run_meas_backward_paper(oct_plan* p, const float* r, hipStream_t s) {
+  OCTCHK(ensure_analytic(p));
+  HIPCHK(launch_analytic_conj(r, p->mask, p->mask_words, (int)p->Mk, (int)p->Nlat, p->B * p->Nlat, p->fM, p->twM,
+                              p->W, s));
+  LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+  a.src = p->W;
+  a.dst = p->W;
+  a.scale = 1.f / (float)p->Nx;
+  HIPCHK(launch_lateral(LAT_FFT, a, s));
+  if (p->lat_dims == 2) {
+    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    b.src = p->W;
+    b.dst = p->W;
+    b.scale = 1.f / (float)p->Ny;
+    HIPCHK(launch_lateral(LAT_FFT, b, s));
+  }
+  return OCT_OK;
+}
+
+// W -> W = F_lat A(s . (Re F_lat^{-1} W - y)) / N_lat with per-block sum r^2 (the paper's
+// backward operator in the normal seam); the real residual goes through yfill
+oct_status run_normal_paper(oct_plan* p, const float* y, double* partial, int* nparts, hipStream_t s) {
+  if (!p->yfill) OCTCHK(dev_alloc(p, &p->yfill, (size_t)p->n_meas()));
+  if (p->lat_dims == 2) {
+    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    b.src = p->W;
+    b.dst = p->W;
+    b.inverse = 1;
+    b.scale = 1.f / (float)p->Ny;
+    HIPCHK(launch_lateral(LAT_FFT, b, s));
+  }
+  LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+  a.src = p->W;
+  a.dstf = p->yfill;
+  a.y = y;
+  a.inverse = 1;
+  a.scale = 1.f / (float)p->Nx;
+  a.partial = partial;
+  if (nparts) *nparts = lat_blocks(a);
+  HIPCHK(launch_lateral(LAT_RESID, a, s));
+  return run_meas_backward_paper(p, p->yfill, s);
 }
 
 // W -> W = F_lat(s . (Re F_lat^{-1} W - y)) / N_lat with per-block sum r^2; returns #partials
@@ -704,6 +761,15 @@ oct_status oct_adjoint(oct_plan_t p, const float* r, void* x, void* stream) {
   return OCT_OK;
 }
 
+oct_status oct_adjoint_paper(oct_plan_t p, const float* r, void* x, void* stream) {
+  if (!p || !r || !x) return fail(OCT_E_INVALID, "null argument");
+  hipStream_t s = S(stream);
+  OCTCHK(run_meas_backward_paper(p, r, s));
+  HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+  OCTCHK(run_lat_adjoint(p, (float2*)x, s));
+  return OCT_OK;
+}
+
 oct_status oct_direct(oct_plan_t p, int32_t kind, const float* y, void* x, void* stream) {
   if (!p || !y || !x) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
@@ -784,10 +850,13 @@ oct_status oct_prox(oct_plan_t p, int32_t pen, double lambda, double delta, int3
   return run_prox(p, pen, tau, tv_inner, haar_levels, (const float2*)v, (float2*)z, nullptr, nullptr, &np, s);
 }
 
-oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, double* L_out, void* stream) {
+oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, int32_t flags, double* L_out, void* stream) {
   if (!p || !L_out || iters < 1) return fail(OCT_E_INVALID, "bad argument");
+  if (flags & ~(int32_t)OCT_SOLVE_PAPER_BACKWARD) return fail(OCT_E_INVALID, "unknown flags");
+  const bool paper = (flags & OCT_SOLVE_PAPER_BACKWARD) != 0;
   hipStream_t s = S(stream);
   OCTCHK(ensure_solver_state(p, OCT_PEN_L1, 1));
+  if (paper) OCTCHK(ensure_analytic(p));
   const int64_t n = p->n_img();
   const int nb = 1024;
   HIPCHK(launch_fill_counter_uniform(p->za, n, seed, s));
@@ -797,7 +866,8 @@ oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, double* L_o
   for (int it = 0; it < iters; ++it) {
     OCTCHK(run_lat_forward(p, p->za, nullptr, nullptr, 0.f, s));
     HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
-    OCTCHK(run_normal(p, nullptr, nullptr, nullptr, s));
+    if (paper) OCTCHK(run_normal_paper(p, nullptr, nullptr, nullptr, s));
+    else OCTCHK(run_normal(p, nullptr, nullptr, nullptr, s));
     HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
     OCTCHK(run_lat_adjoint(p, p->zb, s));
     HIPCHK(launch_norm2_partial(p->zb, n, p->partial, nb, s));
@@ -820,12 +890,14 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   if (prm->penalty == OCT_PEN_HAAR) OCTCHK(check_haar(p, prm->haar_levels));
   if (prm->penalty == OCT_PEN_TV && (prm->tv_inner < 1 || prm->tv_inner > 1000))
     return fail(OCT_E_INVALID, "tv_inner must be 1..1000");
+  if (prm->flags & ~(int32_t)OCT_SOLVE_PAPER_BACKWARD) return fail(OCT_E_INVALID, "unknown solve flags");
+  const bool paper = (prm->flags & OCT_SOLVE_PAPER_BACKWARD) != 0;
   hipStream_t s = S(stream);
   OCTCHK(ensure_solver_state(p, prm->penalty, prm->iters));
   double delta = prm->delta, Lest = 0.0;
   if (!(delta > 0)) {
     if (prm->power_iters < 1) return fail(OCT_E_INVALID, "power_iters must be >= 1 when delta <= 0");
-    OCTCHK(oct_lipschitz(p, prm->power_iters, prm->seed, &Lest, stream));
+    OCTCHK(oct_lipschitz(p, prm->power_iters, prm->seed, prm->flags, &Lest, stream));
     delta = 1.0 / (1.05 * Lest);
   }
   const int64_t n = p->n_img();
@@ -853,6 +925,11 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   float2* pin = nullptr;
   float2* pout = p->p0;
   const bool fused_l1 = (prm->penalty == OCT_PEN_L1) && p->lat_dims == 1;
+  if (paper) {
+    // set up before any work: fails when n_k does not suit the analytic-signal transform
+    OCTCHK(ensure_analytic(p));
+    if (!p->yfill) OCTCHK(dev_alloc(p, &p->yfill, (size_t)p->n_meas()));
+  }
   double* res_part = p->partial;
   double* pen_part = p->partial + p->partial_cap;
   float mu_prev = 0.f;
@@ -861,7 +938,8 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
     if (!fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s));
     HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
     int nres = 0, npen = 0;
-    OCTCHK(run_normal(p, y, res_part, &nres, s));
+    if (paper) OCTCHK(run_normal_paper(p, y, res_part, &nres, s));
+    else OCTCHK(run_normal(p, y, res_part, &nres, s));
     HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
     if (fused_l1) {
       LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);

@@ -88,8 +88,9 @@ enum LatMode {
   LAT_ADJ_MEAS = 2,   // dst = scale * FFT( s . r )                      <- float src
   LAT_NORMAL = 3,     // dst = scale2 * FFT( s . (Re(scale * IFFT(src)) - y) ), sum r^2
   LAT_UPDATE = 4,     // v = x - delta * scale * IFFT(src), x = z + mu (z - zo)
-  LAT_UPDATE_L1 = 5   // as UPDATE, then z' = soft(v), x' = z' + mu' (z' - z),
+  LAT_UPDATE_L1 = 5,  // as UPDATE, then z' = soft(v), x' = z' + mu' (z' - z),
                       // z' -> zo, dst = FFT(x')
+  LAT_RESID = 6       // dstf = s . (Re(scale * IFFT(src)) - y), sum r^2 (the residual alone)
 };
 
 struct LatArgs {
@@ -154,6 +155,10 @@ hipError_t launch_copy(const float2* x, float2* y, int64_t n, hipStream_t s);
 hipError_t launch_zero(float2* x, int64_t n, hipStream_t s);
 hipError_t launch_objective(const double* res_partial, int nres, const double* pen_partial,
                             int npen, double lambda, double* out, hipStream_t s);
+
+// Conjugate analytic signal of each A-scan's spectrum (Hilbert transform along k).
+hipError_t launch_analytic_conj(const float* r, const uint32_t* mask, int words, int Mk, int Nlat, int64_t rows,
+                                const FftDesc& fM, const float2* twM, float2* W, hipStream_t s);
 
 // Direct reconstructions and the NCC metric.
 hipError_t launch_meas_to_complex(const float* y, const uint32_t* mask, int words, int Mk, int Nlat, int64_t n,

@@ -145,7 +145,56 @@ __global__ void __launch_bounds__(256) ncc_reduce_kernel(const double* __restric
   }
 }
 
+// One block per A-scan: W = conj(analytic signal of s . r) along k, the
+// operator A(z) = Re z - j H(z) of the paper's backward operator.  The
+// analytic signal is the discrete one: forward FFT, negative frequencies
+// removed, positive ones (below the Nyquist bin) doubled, inverse FFT.
+template <bool ONE>
+__global__ void __launch_bounds__(1024) analytic_conj_kernel(const float* __restrict__ r,
+                                                             const uint32_t* __restrict__ mask, int words, int Mk,
+                                                             int Nlat, FftDesc fM, const float2* __restrict__ twM,
+                                                             float2* __restrict__ W) {
+  extern __shared__ float2 row[];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t a = blockIdx.x;
+  const int64_t lat = a % Nlat;
+  const float* ra = r + a * Mk;
+  for (int m = tid; m < Mk; m += nthr) row[m] = make_float2(observed(mask, words, lat, m) ? ra[m] : 0.f, 0.f);
+  __syncthreads();
+  fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(row, 1, Mk, fM, twM, tid, nthr);
+  const int half = Mk / 2;
+  const float inv = 1.f / (float)Mk;
+  for (int k = tid; k < Mk; k += nthr) {
+    float h;
+    if (k == 0 || ((Mk & 1) == 0 && k == half)) h = 1.f;
+    else if (k < (Mk + 1) / 2) h = 2.f;
+    else h = 0.f;
+    row[k] = cscale(row[k], h * inv);
+  }
+  __syncthreads();
+  fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(row, 1, Mk, fM, twM, tid, nthr);
+  float2* wa = W + a * Mk;
+  for (int m = tid; m < Mk; m += nthr) wa[m] = cconj(row[m]);
+}
+
 }  // namespace
+
+hipError_t launch_analytic_conj(const float* r, const uint32_t* mask, int words, int Mk, int Nlat, int64_t rows,
+                                const FftDesc& fM, const float2* twM, float2* W, hipStream_t s) {
+  const int bf = Mk / fM.min_radix;
+  const int mb = fft_maxb(fM);
+  int nt = 256;
+  while (nt < 1024 && bf > mb * nt) nt <<= 1;
+  if (bf > mb * nt) return hipErrorInvalidConfiguration;
+  const size_t lds = (size_t)Mk * sizeof(float2);
+  if (fft_one(fM, 1, nt))
+    hipLaunchKernelGGL((analytic_conj_kernel<true>), dim3((unsigned)rows), dim3(nt), lds, s, r, mask, words, Mk, Nlat,
+                       fM, twM, W);
+  else
+    hipLaunchKernelGGL((analytic_conj_kernel<false>), dim3((unsigned)rows), dim3(nt), lds, s, r, mask, words, Mk,
+                       Nlat, fM, twM, W);
+  return hipGetLastError();
+}
 
 hipError_t launch_meas_to_complex(const float* y, const uint32_t* mask, int words, int Mk, int Nlat, int64_t n,
                                   float2* W, hipStream_t s) {

@@ -101,7 +101,8 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
 
   const float2* __restrict__ twl = a.tw;
   // modes that need only real parts (or transform real rows) pair rows p and p + H
-  constexpr bool REAL_PAIRS = MODE == LAT_FWD_MEAS || MODE == LAT_ADJ_MEAS || MODE == LAT_NORMAL;
+  constexpr bool REAL_PAIRS = MODE == LAT_FWD_MEAS || MODE == LAT_ADJ_MEAS || MODE == LAT_NORMAL ||
+                               MODE == LAT_RESID;
   const bool pair = REAL_PAIRS && T >= 2;
   const int H = T >> 1;
   const int nrow_t = pair ? H : T;   // rows that go through the transforms
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       });
   }
   __syncthreads();
-  if ((MODE == LAT_FWD_MEAS || MODE == LAT_NORMAL) && pair) {
+  if ((MODE == LAT_FWD_MEAS || MODE == LAT_NORMAL || MODE == LAT_RESID) && pair) {
     pack_real_pairs(lds, H, rs, L, tid, nthr);
     __syncthreads();
   }
@@ -187,6 +188,26 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
           a.dst[base + (int64_t)l * lg.es + t] = make_float2(xr - a.delta * g.x, xi - a.delta * g.y);
         }
       });
+    return;
+  }
+  if (MODE == LAT_RESID) {
+    // residual rows only (pairs: rows p and p + H from the real and imaginary parts of row p)
+    double acc = 0.0;
+    batched_for(n, tid, nthr,
+      [&](int idx) { const int l = idx >> lt, t = min(idx & (T - 1), nr - 1);
+                     return FM{a.y ? a.y[goff(idx)] : 0.f, mword(l, r0 + t)}; },
+      [&](int idx, FM v) {
+        const int l = idx >> lt, t = idx & (T - 1);
+        if (t < nr) {
+          const float re = !pair ? lds[t * rs + l].x : (t < H ? lds[t * rs + l].x : lds[(t - H) * rs + l].y);
+          float r = 0.f;
+          if ((v.m >> ((r0 + t) & 31)) & 1u) r = re * a.scale - v.f;
+          acc += (double)r * (double)r;
+          a.dstf[base + (int64_t)l * lg.es + t] = r;
+        }
+      });
+    const double s = block_sum_d(acc, red);
+    if (tid == 0 && a.partial) a.partial[bid] = s;
     return;
   }
   if (MODE == LAT_NORMAL && pair) {
@@ -311,6 +332,7 @@ hipError_t launch_lateral_t(LatMode mode, const LatArgs& a, int nthr, hipStream_
     case LAT_NORMAL: hipLaunchKernelGGL((lat_kernel<LAT_NORMAL, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
     case LAT_UPDATE: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
     case LAT_UPDATE_L1: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE_L1, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_RESID: hipLaunchKernelGGL((lat_kernel<LAT_RESID, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
   }
   return hipGetLastError();
 }

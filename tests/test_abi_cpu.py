@@ -21,6 +21,7 @@ def test_header_declares_the_entry_points():
     names = _declared()
     for n in ["oct_plan_create", "oct_plan_destroy", "oct_forward", "oct_adjoint", "oct_grad", "oct_prox",
               "oct_mbir_solve", "oct_lipschitz", "oct_last_error", "oct_plan_footprint_bytes", "oct_direct",
+              "oct_adjoint_paper",
               "oct_ncc"]:
         assert n in names
 
