@@ -60,7 +60,8 @@ __all__ = [
     "Geometry", "kb_beta_default", "kb_kernel", "kb_kernel_standard",
     "kb_deapod", "kb_deapod_standard", "derived", "q_squared", "k_grid",
     "omega", "beta_t", "filter_H", "nufft_cols_forward", "nufft_cols_adjoint",
-    "img_shape", "meas_shape", "forward", "adjoint", "grad", "data_loss", "prox_l1", "tv_grad", "tv_div",
+    "img_shape", "meas_shape", "forward", "adjoint", "grad", "data_loss", "project_box", "prox_l1", "tv_grad", "tv_div",
+    "tv_dual_gap",
     "prox_tv", "tv_value", "haar_forward", "haar_inverse", "haar_detail_mask",
     "prox_haar", "haar_value", "penalty_value", "splitmix64", "counter_uniform",
     "power_start", "lipschitz", "step_size", "fista_momenta", "fista",
@@ -383,13 +384,27 @@ def data_loss(x, y, g: Geometry, mask=None) -> float:
 # ----------------------------------------------------------------------------
 # Proximal operators (Sec. 2.2, eq. (12)-(14); Sec. 2.3, eq. (16))
 # ----------------------------------------------------------------------------
-def prox_l1(v: np.ndarray, tau: float) -> np.ndarray:
-    """argmin_x 1/2 ||x - v||^2 + tau sum |x_i| for complex x (Psi = I, eq. (13)):
-    shrink each modulus by tau, zero when |v_i| <= tau."""
+def project_box(x: np.ndarray, bound=None) -> np.ndarray:
+    """Projection onto the constraint set C of eq. (16).  Reading: for a complex
+    image the box is a bound on each pixel's modulus, C = {x : |x_i| <= bound}
+    (a disc per pixel); bound None means C = C^N."""
+    x = np.asarray(x, dtype=np.complex128)
+    if bound is None:
+        return x.copy()
+    mag = np.abs(x)
+    return np.where(mag > bound, x * (bound / np.where(mag > 0, mag, 1.0)), x)
+
+
+def prox_l1(v: np.ndarray, tau: float, bound=None) -> np.ndarray:
+    """argmin_{x in C} 1/2 ||x - v||^2 + tau sum |x_i| for complex x (Psi = I,
+    eq. (13), (16)): shrink each modulus by tau, zero when |v_i| <= tau.  With
+    the modulus bound the problem stays separable and radial: the modulus is
+    clip(|v_i| - tau, 0, bound), i.e. the projection of the unconstrained
+    result."""
     v = np.asarray(v, dtype=np.complex128)
     mag = np.abs(v)
     scale = np.where(mag > tau, 1.0 - tau / np.where(mag > 0, mag, 1.0), 0.0)
-    return v * scale
+    return project_box(v * scale, bound)
 
 
 def _img_axes(g: Geometry):
@@ -432,12 +447,14 @@ def tv_value(x: np.ndarray, axes) -> float:
     return float(np.sum(np.sqrt(np.sum(np.abs(d) ** 2, axis=0))))
 
 
-def prox_tv(v: np.ndarray, tau: float, axes, n_inner: int, p0=None):
+def prox_tv(v: np.ndarray, tau: float, axes, n_inner: int, p0=None, bound=None):
     """Isotropic complex TV prox by the fast gradient projection (FGP) method of
     Beck and Teboulle (2009) on the dual: x = v + tau div p,
     p <- Proj_{|p_i| <= 1}( r + 1/(4 d tau) grad(v + tau div r) ), with FISTA
     momentum on p restarted each call; p0 warm-starts the dual (its entries
     without a forward neighbour, which carry no edge, are taken as zero).
+    With a constraint set C (eq. (16), modulus bound) their constrained form:
+    the primal point is P_C(v + tau div p) inside every step and at the end.
     Returns (x, p)."""
     v = np.asarray(v, dtype=np.complex128)
     nd = len(axes)
@@ -449,12 +466,12 @@ def prox_tv(v: np.ndarray, tau: float, axes, n_inner: int, p0=None):
         last[ax] = -1
         p[c][tuple(last)] = 0.0
     if tau <= 0:
-        return v.copy(), p
+        return project_box(v, bound), p
     step = 1.0 / (4.0 * nd * tau)
     r = p.copy()
     t = 1.0
     for _ in range(n_inner):
-        d = v + tau * tv_div(r, axes)
+        d = project_box(v + tau * tv_div(r, axes), bound)
         pn = r + step * tv_grad(d, axes)
         mag = np.sqrt(np.sum(np.abs(pn) ** 2, axis=0))
         pn = pn / np.maximum(1.0, mag)[None]
@@ -462,7 +479,20 @@ def prox_tv(v: np.ndarray, tau: float, axes, n_inner: int, p0=None):
         r = pn + ((t - 1.0) / tn) * (pn - p)
         p = pn
         t = tn
-    return v + tau * tv_div(p, axes), p
+    return project_box(v + tau * tv_div(p, axes), bound), p
+
+
+def tv_dual_gap(x: np.ndarray, p: np.ndarray, v: np.ndarray, tau: float, axes, bound=None) -> float:
+    """Duality gap of min_{x in C} 1/2 ||x - v||^2 + tau TV(x) at the primal x and
+    the dual p: with w = v + tau div p the dual value is
+    1/2 ||w - P_C w||^2 - 1/2 ||w||^2 + 1/2 ||v||^2 (the inner minimum over
+    x in C of the Lagrangian), the primal 1/2 ||x - v||^2 + tau TV(x)."""
+    v = np.asarray(v, dtype=np.complex128)
+    w = v + tau * tv_div(p, axes)
+    dual = 0.5 * np.sum(np.abs(w - project_box(w, bound)) ** 2) - 0.5 * np.sum(np.abs(w) ** 2) \
+        + 0.5 * np.sum(np.abs(v) ** 2)
+    primal = 0.5 * np.sum(np.abs(x - v) ** 2) + tau * tv_value(x, axes)
+    return float(primal - dual)
 
 
 def _haar_axes_sizes(x: np.ndarray, axes):
@@ -626,11 +656,12 @@ def fista_momenta(iters: int) -> np.ndarray:
 
 
 def fista(y, g: Geometry, mask, pen: int, lam: float, delta: float, iters: int,
-          tv_inner: int = 10, haar_levels: int = 3, x0=None, backward: str = "exact"):
+          tv_inner: int = 10, haar_levels: int = 3, x0=None, backward: str = "exact", bound=None):
     """FISTA of eq. (15): z^k = prox_{lam delta R}(x^k - delta grad D(x^k)),
     t update, x^{k+1} = z^k + (t^k - 1)/t^{k+1} (z^k - z^{k-1}).
     backward="paper" takes the gradient with the paper's backward operator
-    (eq. (10)-(11)) in place of the exact adjoint.
+    (eq. (10)-(11)) in place of the exact adjoint.  bound: the modulus bound of
+    the constraint set C in the prox of eq. (16) (l1 and TV; None = C^N).
     Returns (z^K, history) with history[k] = 1/2 ||Phi x^k - y||^2 + lam R(z^k)."""
     x = np.zeros(img_shape(g), dtype=np.complex128) if x0 is None \
         else np.array(x0, dtype=np.complex128).reshape(img_shape(g))
@@ -651,10 +682,12 @@ def fista(y, g: Geometry, mask, pen: int, lam: float, delta: float, iters: int,
             gr, res = grad(x, y, g, mask)
         v = x - delta * gr
         if pen == PEN_L1:
-            z = prox_l1(v, tau)
+            z = prox_l1(v, tau, bound)
         elif pen == PEN_TV:
-            z, p = prox_tv(v, tau, axes, tv_inner, p0=p)
+            z, p = prox_tv(v, tau, axes, tv_inner, p0=p, bound=bound)
         elif pen == PEN_HAAR:
+            if bound is not None:
+                raise ValueError("the constrained Haar prox has no closed form")
             z = prox_haar(v, tau, axes, haar_levels)
         else:
             raise ValueError("unknown penalty")

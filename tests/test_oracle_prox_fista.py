@@ -130,6 +130,75 @@ def test_prox_tv_warm_start_continues():
     assert np.linalg.norm(x2 - xe) < np.linalg.norm(x1 - xe)
 
 
+# --- constraint set C of eq. (16): modulus bound -------------------------------------
+def test_prox_l1_with_bound_brute_force():
+    """argmin over the disc |x| <= c of 1/2 |x - v|^2 + tau |x|, by a polar grid
+    search (modulus step 4e-4, angle step 1e-3 rad), against the closed form."""
+    rng = np.random.default_rng(70)
+    tau, c = 0.3, 0.8
+    rho = np.linspace(0.0, c, 2001)
+    th = np.linspace(-math.pi, math.pi, 6284)
+    X = rho[:, None] * np.exp(1j * th[None, :])
+    for v in list(cn(rng, 6) * 1.5) + [0.2 + 0.1j, 0.9 + 0.0j, 1.1j]:
+        f = 0.5 * np.abs(X - v) ** 2 + tau * np.abs(X)
+        i = np.unravel_index(np.argmin(f), f.shape)
+        z = O.prox_l1(np.array([v]), tau, bound=c)[0]
+        assert abs(z - X[i]) < 2e-3, (v, z, X[i])
+        assert abs(z) <= c * (1 + 1e-15)
+    # no bound, and a bound the result never reaches, are the same map
+    v = cn(rng, 50)
+    np.testing.assert_array_equal(O.prox_l1(v, tau), O.prox_l1(v, tau, bound=100.0))
+
+
+@pytest.mark.parametrize("axes,shape", [((3, 2), (1, 1, 12, 16)), ((3, 2, 1), (1, 4, 5, 6))])
+def test_prox_tv_with_bound_duality_gap_vanishes(axes, shape):
+    """Constrained TV prox (FGP with P_C in every step): the duality gap of
+    min_{|x_i| <= c} 1/2||x - v||^2 + tau TV(x) falls to rounding, the result is
+    feasible, and projecting the unconstrained prox afterwards is not optimal
+    (its gap stays large).  An inactive bound changes nothing."""
+    rng = np.random.default_rng(71)
+    v = cn(rng, shape) * 1.5
+    tau, c = 0.3, 0.4
+    gaps = []
+    for n_inner in (10, 100, 3000):
+        x, p = O.prox_tv(v, tau, axes, n_inner, bound=c)
+        assert np.max(np.abs(x)) <= c * (1 + 1e-12)
+        gaps.append(O.tv_dual_gap(x, p, v, tau, axes, bound=c))
+    assert gaps[0] > gaps[1] > max(gaps[2], 0.0) - 1e-12
+    assert abs(gaps[2]) < 1e-9 * np.sum(np.abs(v) ** 2)
+    xu, pu = O.prox_tv(v, tau, axes, 3000)
+    assert O.tv_dual_gap(O.project_box(xu, c), pu, v, tau, axes, bound=c) > 1e3 * abs(gaps[2]) + 1e-3
+    big = 10.0 * np.max(np.abs(v))
+    xb, pb = O.prox_tv(v, tau, axes, 20, bound=big)
+    x0, p0 = O.prox_tv(v, tau, axes, 20)
+    np.testing.assert_array_equal(xb, x0)
+
+
+def test_fista_l1_with_bound_kkt():
+    """Long-run constrained l1 FISTA on the dense problem: feasible, and the KKT
+    conditions of min_{|x_i| <= c} D(x) + lam ||x||_1 hold: |g_i| <= lam at
+    zeros, g_i = -lam z_i/|z_i| strictly inside the disc, and on its edge -g_i
+    points along z_i with modulus >= lam."""
+    g, mask, A, y = _dense_problem()
+    L = np.linalg.svd(A, compute_uv=False)[0] ** 2
+    delta = 1 / (1.05 * L)
+    lam, c = 0.05, 0.5
+    zs, _ = O.fista(y, g, mask, O.PEN_L1, lam, delta, 20000, bound=c)
+    gr, _ = O.grad(zs, y, g, mask)
+    mag = np.abs(zs)
+    assert np.all(mag <= c * (1 + 1e-12))
+    zero = mag < 1e-9
+    edge = mag > c * (1 - 1e-9)
+    inner = ~zero & ~edge
+    assert edge.any()
+    assert np.all(np.abs(gr[zero]) <= lam * (1 + 1e-6))
+    np.testing.assert_allclose(gr[inner], -lam * zs[inner] / mag[inner], atol=1e-6 * lam)
+    u = zs[edge] / mag[edge]
+    proj = np.real(np.conj(u) * -gr[edge])           # component of -g along z
+    perp = np.abs(-gr[edge] - proj * u)
+    assert np.all(proj >= lam * (1 - 1e-6)) and np.all(perp <= 1e-6 * lam)
+
+
 # --- Haar prox ----------------------------------------------------------------------
 def test_haar_single_level_hand_example():
     a = np.array([[1.0, 2.0], [3.0, 5.0]])          # a[l, n]
