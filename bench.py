@@ -444,6 +444,8 @@ def main() -> int:
                     help="only run the synthetic analogue of Table 1 (NCC of direct, interpolated and MBIR images)")
     ap.add_argument("--phi-sizes", action="store_true",
                     help="only time Phi + Phi^H at the batch and volume sizes")
+    ap.add_argument("--bound", type=float, default=0.0,
+                    help="modulus bound of the constraint set C (eq. (16)) as a fraction of max|x_true|; 0 = none")
     ap.add_argument("--paper-backward", action="store_true",
                     help="only compare the paper's backward operator with the exact adjoint (cost and solutions)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -495,16 +497,17 @@ def main() -> int:
     lam = pr["lam"] * float(plan.adjoint(y).abs().max().item())
     L = plan.lipschitz(50, seed=0)
     delta = 1.0 / (1.05 * L)
+    bound = args.bound * float(xt.abs().max().item()) if args.bound > 0 else None
     print(f"[bench] workload ready: lambda={lam:.4g} L={L:.4g}", file=sys.stderr, flush=True)
 
     # ---- whole-job throughput: one solve of `steps` iterations
-    plan.mbir_solve(y, "tv", lam, max(1, args.warmup), delta=delta, tv_inner=10)
+    plan.mbir_solve(y, "tv", lam, max(1, args.warmup), delta=delta, tv_inner=10, bound=bound)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record()
-    z, _ = plan.mbir_solve(y, "tv", lam, args.steps, delta=delta, tv_inner=10)
+    z, _ = plan.mbir_solve(y, "tv", lam, args.steps, delta=delta, tv_inner=10, bound=bound)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -579,6 +582,8 @@ def main() -> int:
         "stages": {k: {"ms": round(v["ms"], 5), "GBps": round(v["GBps"], 1)} for k, v in stages.items()},
         "roofline": roof,
     }
+    if bound is not None:
+        out["config"]["bound"] = f"|x_i| <= {args.bound} max|x_true| (constraint set C)"
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pr, x_true, mask, noise, args.cpu_iters)

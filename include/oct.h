@@ -121,8 +121,15 @@ oct_status oct_adjoint_paper(oct_plan_t plan, const float* r, void* x, void* str
 oct_status oct_grad(oct_plan_t plan, const void* x, const float* y, void* g,
                     double* half_resid_sq, void* stream);
 
-/* z = prox_{lambda delta R}(v) (eq. (16) with C = C^N).
- * OCT_PEN_L1: complex soft threshold by tau = lambda * delta.
+/* z = prox_{lambda delta R}(v) over the constraint set C of eq. (16).
+ * bound: C = {x : |x_i| <= bound} (a modulus bound per pixel, the complex
+ * form of a box) when bound > 0 and finite; 0, negative or +inf: C = C^N;
+ * NaN: OCT_E_INVALID.
+ * OCT_PEN_L1: complex soft threshold by tau = lambda * delta, then the
+ *   modulus clipped to the bound (exact: the constrained problem is radial).
+ * OCT_PEN_TV with a bound: the constrained fast gradient projection (the
+ *   primal point projected onto C in every step and at the end).
+ * OCT_PEN_HAAR with a bound: OCT_E_UNSUPPORTED (no closed form).
  * OCT_PEN_TV: isotropic TV over the depth and lateral axes (forward
  *   differences, zero at the last index), solved by tv_inner steps of the fast
  *   gradient projection on the dual; state, if not NULL, is the dual
@@ -132,7 +139,7 @@ oct_status oct_grad(oct_plan_t plan, const void* x, const float* y, void* g,
  *   axes, soft threshold on the detail bands.
  * v and z are images and may not alias. */
 oct_status oct_prox(oct_plan_t plan, int32_t penalty, double lambda, double delta,
-                    int32_t tv_inner, int32_t haar_levels, const void* v, void* z,
+                    int32_t tv_inner, int32_t haar_levels, double bound, const void* v, void* z,
                     void* state, void* stream);
 
 /* Power iteration on Phi^H Phi (the Lipschitz constant behind the step size of
@@ -162,6 +169,8 @@ typedef struct {
   double lambda;          /* regularisation weight (absolute)                     */
   double delta;           /* step size; <= 0 selects 1 / (1.05 L_power), L_power
                              from oct_lipschitz with these flags                  */
+  double bound;           /* modulus bound of the constraint set C of eq. (16)
+                             (as in oct_prox; 0 = none)                           */
   const void* x0;         /* device image, start point; NULL = zero               */
 } oct_solve_params;
 

@@ -46,7 +46,7 @@ class _CSolveParams(ctypes.Structure):
     _fields_ = [("penalty", ctypes.c_int32), ("iters", ctypes.c_int32), ("tv_inner", ctypes.c_int32),
                 ("haar_levels", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("seed", ctypes.c_uint64), ("lambda_", ctypes.c_double),
-                ("delta", ctypes.c_double), ("x0", ctypes.c_void_p)]
+                ("delta", ctypes.c_double), ("bound", ctypes.c_double), ("x0", ctypes.c_void_p)]
 
 
 class _CSolveReport(ctypes.Structure):
@@ -71,7 +71,7 @@ def _load():
         "oct_adjoint_paper": ([P, P, P, P], ctypes.c_int),
         "oct_grad": ([P, P, P, P, P, P], ctypes.c_int),
         "oct_prox": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
-                      P, P, P, P], ctypes.c_int),
+                      ctypes.c_double, P, P, P, P], ctypes.c_int),
         "oct_lipschitz": ([P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), P],
                           ctypes.c_int),
         "oct_mbir_solve": ([P, P, ctypes.POINTER(_CSolveParams), P, ctypes.POINTER(_CSolveReport), P],
@@ -264,7 +264,8 @@ class Plan:
         return g_out, resid
 
     def prox(self, penalty, lam: float, delta: float, v, z=None, state=None, tv_inner: int = 10,
-             haar_levels: int = 3, stream=None):
+             haar_levels: int = 3, bound=None, stream=None):
+        """z = prox_{lam delta R}(v) over C = {|x_i| <= bound} (bound None: no constraint)."""
         import torch
         g = self.geom
         pen = PENALTIES[penalty] if isinstance(penalty, str) else int(penalty)
@@ -274,7 +275,7 @@ class Plan:
         if state is not None:
             sp = _dev(state, torch.complex64, (g.lateral_dims + 1,) + g.img_shape, "state")
         _check(_lib.oct_prox(self._h, pen, float(lam), float(delta), int(tv_inner), int(haar_levels),
-                             _dev(v, torch.complex64, g.img_shape, "v"), _dev(z, torch.complex64, g.img_shape, "z"),
+                             0.0 if bound is None else float(bound), _dev(v, torch.complex64, g.img_shape, "v"), _dev(z, torch.complex64, g.img_shape, "z"),
                              sp, ctypes.c_void_p(_stream_ptr(stream))))
         return z
 
@@ -298,10 +299,11 @@ class Plan:
 
     def mbir_solve(self, y, penalty, lam: float, iters: int, delta: float = 0.0, tv_inner: int = 10,
                    haar_levels: int = 3, power_iters: int = 50, seed: int = 0, x0=None, x_out=None,
-                   objective: bool = False, paper_backward: bool = False, stream=None):
+                   objective: bool = False, paper_backward: bool = False, bound=None, stream=None):
         """FISTA; returns (z^K, info) with info = {delta, lipschitz, objective (np.ndarray or None)}.
         paper_backward=True takes each gradient with the backward operator of
-        eq. (10)-(11) (adjoint_paper) instead of the exact adjoint."""
+        eq. (10)-(11) (adjoint_paper) instead of the exact adjoint; bound sets the
+        constraint set C = {|x_i| <= bound} of the prox (l1, TV; None: none)."""
         import torch
         g = self.geom
         pen = PENALTIES[penalty] if isinstance(penalty, str) else int(penalty)
@@ -309,7 +311,7 @@ class Plan:
             x_out = torch.empty(g.img_shape, dtype=torch.complex64, device=y.device)
         prm = _CSolveParams(pen, int(iters), int(tv_inner), int(haar_levels), int(power_iters),
                             SOLVE_PAPER_BACKWARD if paper_backward else 0,
-                            int(seed), float(lam), float(delta),
+                            int(seed), float(lam), float(delta), 0.0 if bound is None else float(bound),
                             None if x0 is None else _dev(x0, torch.complex64, g.img_shape, "x0").value)
         obj = np.zeros(iters, dtype=np.float64) if objective else None
         rep = _CSolveReport(0.0, 0.0, obj.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if objective else None)

@@ -326,6 +326,7 @@ LatArgs lat_args(const oct_plan* p, const LineGeom& lg, bool yaxis) {
   a.n_tiles = (lg.rows + a.T - 1) / a.T;
   a.scale = 1.f;
   a.scale2 = 1.f;
+  a.bound = INFINITY;
   a.mask = p->mask;
   a.mask_words = p->mask_words;
   return a;
@@ -577,22 +578,31 @@ oct_status check_haar(const oct_plan* p, int levels) {
   return OCT_OK;
 }
 
+// Modulus bound of the constraint set C of eq. (16): > 0 and finite selects
+// C = {|x_i| <= bound}; 0, negative or +inf select C = C^N (+inf on the device).
+oct_status check_bound(double b) {
+  if (std::isnan(b)) return fail(OCT_E_INVALID, "bound is NaN");
+  return OCT_OK;
+}
+float bound_f(double b) { return (b > 0 && std::isfinite(b)) ? (float)b : INFINITY; }
+
 // z = prox(v) with FP64 partials of R(z) in p->partial[0..*np)
-oct_status run_prox(oct_plan* p, int pen, float tau, int tv_inner, int haar_levels, const float2* v, float2* z,
-                    const float2* p_in, float2* p_out, int* np, hipStream_t s) {
+oct_status run_prox(oct_plan* p, int pen, float tau, float bound, int tv_inner, int haar_levels, const float2* v,
+                    float2* z, const float2* p_in, float2* p_out, int* np, hipStream_t s) {
   ProxGeom pg = prox_geom(p);
   if (pen == OCT_PEN_L1) {
     const int nb = 1024;
-    HIPCHK(launch_prox_l1(v, z, p->n_img(), tau, p->partial, nb, s));
+    HIPCHK(launch_prox_l1(v, z, p->n_img(), tau, bound, p->partial, nb, s));
     *np = nb;
   } else if (pen == OCT_PEN_HAAR) {
+    if (bound < INFINITY) return fail(OCT_E_UNSUPPORTED, "a modulus bound with the Haar prox has no closed form");
     OCTCHK(check_haar(p, haar_levels));
     HIPCHK(launch_prox_haar(pg, haar_levels, v, z, tau, p->partial, s));
     *np = haar_partials(pg, haar_levels);
   } else if (pen == OCT_PEN_TV) {
     if (tv_inner < 1 || tv_inner > 1000) return fail(OCT_E_INVALID, "tv_inner must be 1..1000");
     std::vector<float> mom = fgp_momenta(tv_inner);
-    HIPCHK(launch_prox_tv(pg, tv_inner, mom.data(), v, z, p_in, p_out, tau, p->partial, p->tvwork, s));
+    HIPCHK(launch_prox_tv(pg, tv_inner, mom.data(), v, z, p_in, p_out, tau, bound, p->partial, p->tvwork, s));
     *np = tv_partials(pg, tv_inner);
   } else {
     return fail(OCT_E_INVALID, "unknown penalty");
@@ -828,26 +838,30 @@ oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, dou
 }
 
 oct_status oct_prox(oct_plan_t p, int32_t pen, double lambda, double delta, int32_t tv_inner, int32_t haar_levels,
-                    const void* v, void* z, void* state, void* stream) {
+                    double bound, const void* v, void* z, void* state, void* stream) {
   if (!p || !v || !z) return fail(OCT_E_INVALID, "null argument");
   if (v == z) return fail(OCT_E_INVALID, "v and z may not alias");
   if (!(lambda >= 0) || !(delta > 0)) return fail(OCT_E_INVALID, "need lambda >= 0 and delta > 0");
+  OCTCHK(check_bound(bound));
   hipStream_t s = S(stream);
   OCTCHK(ensure_solver_state(p, pen, 1));
   const float tau = (float)(lambda * delta);
+  const float bf = bound_f(bound);
   int np = 0;
   if (pen == OCT_PEN_TV) {
     if (!(tau > 0)) {
-      HIPCHK(launch_copy((const float2*)v, (float2*)z, p->n_img(), s));
+      // no TV term: z = P_C(v)
+      if (bf < INFINITY) HIPCHK(launch_prox_l1((const float2*)v, (float2*)z, p->n_img(), 0.f, bf, p->partial, 1024, s));
+      else HIPCHK(launch_copy((const float2*)v, (float2*)z, p->n_img(), s));
       return OCT_OK;
     }
     const int64_t npel = p->n_img() * (p->lat_dims + 1);
-    OCTCHK(run_prox(p, pen, tau, tv_inner, haar_levels, (const float2*)v, (float2*)z, (const float2*)state, p->p0,
-                    &np, s));
+    OCTCHK(run_prox(p, pen, tau, bf, tv_inner, haar_levels, (const float2*)v, (float2*)z, (const float2*)state,
+                    p->p0, &np, s));
     if (state) HIPCHK(launch_copy(p->p0, (float2*)state, npel, s));
     return OCT_OK;
   }
-  return run_prox(p, pen, tau, tv_inner, haar_levels, (const float2*)v, (float2*)z, nullptr, nullptr, &np, s);
+  return run_prox(p, pen, tau, bf, tv_inner, haar_levels, (const float2*)v, (float2*)z, nullptr, nullptr, &np, s);
 }
 
 oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, int32_t flags, double* L_out, void* stream) {
@@ -891,6 +905,10 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   if (prm->penalty == OCT_PEN_TV && (prm->tv_inner < 1 || prm->tv_inner > 1000))
     return fail(OCT_E_INVALID, "tv_inner must be 1..1000");
   if (prm->flags & ~(int32_t)OCT_SOLVE_PAPER_BACKWARD) return fail(OCT_E_INVALID, "unknown solve flags");
+  OCTCHK(check_bound(prm->bound));
+  const float bf = bound_f(prm->bound);
+  if (prm->penalty == OCT_PEN_HAAR && bf < INFINITY)
+    return fail(OCT_E_UNSUPPORTED, "a modulus bound with the Haar prox has no closed form");
   const bool paper = (prm->flags & OCT_SOLVE_PAPER_BACKWARD) != 0;
   hipStream_t s = S(stream);
   OCTCHK(ensure_solver_state(p, prm->penalty, prm->iters));
@@ -952,6 +970,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
       a.mu_next = (float)mu[k];
       a.delta = (float)delta;
       a.tau = tau;
+      a.bound = bf;
       a.partial = pen_part;
       npen = lat_blocks(a);
       HIPCHK(launch_lateral(LAT_UPDATE_L1, a, s));
@@ -974,13 +993,15 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
       HIPCHK(launch_lateral(LAT_UPDATE, a, s));
       // z^k -> zo (z^{k-2} is no longer needed)
       if (prm->penalty == OCT_PEN_TV && !(tau > 0)) {
-        HIPCHK(launch_copy(p->X1, zo, n, s));
+        // no TV term (its partials are zero): z = P_C(v)
+        if (bf < INFINITY) HIPCHK(launch_prox_l1(p->X1, zo, n, 0.f, bf, nullptr, 1024, s));
+        else HIPCHK(launch_copy(p->X1, zo, n, s));
         HIPCHK(launch_zero(reinterpret_cast<float2*>(pen_part), 1, s));
         npen = 1;
       } else {
         double* save = p->partial;
         p->partial = pen_part;
-        oct_status st = run_prox(p, prm->penalty, tau, prm->tv_inner, prm->haar_levels, p->X1, zo, pin, pout,
+        oct_status st = run_prox(p, prm->penalty, tau, bf, prm->tv_inner, prm->haar_levels, p->X1, zo, pin, pout,
                                  &npen, s);
         p->partial = save;
         OCTCHK(st);
@@ -1046,7 +1067,7 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
     }
     case OCT_STAGE_PROX: {
       int np = 0;
-      return run_prox(p, pen, 1e-3f, 10, 3, p->X1, p->zb, pen == OCT_PEN_TV ? p->p0 : nullptr,
+      return run_prox(p, pen, 1e-3f, INFINITY, 10, 3, p->X1, p->zb, pen == OCT_PEN_TV ? p->p0 : nullptr,
                       pen == OCT_PEN_TV ? p->p1 : nullptr, &np, s);
     }
     default:

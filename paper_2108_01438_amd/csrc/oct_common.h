@@ -117,6 +117,7 @@ struct LatArgs {
   float mu_next;         // momentum forming the next x (UPDATE_L1)
   float delta;
   float tau;
+  float bound;           // UPDATE_L1: modulus bound of the constraint set (+inf: none)
   double* partial;       // per-block FP64 partial sums (NORMAL: 1/2 r^2; UPDATE_L1: |z'|)
 };
 
@@ -175,14 +176,15 @@ struct ProxGeom {
   int B, Ny, Nx, Nz;     // image [B][Ny][Nx][Nz]
   int lateral_dims;
 };
-hipError_t launch_prox_l1(const float2* v, float2* z, int64_t n, float tau, double* partial,
+// bound: modulus bound of the constraint set C of eq. (16), +inf for C = C^N
+hipError_t launch_prox_l1(const float2* v, float2* z, int64_t n, float tau, float bound, double* partial,
                           int nblocks, hipStream_t s);
 int haar_partials(const ProxGeom& g, int levels);
 hipError_t launch_prox_haar(const ProxGeom& g, int levels, const float2* v, float2* z,
                             float tau, double* partial, hipStream_t s);
 int tv_partials(const ProxGeom& g, int n_inner);
 hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, const float2* v,
-                          float2* z, const float2* p_in, float2* p_out, float tau,
+                          float2* z, const float2* p_in, float2* p_out, float tau, float bound,
                           double* partial, float2* work, hipStream_t s);
 size_t tv_work_elems(const ProxGeom& g);
 
@@ -192,6 +194,7 @@ struct Tv2dArgs {
   int Nz, Nx, H, n_inner, CZ, CL, ntz, ntl;
   int64_t n_total;          // image elements (stride between dual components)
   float tau, step;
+  float bound;              // modulus bound of the constraint set (used when the kernel is built for it)
   float mom[TV_MAX_TILED_INNER + 1];
   const float2* v;
   float2* z;

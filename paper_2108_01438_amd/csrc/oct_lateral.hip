@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
           const float vr = z.x + a.mu * (z.x - zo.x) - a.delta * g.x;
           const float vi = z.y + a.mu * (z.y - zo.y) - a.delta * g.y;
           const float mag = sqrtf(vr * vr + vi * vi);
-          const float sc = mag > a.tau ? 1.f - a.tau / mag : 0.f;
+          const float sc = mag > a.tau ? fminf(1.f - a.tau / mag, a.bound / mag) : 0.f;
           const float2 zn = make_float2(vr * sc, vi * sc);
           acc += (double)sqrtf(zn.x * zn.x + zn.y * zn.y);
           a.zo[off] = zn;

@@ -94,13 +94,16 @@ __global__ void zero_kernel(float2* y, int64_t n) {
     y[i] = make_float2(0.f, 0.f);
 }
 
-__global__ void prox_l1_kernel(const float2* __restrict__ v, float2* z, int64_t n, float tau, double* partial) {
+// soft threshold by tau, then the modulus clipped to bound (the projection onto
+// C; exact for l1 because the constrained problem stays radial per pixel)
+__global__ void prox_l1_kernel(const float2* __restrict__ v, float2* z, int64_t n, float tau, float bound,
+                               double* partial) {
   __shared__ double sh[16];
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float2 a = v[i];
     const float mag = sqrtf(a.x * a.x + a.y * a.y);
-    const float sc = mag > tau ? 1.f - tau / mag : 0.f;
+    const float sc = mag > tau ? fminf(1.f - tau / mag, bound / mag) : 0.f;
     const float2 r = make_float2(a.x * sc, a.y * sc);
     acc += (double)sqrtf(r.x * r.x + r.y * r.y);
     z[i] = r;
@@ -328,14 +331,18 @@ __device__ __forceinline__ float2 tv_div_at(const TvIdx& d, const float2* __rest
   return acc;
 }
 
+// out = P_C(v + tau div r), P_C the modulus clip to bound (+inf: none)
 __global__ void tv_div_kernel(TvIdx d, const float2* __restrict__ v, const float2* __restrict__ r, float tau,
-                              float2* out) {
+                              float bound, float2* out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
     int iz, ix, iy;
     tv_coords(d, i, iz, ix, iy);
     const float2 dv = tv_div_at(d, r, i, iz, ix, iy);
     const float2 a = v[i];
-    out[i] = make_float2(a.x + tau * dv.x, a.y + tau * dv.y);
+    float2 x = make_float2(a.x + tau * dv.x, a.y + tau * dv.y);
+    const float m2 = x.x * x.x + x.y * x.y;
+    if (m2 > bound * bound) x = cscale(x, bound * rsqrtf(m2));
+    out[i] = x;
   }
 }
 
@@ -419,6 +426,9 @@ __device__ __forceinline__ float lane_next(float v) {
 // index along that axis, and every sample outside the image).  The step of
 // such a component is zero too, so it stays zero, and the divergence needs
 // no boundary tests: (div p)_i = p_i - p_{i-1} along each axis.
+// BOUND: the constrained FGP of Beck and Teboulle, the primal point projected
+// onto C = {|x_i| <= bound} in every step and at the end.
+template <bool BOUND>
 __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   // strip-edge exchange rows: wave w publishes its last column in xr[w + 1]
   // and its first in xd[w]; xr[0] and xd[TV_WAVES] stay zero, so every read
@@ -444,8 +454,13 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   const bool zedge = (n >= 0 && n < Nz - 1);
   const int64_t ib = (int64_t)b * Nx * Nz;
   const int64_t N = a.n_total;
-  const float tau = a.tau, step = a.step;
+  const float tau = a.tau, step = a.step, bound = a.bound;
   const float sz = zedge ? step : 0.f;
+  auto proj = [&](float2 x) __attribute__((always_inline)) {
+    if (!BOUND) return x;
+    const float sc = fminf(1.f, bound * __builtin_amdgcn_rsqf(x.x * x.x + x.y * x.y));
+    return cscale(x, sc);
+  };
   if (w == 0) xr[0][lane] = make_float2(0.f, 0.f);
   if (w == TV_WAVES - 1) xd[TV_WAVES][lane] = make_float2(0.f, 0.f);
 
@@ -484,7 +499,7 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
       const float2 lp = (s > 0) ? rl[s - 1] : xr[w][lane];
       const float dx = (rz[s].x - lane_prev(rz[s].x)) + (rl[s].x - lp.x);
       const float dy = (rz[s].y - lane_prev(rz[s].y)) + (rl[s].y - lp.y);
-      d[s] = make_float2(fmaf(tau, dx, v[s].x), fmaf(tau, dy, v[s].y));
+      d[s] = proj(make_float2(fmaf(tau, dx, v[s].x), fmaf(tau, dy, v[s].y)));
     }
     xd[w][lane] = d[0];
     __syncthreads();
@@ -527,7 +542,7 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
     const float2 lp = (s > 0) ? Pl[s - 1] : xr[w][lane];
     const float dx = (Pz[s].x - lane_prev(Pz[s].x)) + (Pl[s].x - lp.x);
     const float dy = (Pz[s].y - lane_prev(Pz[s].y)) + (Pl[s].y - lp.y);
-    z[s] = make_float2(fmaf(tau, dx, v[s].x), fmaf(tau, dy, v[s].y));
+    z[s] = proj(make_float2(fmaf(tau, dx, v[s].x), fmaf(tau, dy, v[s].y)));
   }
   xd[w][lane] = z[0];
   __syncthreads();
@@ -602,9 +617,9 @@ hipError_t launch_zero(float2* x, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_prox_l1(const float2* v, float2* z, int64_t n, float tau, double* partial, int nblocks,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(prox_l1_kernel, dim3(nblocks), dim3(256), 0, s, v, z, n, tau, partial);
+hipError_t launch_prox_l1(const float2* v, float2* z, int64_t n, float tau, float bound, double* partial,
+                          int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(prox_l1_kernel, dim3(nblocks), dim3(256), 0, s, v, z, n, tau, bound, partial);
   return hipGetLastError();
 }
 
@@ -679,8 +694,8 @@ int tv_partials(const ProxGeom& g, int n_inner) {
 
 // p_in (nullable = zero) -> p_out; z = v + tau div p_out; partial = TV(z).
 hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, const float2* v, float2* z,
-                          const float2* p_in, float2* p_out, float tau, double* partial, float2* work,
-                          hipStream_t s) {
+                          const float2* p_in, float2* p_out, float tau, float bound, double* partial,
+                          float2* work, hipStream_t s) {
   if (tv_tiled(g, n_inner)) {
     Tv2dArgs a{};
     a.Nz = g.Nz;
@@ -691,6 +706,7 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
     a.n_total = (int64_t)g.B * g.Nx * g.Nz;
     a.tau = tau;
     a.step = 1.0f / (8.0f * tau);
+    a.bound = bound;
     for (int k = 0; k < n_inner; ++k) a.mom[k] = mom[k];
     a.mom[n_inner] = 1.f;   // the last step leaves the plain dual in the kernel's P
     a.v = v;
@@ -699,7 +715,8 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
     a.pout = p_out;
     a.partial = partial;
     const int nb = a.ntz * a.ntl * g.B;
-    hipLaunchKernelGGL(tv2d_tile_kernel, dim3(nb), dim3(TV_WAVES * 64), 0, s, a);
+    if (bound < INFINITY) hipLaunchKernelGGL(tv2d_tile_kernel<true>, dim3(nb), dim3(TV_WAVES * 64), 0, s, a);
+    else hipLaunchKernelGGL(tv2d_tile_kernel<false>, dim3(nb), dim3(TV_WAVES * 64), 0, s, a);
     return hipGetLastError();
   }
   TvIdx d;
@@ -723,10 +740,10 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
   hipLaunchKernelGGL(copy_kernel, dim3(grid_for(np, 256)), dim3(256), 0, s, p_out, r, np);
   const float step = 1.0f / (4.0f * d.nd * tau);
   for (int k = 0; k < n_inner; ++k) {
-    hipLaunchKernelGGL(tv_div_kernel, dim3(gb), dim3(256), 0, s, d, v, r, tau, dd);
+    hipLaunchKernelGGL(tv_div_kernel, dim3(gb), dim3(256), 0, s, d, v, r, tau, bound, dd);
     hipLaunchKernelGGL(tv_step_kernel, dim3(gb), dim3(256), 0, s, d, dd, r, p_out, step, mom[k]);
   }
-  hipLaunchKernelGGL(tv_div_kernel, dim3(gb), dim3(256), 0, s, d, v, p_out, tau, z);
+  hipLaunchKernelGGL(tv_div_kernel, dim3(gb), dim3(256), 0, s, d, v, p_out, tau, bound, z);
   hipLaunchKernelGGL(tv_value_kernel, dim3(gb), dim3(256), 0, s, d, z, partial);
   return hipGetLastError();
 }
