@@ -60,6 +60,7 @@ __all__ = [
     "Geometry", "kb_beta_default", "kb_kernel", "kb_kernel_standard",
     "kb_deapod", "kb_deapod_standard", "derived", "q_squared", "k_grid",
     "omega", "beta_t", "filter_H", "nufft_cols_forward", "nufft_cols_adjoint",
+    "literal_cols_forward", "literal_cols_adjoint", "columns_forward", "columns_adjoint",
     "img_shape", "meas_shape", "forward", "adjoint", "grad", "data_loss", "project_box", "prox_l1", "tv_grad", "tv_div",
     "tv_dual_gap",
     "prox_tv", "tv_value", "haar_forward", "haar_inverse", "haar_detail_mask",
@@ -97,6 +98,7 @@ class Geometry:
     kb_width: int = 6                      # J
     oversamp: float = 2.0                  # sigma
     kb_beta: float = 0.0                   # <= 0: Beatty closed form
+    model: int = 0                         # 0: NUFFT at every detector wavenumber; 1: literal K, Q, D chain
 
     def with_(self, **kw) -> "Geometry":
         return replace(self, **kw)
@@ -274,6 +276,64 @@ def nufft_cols_forward(cols: np.ndarray, q2: np.ndarray, g: Geometry,
     return filter_H(g, q2) * U
 
 
+def _even_geometry(g: Geometry) -> Geometry:
+    """The N even detector wavenumbers k_{2j} = k_min + 2 j dk, j < N, with the
+    depth pitch, focus and window of g and no dispersion phase."""
+    d = derived(g)
+    n = g.n_depth
+    return g.with_(n_k=n, k_max=g.k_min + 2.0 * (n - 1) * d.dk, dz=d.dz, z_focus=d.z_f,
+                   disp_a=0.0, disp_b=0.0, model=0)
+
+
+def _check_literal(g: Geometry):
+    if g.n_k != 2 * g.n_depth:
+        raise ValueError("the literal chain has M_k = 2 N_z (Q pads N to 2N, D is 2N x 2N)")
+
+
+def literal_cols_forward(cols: np.ndarray, q2: np.ndarray, g: Geometry, exact: bool = False) -> np.ndarray:
+    """The paper's literal chain per lateral frequency, eq. (4)-(9):
+    K: the filtered spectrum f^ . x^(q, beta) sampled at the N wavenumbers of
+    the even detector pixels (the same KB NUFFT, or the plain NUDFT in exact
+    mode), u = K x its N-point inverse DFT; Q pads u with N zeros; D is the
+    2N-point DFT; then the dispersion phase e^{j Omega} of all 2N pixels.
+    Reading: with D Q reproducing the K samples at the even pixels, K samples
+    the N even wavenumbers; the odd pixels are the trigonometric interpolation
+    that D Q implies (exact at q = 0, where beta = 2k is linear in k)."""
+    _check_literal(g)
+    n = g.n_depth
+    uh = nufft_cols_forward(cols, q2, _even_geometry(g), exact=exact)      # (C, N)
+    u = sfft.ifft(uh, axis=1)
+    pad = np.zeros((cols.shape[0], 2 * n), dtype=np.complex128)
+    pad[:, :n] = u
+    return np.exp(1j * omega(g))[None, :] * sfft.fft(pad, axis=1)
+
+
+def literal_cols_adjoint(rows: np.ndarray, q2: np.ndarray, g: Geometry, exact: bool = False) -> np.ndarray:
+    """Exact adjoint of ``literal_cols_forward``: e^{-j Omega}, D^H (2N ifft x 2N),
+    Q^T (first N), the adjoint of the N-point inverse DFT (fft / N), then the
+    adjoint NUFFT at the even wavenumbers."""
+    _check_literal(g)
+    n = g.n_depth
+    w = np.exp(-1j * omega(g))[None, :] * np.asarray(rows, dtype=np.complex128)
+    u = (sfft.ifft(w, axis=1) * (2 * n))[:, :n]
+    uh = sfft.fft(u, axis=1) / n
+    return nufft_cols_adjoint(uh, q2, _even_geometry(g), exact=exact)
+
+
+def columns_forward(cols, q2, g: Geometry, exact: bool = False):
+    """Per-lateral-frequency part of the model: the direct NUFFT at every
+    detector wavenumber (model 0) or the literal chain (model 1)."""
+    if g.model == 1:
+        return literal_cols_forward(cols, q2, g, exact=exact)
+    return nufft_cols_forward(cols, q2, g, exact=exact)
+
+
+def columns_adjoint(rows, q2, g: Geometry, exact: bool = False):
+    if g.model == 1:
+        return literal_cols_adjoint(rows, q2, g, exact=exact)
+    return nufft_cols_adjoint(rows, q2, g, exact=exact)
+
+
 def nufft_cols_adjoint(rows: np.ndarray, q2: np.ndarray, g: Geometry,
                        exact: bool = False) -> np.ndarray:
     """Exact adjoint of ``nufft_cols_forward``: (C, M_k) -> (C, N_z)."""
@@ -333,7 +393,7 @@ def forward(x: np.ndarray, g: Geometry, mask=None, exact: bool = False,
     q2 = np.broadcast_to(q_squared(g)[None], img_shape(g)[:3]).reshape(-1)
     W = np.empty((cols.shape[0], g.n_k), dtype=np.complex128)
     for a, b in _chunks(cols.shape[0], chunk):
-        W[a:b] = nufft_cols_forward(cols[a:b], q2[a:b], g, exact=exact)
+        W[a:b] = columns_forward(cols[a:b], q2[a:b], g, exact=exact)
     V = sfft.ifftn(W.reshape(meas_shape(g)), axes=_lat_axes(g))
     y = V.real
     if mask is not None:
@@ -359,7 +419,7 @@ def adjoint_complex(R: np.ndarray, g: Geometry, exact: bool = False, chunk: int 
     q2 = np.broadcast_to(q_squared(g)[None], img_shape(g)[:3]).reshape(-1)
     X = np.empty((rows.shape[0], g.n_depth), dtype=np.complex128)
     for a, b in _chunks(rows.shape[0], chunk):
-        X[a:b] = nufft_cols_adjoint(rows[a:b], q2[a:b], g, exact=exact)
+        X[a:b] = columns_adjoint(rows[a:b], q2[a:b], g, exact=exact)
     return sfft.ifftn(X.reshape(img_shape(g)), axes=_lat_axes(g)) * _n_lat(g)
 
 

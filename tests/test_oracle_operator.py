@@ -212,6 +212,51 @@ def test_paper_backward_relation():
         assert np.linalg.norm(P[:, n] - c[n] * A[:, n]) < 1e-11
 
 
+# --- the paper's literal K, Q, D chain (model 1) -------------------------------
+def test_literal_chain_equals_the_direct_model_at_one_ascan():
+    """At q = 0 (one A-scan) beta = 2k is linear in k, so the spectrum sampled at
+    the even pixels and trigonometrically interpolated by D Q is exact: the
+    literal chain equals the direct model at every pixel (exact NUDFT mode,
+    with 2nd and 3rd order dispersion)."""
+    rng = np.random.default_rng(31)
+    g = O.Geometry(n_depth=32, n_x=1, n_k=64, disp_a=3e-3, disp_b=1e-5, model=1)
+    x = cn(rng, O.img_shape(g))
+    lit = O.forward(x, g, exact=True)
+    direct = O.forward(x, g.with_(model=0), exact=True)
+    assert rel(lit, direct) < 1e-12
+
+
+def test_literal_chain_even_pixels_are_the_direct_model():
+    """For any lateral frequency the even detector pixels of the literal chain
+    carry K's samples unchanged, so they equal the direct model there; the odd
+    pixels (interpolated) differ when q != 0."""
+    rng = np.random.default_rng(32)
+    g = O.Geometry(n_depth=64, n_x=24, n_k=128, model=1)
+    x = cn(rng, O.img_shape(g))
+    lit = O.forward(x, g)
+    direct = O.forward(x, g.with_(model=0))
+    assert rel(lit[..., ::2], direct[..., ::2]) < 1e-12
+    assert rel(lit[..., 1::2], direct[..., 1::2]) > 1e-3
+
+
+@pytest.mark.parametrize("kw", [dict(n_depth=32, n_x=12, n_k=64), dict(n_depth=16, n_x=6, n_y=5, lateral_dims=2, n_k=32)])
+def test_literal_chain_adjoint_identity(kw):
+    rng = np.random.default_rng(33)
+    g = O.Geometry(model=1, **kw)
+    mask = (rng.random(O.meas_shape(g)[1:]) < 0.6).astype(np.uint8)
+    x = cn(rng, O.img_shape(g))
+    r = rng.standard_normal(O.meas_shape(g))
+    a = np.sum(O.forward(x, g, mask) * r)
+    b = np.real(np.vdot(x, O.adjoint(r, g, mask)))
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_literal_chain_needs_mk_twice_nz():
+    g = O.Geometry(n_depth=32, n_x=4, n_k=48, model=1)
+    with pytest.raises(ValueError):
+        O.forward(np.zeros(O.img_shape(g), complex), g)
+
+
 # --- lateral structure ---------------------------------------------------------
 def test_lateral_shift_equivariance():
     g = O.Geometry(n_depth=32, n_x=8, n_k=32)
