@@ -75,7 +75,21 @@ typedef struct {
   double disp_a, disp_b;  /* Omega_m = a (m-m_c)^2 + b (m-m_c)^3, m_c=(M_k-1)/2   */
   double oversamp;        /* sigma; K = sigma * N_z must be an integer            */
   double kb_beta;         /* KB shape; <= 0 selects pi sqrt(J^2/s^2 (s-1/2)^2-0.8)*/
+  int32_t model;          /* oct_model: how K, Q and D of eq. (6)-(8) are formed  */
 } oct_geometry;
+
+/* The per-lateral-frequency part of Phi (eq. (5)-(8)).
+ * OCT_MODEL_DIRECT: the NUFFT evaluated at beta_m(q) = sqrt(4 k_m^2 - q^2) of
+ *   every spectrometer wavenumber, then the filter and e^{j Omega}; any n_k.
+ * OCT_MODEL_LITERAL: the paper's chain as printed, for n_k = 2 n_depth: K
+ *   samples the filtered spectrum at the N wavenumbers of the even pixels (the
+ *   same NUFFT) and takes its N-point inverse DFT, Q pads to 2N, D is the
+ *   2N-point DFT, then e^{j Omega}.  The odd pixels are the trigonometric
+ *   interpolation D Q implies (equal to the direct model at q = 0).
+ * Every entry point (forward, adjoint, gradient, solve, power iteration, the
+ * paper's backward operator, the ISAM images) follows the plan's model; the
+ * axial and dispersion-corrected images use the direct model at q = 0. */
+typedef enum { OCT_MODEL_DIRECT = 0, OCT_MODEL_LITERAL = 1 } oct_model;
 
 /* Create a plan: builds the FP64-derived tables (wavenumber grid, filter
  * phases, deapodisation, KB polynomial pieces, twiddles), packs the mask and

@@ -39,7 +39,7 @@ class _CGeometry(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                 ("z_focus", ctypes.c_double), ("beam_waist", ctypes.c_double),
                 ("disp_a", ctypes.c_double), ("disp_b", ctypes.c_double),
-                ("oversamp", ctypes.c_double), ("kb_beta", ctypes.c_double)]
+                ("oversamp", ctypes.c_double), ("kb_beta", ctypes.c_double), ("model", ctypes.c_int32)]
 
 
 class _CSolveParams(ctypes.Structure):
@@ -121,6 +121,7 @@ class Geometry:
     kb_width: int = 6
     oversamp: float = 2.0
     kb_beta: float = 0.0
+    model: int = 0            # 0: NUFFT at every detector wavenumber; 1: the literal K, Q, D chain (n_k = 2 n_depth)
 
     @classmethod
     def from_dict(cls, d: dict) -> "Geometry":
@@ -130,7 +131,7 @@ class Geometry:
     def to_c(self) -> _CGeometry:
         return _CGeometry(self.lateral_dims, self.kb_width, self.n_depth, self.n_x, self.n_y, self.n_k,
                           self.batch, self.k_min, self.k_max, self.dx, self.dy, self.dz, self.z_focus,
-                          self.beam_waist, self.disp_a, self.disp_b, self.oversamp, self.kb_beta)
+                          self.beam_waist, self.disp_a, self.disp_b, self.oversamp, self.kb_beta, self.model)
 
     @property
     def img_shape(self):

@@ -173,7 +173,15 @@ struct oct_plan {
   double dk = 0, dz = 0, zf = 0, kbb = 0, ct = 0, df = 0;
   FftDesc fK{}, fX{}, fY{}, fM{};
   float2 *twK = nullptr, *twX = nullptr, *twY = nullptr;
-  float2* twM = nullptr;         // spectral-axis transform of the analytic signal, built on first use
+  float2* twM = nullptr;         // spectral-axis transform (analytic signal; literal chain's D)
+  // literal K, Q, D chain (model 1): even-pixel NUFFT tables, the N-point transform, e^{j Omega}
+  int model = OCT_MODEL_DIRECT;
+  FftDesc fN{};
+  float2* twN = nullptr;
+  double* k2x4e = nullptr;       // [N] 4 k_{2j}^2
+  float2* phase_e = nullptr;     // [N] e^{-j 2 k_{2j} z_f}
+  float2* omph = nullptr;        // [Mk] e^{j Omega_m}
+  float2* Wn = nullptr;          // [batch][lat][N] samples of K
   float* deap = nullptr;
   double* k2x4 = nullptr;
   float2* phase = nullptr;
@@ -240,6 +248,9 @@ oct_status validate(const oct_geometry* g) {
   if (!(g->dx > 0) || (g->lateral_dims == 2 && !(g->dy > 0))) return fail(OCT_E_INVALID, "lateral pitch must be > 0");
   if (g->kb_width != 4 && g->kb_width != 6 && g->kb_width != 8)
     return fail(OCT_E_INVALID, "kb_width must be 4, 6 or 8");
+  if (g->model != OCT_MODEL_DIRECT && g->model != OCT_MODEL_LITERAL) return fail(OCT_E_INVALID, "unknown model");
+  if (g->model == OCT_MODEL_LITERAL && g->n_k != 2 * g->n_depth)
+    return fail(OCT_E_INVALID, "the literal chain needs n_k = 2 n_depth");
   if (!(g->oversamp >= 1.0)) return fail(OCT_E_INVALID, "oversamp must be >= 1");
   const double Kf = g->oversamp * (double)g->n_depth;
   if (std::fabs(Kf - std::round(Kf)) > 1e-9) return fail(OCT_E_INVALID, "oversamp * n_depth must be an integer");
@@ -256,6 +267,14 @@ oct_status unsupported_sizes(const oct_geometry* g) {
   if (g->lateral_dims == 2 && (g->n_y > 4096 || !factorize((int)g->n_y, d)))
     return fail(OCT_E_UNSUPPORTED, "n_y must be 7-smooth and <= 4096");
   if (g->n_k > 8192) return fail(OCT_E_UNSUPPORTED, "n_k > 8192");
+  if (g->model == OCT_MODEL_LITERAL) {
+    FftDesc fn, fm;
+    if (!factorize((int)g->n_depth, fn) || !factorize((int)g->n_k, fm))
+      return fail(OCT_E_UNSUPPORTED, "the literal chain needs a 7-smooth n_depth");
+    bool one;
+    if (literal_dq_threads(fn, fm, &one) == 0)
+      return fail(OCT_E_UNSUPPORTED, "n_k has too many radix-2/3 butterflies per stage");
+  }
   // the kernels' compile-time FFT paths must use the radix plan of factorize
   {
     constexpr int sizes[] = {OCT_CT_K_SIZES, OCT_CT_LAT_SIZES};
@@ -359,6 +378,41 @@ NufftArgs nufft_args(const oct_plan* p) {
 }
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// NUFFT column arguments of the literal chain's K: the N even detector
+// wavenumbers k_{2j} = k_min + 2 j dk, the focus phase without Omega
+NufftArgs even_args(const oct_plan* p) {
+  NufftArgs a = nufft_args(p);
+  a.Mk = (int)p->Nz;
+  a.dk = 2.0 * p->dk;
+  a.k2x4 = p->k2x4e;
+  a.phase = p->phase_e;
+  return a;
+}
+
+// X1 (lateral spectra of the image) -> W (spectra at the detector pixels)
+oct_status run_cols_fwd(oct_plan* p, hipStream_t s) {
+  if (p->model == OCT_MODEL_DIRECT) {
+    HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+    return OCT_OK;
+  }
+  HIPCHK(launch_nufft_fwd(even_args(p), p->X1, p->Wn, s));
+  HIPCHK(launch_literal_dq(false, p->Wn, p->W, p->omph, (int)p->Nz, p->B * p->Nlat, p->fN, p->twN, p->fM, p->twM,
+                           s));
+  return OCT_OK;
+}
+
+// W -> X1 (the exact adjoint of run_cols_fwd)
+oct_status run_cols_adj(oct_plan* p, hipStream_t s) {
+  if (p->model == OCT_MODEL_DIRECT) {
+    HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+    return OCT_OK;
+  }
+  HIPCHK(launch_literal_dq(true, p->W, p->Wn, p->omph, (int)p->Nz, p->B * p->Nlat, p->fN, p->twN, p->fM, p->twM,
+                           s));
+  HIPCHK(launch_nufft_adj(even_args(p), p->Wn, p->X1, s));
+  return OCT_OK;
+}
 
 // x (image, or z + mu (z - zo) when z != NULL) -> X1 = F_lat x
 oct_status run_lat_forward(oct_plan* p, const float2* x, const float2* z, const float2* zo, float mu, hipStream_t s) {
@@ -627,6 +681,8 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   b += (size_t)(K + g->n_x + g->n_y) * 8 + (size_t)g->n_depth * 4 + (size_t)g->n_k * (8 + 8) +
        (size_t)Nlat * (8 + 4) * 2 + (size_t)g->n_k * 8 + (size_t)Nlat * ((g->n_k + 31) / 32) * 4;
   b += (size_t)N * 8 + (size_t)M * 8;            // workspace X1, W
+  if (g->model == OCT_MODEL_LITERAL)             // K's samples and the literal chain's tables
+    b += (size_t)N * 8 + (size_t)g->n_depth * 16 + (size_t)g->n_k * 16;
   b += (size_t)N * 8 * 2;                        // FISTA iterates
   if (penalty == OCT_PEN_TV) b += (size_t)N * 8 * (2 * nd + 1 + nd);
   b += 64 * 1024 * 8;                            // partials, scalars, history
@@ -723,6 +779,31 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   if ((st = upload(p, &p->phase_nd, ph_nd)) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->q2zero, std::vector<double>(p->Nlat, 0.0))) != OCT_OK) return cleanup(st);
   if ((st = upload(p, &p->beamone, std::vector<float>(p->Nlat, 1.f))) != OCT_OK) return cleanup(st);
+  p->model = g->model;
+  if (p->model == OCT_MODEL_LITERAL) {
+    // K at the even detector wavenumbers (same grid formula as k above), the
+    // N-point and 2N-point transforms, e^{j Omega} of all pixels
+    std::vector<double> k2e(p->Nz);
+    std::vector<float2> phe(p->Nz), om(p->Mk);
+    for (int64_t j = 0; j < p->Nz; ++j) {
+      const double kj = k[2 * j];
+      k2e[j] = 4.0 * kj * kj;
+      const double a = -2.0 * kj * p->zf;
+      phe[j] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    for (int64_t m = 0; m < p->Mk; ++m) {
+      const double u = (double)m - mc;
+      const double o = g->disp_a * u * u + g->disp_b * u * u * u;
+      om[m] = make_float2((float)std::cos(o), (float)std::sin(o));
+    }
+    factorize((int)p->Nz, p->fN);
+    if ((st = upload(p, &p->twN, twiddles(p->fN))) != OCT_OK) return cleanup(st);
+    if ((st = upload(p, &p->k2x4e, k2e)) != OCT_OK) return cleanup(st);
+    if ((st = upload(p, &p->phase_e, phe)) != OCT_OK) return cleanup(st);
+    if ((st = upload(p, &p->omph, om)) != OCT_OK) return cleanup(st);
+    if ((st = ensure_analytic(p)) != OCT_OK) return cleanup(st);
+    if ((st = dev_alloc(p, &p->Wn, p->n_img())) != OCT_OK) return cleanup(st);
+  }
 
   if (mask) {
     p->mask_words = (int)((p->Mk + 31) / 32);
@@ -757,7 +838,7 @@ oct_status oct_forward(oct_plan_t p, const void* x, float* y, void* stream) {
   if (!p || !x || !y) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
   OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
-  HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+  OCTCHK(run_cols_fwd(p, s));
   OCTCHK(run_meas_forward(p, y, s));
   return OCT_OK;
 }
@@ -766,7 +847,7 @@ oct_status oct_adjoint(oct_plan_t p, const float* r, void* x, void* stream) {
   if (!p || !r || !x) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
   OCTCHK(run_meas_adjoint(p, r, s));
-  HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+  OCTCHK(run_cols_adj(p, s));
   OCTCHK(run_lat_adjoint(p, (float2*)x, s));
   return OCT_OK;
 }
@@ -775,7 +856,7 @@ oct_status oct_adjoint_paper(oct_plan_t p, const float* r, void* x, void* stream
   if (!p || !r || !x) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
   OCTCHK(run_meas_backward_paper(p, r, s));
-  HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+  OCTCHK(run_cols_adj(p, s));
   OCTCHK(run_lat_adjoint(p, (float2*)x, s));
   return OCT_OK;
 }
@@ -801,7 +882,7 @@ oct_status oct_direct(oct_plan_t p, int32_t kind, const float* y, void* x, void*
       if (!p->yfill) OCTCHK(dev_alloc(p, &p->yfill, (size_t)p->n_meas()));
       HIPCHK(launch_interp_fill(y, p->mask, p->mask_words, (int)p->Mk, (int)p->Nlat, p->B * p->Nlat, p->yfill, s));
       OCTCHK(run_meas_adjoint(p, p->yfill, s, false));
-      HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+      OCTCHK(run_cols_adj(p, s));
       return run_lat_adjoint(p, (float2*)x, s);
     }
     default:
@@ -828,11 +909,11 @@ oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, dou
   if (!p || !x || !y || !gout) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
   OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
-  HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+  OCTCHK(run_cols_fwd(p, s));
   int np = 0;
   OCTCHK(run_normal(p, y, p->partial, &np, s));
   if (half_resid_sq) HIPCHK(launch_reduce_sum(p->partial, np, half_resid_sq, 0.5, 0, s));
-  HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+  OCTCHK(run_cols_adj(p, s));
   OCTCHK(run_lat_adjoint(p, (float2*)gout, s));
   return OCT_OK;
 }
@@ -879,10 +960,10 @@ oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, int32_t fla
   HIPCHK(launch_scale_by_inv_sqrt(p->za, p->za, n, p->dscal, s));
   for (int it = 0; it < iters; ++it) {
     OCTCHK(run_lat_forward(p, p->za, nullptr, nullptr, 0.f, s));
-    HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+    OCTCHK(run_cols_fwd(p, s));
     if (paper) OCTCHK(run_normal_paper(p, nullptr, nullptr, nullptr, s));
     else OCTCHK(run_normal(p, nullptr, nullptr, nullptr, s));
-    HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+    OCTCHK(run_cols_adj(p, s));
     OCTCHK(run_lat_adjoint(p, p->zb, s));
     HIPCHK(launch_norm2_partial(p->zb, n, p->partial, nb, s));
     HIPCHK(launch_reduce_sum(p->partial, nb, p->dscal, 1.0, 0, s));
@@ -954,11 +1035,11 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   if (fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, 0.f, s));
   for (int k = 0; k < prm->iters; ++k) {
     if (!fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s));
-    HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+    OCTCHK(run_cols_fwd(p, s));
     int nres = 0, npen = 0;
     if (paper) OCTCHK(run_normal_paper(p, y, res_part, &nres, s));
     else OCTCHK(run_normal(p, y, res_part, &nres, s));
-    HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+    OCTCHK(run_cols_adj(p, s));
     if (fused_l1) {
       LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
       a.src = p->X1;
@@ -1036,7 +1117,7 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
     case OCT_STAGE_LAT_FWD:
       return run_lat_forward(p, nullptr, p->za, p->zb, 0.5f, s);
     case OCT_STAGE_NUFFT_FWD:
-      HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
+      OCTCHK(run_cols_fwd(p, s));
       return OCT_OK;
     case OCT_STAGE_NORMAL: {
       if (!y) return fail(OCT_E_INVALID, "OCT_STAGE_NORMAL needs y");
@@ -1044,7 +1125,7 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
       return run_normal(p, y, p->partial, &np, s);
     }
     case OCT_STAGE_NUFFT_ADJ:
-      HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
+      OCTCHK(run_cols_adj(p, s));
       return OCT_OK;
     case OCT_STAGE_LAT_UPDATE: {
       if (p->lat_dims == 2) {

@@ -161,6 +161,13 @@ hipError_t launch_objective(const double* res_partial, int nres, const double* p
 hipError_t launch_analytic_conj(const float* r, const uint32_t* mask, int words, int Mk, int Nlat, int64_t rows,
                                 const FftDesc& fM, const float2* twM, float2* W, hipStream_t s);
 
+// Q and D of the literal chain (M_k = 2N) per lateral-frequency column: forward
+// N samples of K -> 2N spectra with e^{j Omega}; adjoint the reverse.
+int literal_dq_threads(const FftDesc& fN, const FftDesc& fM, bool* one);
+hipError_t launch_literal_dq(bool adjoint, const float2* in, float2* out, const float2* om, int N, int64_t cols,
+                             const FftDesc& fN, const float2* twN, const FftDesc& fM, const float2* twM,
+                             hipStream_t s);
+
 // Direct reconstructions and the NCC metric.
 hipError_t launch_meas_to_complex(const float* y, const uint32_t* mask, int words, int Mk, int Nlat, int64_t n,
                                   float2* W, hipStream_t s);
