@@ -138,7 +138,7 @@ STAGE_KERNEL = {
     "normal": "lat_kernel<3, false>",
     "nufft_adj": "nufft_adj_kernel<6, true>",
     "lat_update": "lat_kernel<4, false>",
-    "prox": "tv2d_tile_kernel",
+    "prox": "tv2d_tile_kernel<false>",
 }
 STAGE_SOURCE = {
     "lat_fwd": "oct_lateral.hip", "normal": "oct_lateral.hip", "lat_update": "oct_lateral.hip",
