@@ -67,10 +67,11 @@ __all__ = [
     "prox_haar", "haar_value", "penalty_value", "splitmix64", "counter_uniform",
     "power_start", "lipschitz", "step_size", "fista_momenta", "fista",
     "lambda_max", "paper_backward_nx1", "paper_backward", "adjoint_complex", "ncc", "direct_axial", "direct_isam", "interp_fill",
-    "interp_isam", "PEN_L1", "PEN_TV", "PEN_HAAR",
+    "interp_isam", "PEN_L1", "PEN_TV", "PEN_HAAR", "PEN_DTCWT",
+    "maxflat_halfband_factor", "dtcwt_filters", "dtcwt_forward", "dtcwt_inverse", "prox_dtcwt", "dtcwt_value",
 ]
 
-PEN_L1, PEN_TV, PEN_HAAR = 0, 1, 2
+PEN_L1, PEN_TV, PEN_HAAR, PEN_DTCWT = 0, 1, 2, 3
 
 
 # ----------------------------------------------------------------------------
@@ -629,8 +630,214 @@ def haar_value(x: np.ndarray, axes, levels: int) -> float:
     return float(np.sum(np.abs(c[haar_detail_mask(c.shape, axes, levels)])))
 
 
+# ----------------------------------------------------------------------------
+# Dual-tree complex wavelet transform (Sec. 2.2, the DT-CWT of Selesnick,
+# Baraniuk and Kingsbury), 2-D, for B-scans
+# ----------------------------------------------------------------------------
+def maxflat_halfband_factor(K: int, L: int):
+    """Orthonormal lowpass pair (h, g) of Selesnick's common-factor design of
+    approximate Hilbert-transform pairs of wavelet bases: h = F D, g = F D~
+    with D the degree-L maximally flat (Thiran) allpass denominator for a
+    half-sample delay, D~(z) = z^-L D(1/z), and F = Q (1 + 1/z)^K chosen so that
+    P = H(z) H(1/z) = (z + 2 + 1/z)^K D(z) D(1/z) R(z) is halfband (p(0) = 1,
+    p(2n) = 0): a linear system for the symmetric R, whose minimum-phase
+    spectral factor is Q.  Then g(n) is approximately h(n - 1/2).  L = 0 gives
+    the Daubechies orthonormal filter with K vanishing moments.  Normalised to
+    sum sqrt(2)."""
+    d = np.array([(-1) ** n * math.comb(L, n)
+                  * np.prod([(0.5 - L + k) / (1.5 + k) for k in range(n)]) for n in range(L + 1)])
+    s = np.convolve(d, d[::-1])                         # D(z) D(1/z)
+    b = np.array([1.0])
+    for _ in range(K):
+        b = np.convolve(b, [1.0, 2.0, 1.0])            # (z + 2 + 1/z)^K
+    q0 = np.convolve(b, s)
+    M = K + L - 1                                       # R(z) = sum_{|i| <= M} r_|i| z^-i
+    nP = K + L + M
+    cols = []
+    for i in range(M + 1):
+        r = np.zeros(2 * M + 1)
+        r[M + i] = 1.0
+        r[M - i] = 1.0
+        cols.append(np.convolve(q0, r))
+    A = np.array(cols).T
+    rows = [nP + 2 * n for n in range((nP + 1) // 2)]
+    rhs = np.zeros(len(rows))
+    rhs[0] = 1.0
+    coef = np.linalg.solve(A[rows], rhs)
+    R = np.zeros(2 * M + 1)
+    R[M] = coef[0]
+    for i in range(1, M + 1):
+        R[M + i] = R[M - i] = coef[i]
+    roots = np.roots(R) if M > 0 else np.array([])
+    f = np.real(np.poly(roots[np.abs(roots) < 1.0])) if M > 0 else np.array([1.0])
+    for _ in range(K):
+        f = np.convolve(f, [1.0, 1.0])
+    h = np.convolve(f, d)
+    g = np.convolve(f, d[::-1])
+    sc = math.sqrt(2.0) / np.sum(h)
+    return h * sc, g * sc
+
+
+def dtcwt_filters():
+    """Lowpass analysis filters of the two trees.  First level: the 6-tap
+    Daubechies filter (tree a) and the same filter one sample later (tree b).
+    Later levels: the 12-tap common-factor pair (K = 3, L = 3) of
+    ``maxflat_halfband_factor``.  Every filter is padded to even length."""
+    d1, _ = maxflat_halfband_factor(3, 0)
+    first_a = np.concatenate([d1, [0.0, 0.0]])
+    first_b = np.concatenate([[0.0], d1, [0.0]])
+    ha, hb = maxflat_halfband_factor(3, 3)
+    return {"first": (first_a, first_b), "later": (ha, hb)}
+
+
+def _qmf(h):
+    """Highpass of an orthonormal even-length lowpass: (-1)^k h(L-1-k)."""
+    n = len(h)
+    return np.array([(-1) ** k * h[n - 1 - k] for k in range(n)])
+
+
+def _afb(x, h0, axis):
+    """One periodic analysis step along ``axis``: lo[i] = sum_k h0[k] x[2i + k],
+    hi[i] = sum_k h1[k] x[2i + k] (indices mod n)."""
+    x = np.moveaxis(np.asarray(x), axis, -1)
+    n = x.shape[-1]
+    h1 = _qmf(h0)
+    idx = (2 * np.arange(n // 2)[:, None] + np.arange(len(h0))[None, :]) % n
+    seg = x[..., idx]                                   # (..., n/2, L)
+    lo = np.tensordot(seg, h0, axes=([-1], [0]))
+    hi = np.tensordot(seg, h1, axes=([-1], [0]))
+    return np.moveaxis(lo, -1, axis), np.moveaxis(hi, -1, axis)
+
+
+def _sfb(lo, hi, h0, axis):
+    """Transpose (= inverse, the analysis being orthogonal) of ``_afb``."""
+    lo = np.moveaxis(np.asarray(lo), axis, -1)
+    hi = np.moveaxis(np.asarray(hi), axis, -1)
+    m = lo.shape[-1]
+    n = 2 * m
+    h1 = _qmf(h0)
+    out = np.zeros(lo.shape[:-1] + (n,), dtype=np.result_type(lo, hi, np.float64))
+    for k in range(len(h0)):
+        idx = (2 * np.arange(m) + k) % n
+        np.add.at(out, (..., idx), h0[k] * lo + h1[k] * hi)
+    return np.moveaxis(out, -1, axis)
+
+
+_DT_TREES = (("a", "a"), ("a", "b"), ("b", "a"), ("b", "b"))
+
+
+def _tree_forward(x, axes, levels, tz, tl, F):
+    """Separable orthonormal 2-D DWT of one tree (depth filters of tree tz,
+    lateral of tree tl): per level, depth then lateral analysis; returns the
+    detail bands [(lh, hl, hh) per level] and the final low band."""
+    az, al = axes
+    pick = {"a": 0, "b": 1}
+    low = x
+    bands = []
+    for lev in range(levels):
+        key = "first" if lev == 0 else "later"
+        fz, fl = F[key][pick[tz]], F[key][pick[tl]]
+        lz, hz = _afb(low, fz, az)
+        ll, lh = _afb(lz, fl, al)        # low depth: low / high lateral
+        hl, hh = _afb(hz, fl, al)        # high depth: low / high lateral
+        bands.append((lh, hl, hh))
+        low = ll
+    return bands, low
+
+
+def _tree_inverse(bands, low, axes, levels, tz, tl, F):
+    az, al = axes
+    pick = {"a": 0, "b": 1}
+    for lev in reversed(range(levels)):
+        key = "first" if lev == 0 else "later"
+        fz, fl = F[key][pick[tz]], F[key][pick[tl]]
+        lh, hl, hh = bands[lev]
+        lz = _sfb(low, lh, fl, al)
+        hz = _sfb(hl, hh, fl, al)
+        low = _sfb(lz, hz, fz, az)
+    return low
+
+
+def dtcwt_forward(x, axes, levels: int):
+    """2-D DT-CWT of x over (depth axis, lateral axis): the four separable trees
+    (depth filters of tree a or b x lateral filters of tree a or b), each
+    scaled by 1/2, and per level and detail band the orthonormal combination
+    u1 = (aa - bb)/sqrt2, v1 = (ab + ba)/sqrt2, u2 = (aa + bb)/sqrt2,
+    v2 = (ab - ba)/sqrt2: the complex coefficients u1 + j v1 and u2 + j v2 of
+    the six orientations.  For a complex image the trees act on it linearly
+    and a coefficient is the pair (u, v) of complex numbers.  Returns
+    (details [level][band] = ((u1, v1), (u2, v2)), lows {tree: band})."""
+    F = dtcwt_filters()
+    x = np.asarray(x, dtype=np.complex128)
+    tr = {t: _tree_forward(0.5 * x, axes, levels, t[0], t[1], F) for t in _DT_TREES}
+    r2 = 1.0 / math.sqrt(2.0)
+    details = []
+    for lev in range(levels):
+        per = []
+        for b in range(3):
+            aa, ab = tr[("a", "a")][0][lev][b], tr[("a", "b")][0][lev][b]
+            ba, bb = tr[("b", "a")][0][lev][b], tr[("b", "b")][0][lev][b]
+            per.append((((aa - bb) * r2, (ab + ba) * r2), ((aa + bb) * r2, (ab - ba) * r2)))
+        details.append(per)
+    lows = {t: tr[t][1] for t in _DT_TREES}
+    return details, lows
+
+
+def dtcwt_inverse(details, lows, axes, levels: int):
+    """Adjoint of ``dtcwt_forward`` (its inverse: the transform is a Parseval frame)."""
+    F = dtcwt_filters()
+    r2 = 1.0 / math.sqrt(2.0)
+    out = 0.0
+    for t in _DT_TREES:
+        bands = []
+        for lev in range(levels):
+            per = []
+            for b in range(3):
+                (u1, v1), (u2, v2) = details[lev][b]
+                aa, bb = (u1 + u2) * r2, (u2 - u1) * r2
+                ab, ba = (v1 + v2) * r2, (v1 - v2) * r2
+                per.append({("a", "a"): aa, ("a", "b"): ab, ("b", "a"): ba, ("b", "b"): bb}[t])
+            bands.append(tuple(per))
+        out = out + 0.5 * _tree_inverse(bands, lows[t], axes, levels, t[0], t[1], F)
+    return out
+
+
+def _dtcwt_axes(x, axes):
+    if len(axes) != 2:
+        raise ValueError("the DT-CWT here is 2-D (B-scans)")
+    return axes
+
+
+def prox_dtcwt(v, tau: float, axes, levels: int):
+    """W^T soft(W v) for the DT-CWT W: every complex coefficient (u, v) of the
+    detail bands shrinks its modulus sqrt(|u|^2 + |v|^2) by tau, the low bands
+    are kept.  (W is a Parseval frame, not a basis: this is the usual
+    shrinkage step for the DT-CWT penalty, exact for an orthonormal W.)"""
+    axes = _dtcwt_axes(v, axes)
+    details, lows = dtcwt_forward(v, axes, levels)
+    out = []
+    for per in details:
+        pb = []
+        for pair in per:
+            q = []
+            for u, w in pair:
+                mag = np.sqrt(np.abs(u) ** 2 + np.abs(w) ** 2)
+                sc = np.where(mag > tau, 1.0 - tau / np.where(mag > 0, mag, 1.0), 0.0)
+                q.append((u * sc, w * sc))
+            pb.append(tuple(q))
+        out.append(pb)
+    return dtcwt_inverse(out, lows, axes, levels)
+
+
+def dtcwt_value(x, axes, levels: int) -> float:
+    """||W x||_1 over the detail bands: the sum of the coefficient moduli."""
+    details, _ = dtcwt_forward(x, _dtcwt_axes(x, axes), levels)
+    return float(sum(np.sum(np.sqrt(np.abs(u) ** 2 + np.abs(w) ** 2))
+                     for per in details for pair in per for u, w in pair))
+
+
 def penalty_value(x: np.ndarray, g: Geometry, pen: int, haar_levels: int = 3) -> float:
-    """R(x) of eq. (12) for the three regularisers."""
+    """R(x) of eq. (12) for the regularisers (haar_levels also sets the DT-CWT levels)."""
     x = np.asarray(x, dtype=np.complex128).reshape(img_shape(g))
     if pen == PEN_L1:
         return float(np.sum(np.abs(x)))
@@ -638,6 +845,8 @@ def penalty_value(x: np.ndarray, g: Geometry, pen: int, haar_levels: int = 3) ->
         return tv_value(x, _img_axes(g))
     if pen == PEN_HAAR:
         return haar_value(x, _img_axes(g), haar_levels)
+    if pen == PEN_DTCWT:
+        return dtcwt_value(x, _img_axes(g), haar_levels)
     raise ValueError("unknown penalty")
 
 
@@ -749,6 +958,10 @@ def fista(y, g: Geometry, mask, pen: int, lam: float, delta: float, iters: int,
             if bound is not None:
                 raise ValueError("the constrained Haar prox has no closed form")
             z = prox_haar(v, tau, axes, haar_levels)
+        elif pen == PEN_DTCWT:
+            if bound is not None:
+                raise ValueError("the constrained DT-CWT step has no closed form")
+            z = prox_dtcwt(v, tau, axes, haar_levels)
         else:
             raise ValueError("unknown penalty")
         hist[k] = 0.5 * float(np.sum(res * res)) + lam * penalty_value(z, g, pen, haar_levels)
