@@ -430,6 +430,54 @@ def paper_backward_bench(steps: int = 100, reps: int = 50) -> dict:
     return out
 
 
+def penalties_bench(steps: int = 100, reps: int = 20) -> dict:
+    """The four regularisers on the full B-scan workload (2048 x 1000, 50%
+    random mask): per penalty the prox alone (HIP events, `reps` calls), one
+    FISTA solve of `steps` iterations, and the NCC of its result with the
+    specimen.  lambda = 0.01 lambda_max (l1, Haar, DT-CWT), 0.005 (TV);
+    3 wavelet levels, 10 FGP steps."""
+    import numpy as np
+    import torch
+    import paper_2108_01438_amd as P
+    import synth
+    torch.cuda.set_device(0)
+    geom, pr, x_true, mask, noise = make_workload(P, synth, torch)
+    plan = P.Plan(geom, mask)
+    mask_d = torch.from_numpy(mask.astype(np.float32)[None]).cuda()
+    xt = torch.from_numpy(x_true.astype(np.complex64)).cuda()
+    yc = plan.forward(xt)
+    sigma = pr["noise"] * float(yc.abs().max().item())
+    y = ((yc + sigma * torch.from_numpy(noise.astype(np.float32)).cuda()) * mask_d).contiguous()
+    lmax = float(plan.adjoint(y).abs().max().item())
+    delta = 1.0 / (1.05 * plan.lipschitz(50, seed=0))
+    v = plan.adjoint(y)
+    zbuf = torch.empty_like(v)
+    out = {"workload": "B-scan 2048 spectral px x 1000 A-scans, 50% random mask; 3 wavelet levels, 10 FGP steps"}
+    for pen, frac in (("l1", 0.01), ("tv", 0.005), ("haar", 0.01), ("dtcwt", 0.01)):
+        lam = frac * lmax
+        for _ in range(3):
+            plan.prox(pen, lam, delta, v, zbuf, haar_levels=3)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            plan.prox(pen, lam, delta, v, zbuf, haar_levels=3)
+        b.record()
+        torch.cuda.synchronize()
+        prox_ms = a.elapsed_time(b) / reps
+        plan.mbir_solve(y, pen, lam, 5, delta=delta, tv_inner=10, haar_levels=3)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        z, _ = plan.mbir_solve(y, pen, lam, steps, delta=delta, tv_inner=10, haar_levels=3)
+        e1.record()
+        torch.cuda.synchronize()
+        out[pen] = {"lambda_frac": frac, "prox_ms": round(prox_ms, 5),
+                    "ms_per_iteration": round(e0.elapsed_time(e1) / steps, 5),
+                    "ncc_vs_specimen": round(plan.ncc(z, xt), 5)}
+    return out
+
+
 def literal_bench(steps: int = 100, reps: int = 50) -> dict:
     """The paper's literal K, Q, D chain (model 1) against the direct model on a
     B-scan in the paper's sizing (M_k = 2 N_z: 1024 depth samples, 1000 A-scans,
@@ -504,6 +552,8 @@ def main() -> int:
                     help="only time Phi + Phi^H at the batch and volume sizes")
     ap.add_argument("--bound", type=float, default=0.0,
                     help="modulus bound of the constraint set C (eq. (16)) as a fraction of max|x_true|; 0 = none")
+    ap.add_argument("--penalties", action="store_true",
+                    help="only compare the four regularisers (prox time, FISTA time, NCC) on the B-scan workload")
     ap.add_argument("--literal", action="store_true",
                     help="only compare the paper's literal K, Q, D chain with the direct model (M_k = 2 N_z)")
     ap.add_argument("--paper-backward", action="store_true",
@@ -526,6 +576,9 @@ def main() -> int:
         return 0
     if args.phi_sizes:
         print(json.dumps(phi_sizes_bench()), flush=True)
+        return 0
+    if args.penalties:
+        print(json.dumps(penalties_bench(args.steps)), flush=True)
         return 0
     if args.literal:
         print(json.dumps(literal_bench(args.steps)), flush=True)

@@ -57,7 +57,7 @@ typedef enum {
 
 /* Regularisers R of Sec. 2.2: l1 with Psi = I (eq. (13)), isotropic total
  * variation (eq. (14)), and a multi-level orthonormal Haar wavelet l1. */
-typedef enum { OCT_PEN_L1 = 0, OCT_PEN_TV = 1, OCT_PEN_HAAR = 2 } oct_penalty;
+typedef enum { OCT_PEN_L1 = 0, OCT_PEN_TV = 1, OCT_PEN_HAAR = 2, OCT_PEN_DTCWT = 3 } oct_penalty;
 
 /* Acquisition geometry (Sec. 2.1, eq. (4)-(9); optics of Sec. 3.1). */
 typedef struct {
@@ -151,10 +151,23 @@ oct_status oct_grad(oct_plan_t plan, const void* x, const float* y, void* g,
  *   overwritten with the new dual; NULL starts from zero.
  * OCT_PEN_HAAR: haar_levels-level orthonormal Haar over the depth and lateral
  *   axes, soft threshold on the detail bands.
+ * OCT_PEN_DTCWT (B-scans; Sec. 2.2): haar_levels-level 2-D dual-tree complex
+ *   wavelet transform W (four separable orthonormal trees scaled by 1/2,
+ *   combined into six oriented complex subbands; filters of the common-factor
+ *   Hilbert-pair design, see oct_dtcwt_filter), z = W^T soft_tau(W v) with
+ *   every complex detail coefficient's modulus shrunk by tau, low bands kept.
+ *   Dimensions divisible by 2^haar_levels; volumes and a bound give
+ *   OCT_E_UNSUPPORTED.
  * v and z are images and may not alias. */
 oct_status oct_prox(oct_plan_t plan, int32_t penalty, double lambda, double delta,
                     int32_t tv_inner, int32_t haar_levels, double bound, const void* v, void* z,
                     void* state, void* stream);
+
+/* Lowpass analysis filter of the DT-CWT (host, no device work): which = 0/1
+ * first level of tree a/b, 2/3 later levels of tree a/b.  Writes up to 16
+ * taps to h0 (host) and their count to *n; the highpass is
+ * h1[k] = (-1)^k h0[n-1-k].  OCT_E_INVALID for another `which`. */
+oct_status oct_dtcwt_filter(int32_t which, float* h0, int32_t* n);
 
 /* Power iteration on Phi^H Phi (the Lipschitz constant behind the step size of
  * Sec. 2.3): x_0 = u / ||u|| with u from the SplitMix64 counter generator

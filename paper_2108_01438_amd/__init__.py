@@ -17,8 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboct.so")
 
 OCT_OK, OCT_E_INVALID, OCT_E_NOMEM, OCT_E_DEVICE, OCT_E_UNSUPPORTED = range(5)
-PEN_L1, PEN_TV, PEN_HAAR = 0, 1, 2
-PENALTIES = {"l1": PEN_L1, "tv": PEN_TV, "haar": PEN_HAAR}
+PEN_L1, PEN_TV, PEN_HAAR, PEN_DTCWT = 0, 1, 2, 3
+PENALTIES = {"l1": PEN_L1, "tv": PEN_TV, "haar": PEN_HAAR, "dtcwt": PEN_DTCWT}
 # direct reconstructions of Sec. 3.1 (oct_direct_kind)
 DIRECT = {"axial": 0, "dispersion": 1, "isam": 2, "interp_isam": 3}
 # oct_solve_flags
@@ -69,6 +69,7 @@ def _load():
         "oct_forward": ([P, P, P, P], ctypes.c_int),
         "oct_adjoint": ([P, P, P, P], ctypes.c_int),
         "oct_adjoint_paper": ([P, P, P, P], ctypes.c_int),
+        "oct_dtcwt_filter": ([ctypes.c_int32, P, P], ctypes.c_int),
         "oct_grad": ([P, P, P, P, P, P], ctypes.c_int),
         "oct_prox": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                       ctypes.c_double, P, P, P, P], ctypes.c_int),
@@ -140,6 +141,15 @@ class Geometry:
     @property
     def meas_shape(self):
         return (self.batch, self.n_y, self.n_x, self.n_k)
+
+
+def dtcwt_filter(which: int) -> np.ndarray:
+    """Lowpass analysis filter of the DT-CWT as the library designed it
+    (0/1: first level, tree a/b; 2/3: later levels, tree a/b)."""
+    taps = (ctypes.c_float * 16)()
+    n = ctypes.c_int32()
+    _check(_lib.oct_dtcwt_filter(int(which), taps, ctypes.byref(n)))
+    return np.array(taps[:n.value], dtype=np.float64)
 
 
 def footprint_bytes(geom: Geometry, penalty: int = PEN_L1) -> int:
@@ -323,4 +333,4 @@ class Plan:
 
 
 __all__ = ["Geometry", "Plan", "OctError", "footprint_bytes", "last_error", "LIB_PATH",
-           "PEN_L1", "PEN_TV", "PEN_HAAR", "PENALTIES", "DIRECT", "SOLVE_PAPER_BACKWARD"]
+           "PEN_L1", "PEN_TV", "PEN_HAAR", "PEN_DTCWT", "PENALTIES", "dtcwt_filter", "DIRECT", "SOLVE_PAPER_BACKWARD"]

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liboct.so")
-SOURCES = ["oct_lateral.hip", "oct_nufft.hip", "oct_prox.hip", "oct_direct.hip", "oct_literal.hip", "oct_api.cpp"]
+SOURCES = ["oct_lateral.hip", "oct_nufft.hip", "oct_prox.hip", "oct_direct.hip", "oct_literal.hip", "oct_dtcwt.hip", "oct_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled: plain float code is compiled to

@@ -203,6 +203,7 @@ struct oct_plan {
   // solver state, allocated on first use
   float2 *za = nullptr, *zb = nullptr;
   float2 *p0 = nullptr, *p1 = nullptr, *tvwork = nullptr;
+  float2* dtwork = nullptr;      // DT-CWT trees and staging (8 images)
   double* hist = nullptr;
   int hist_cap = 0;
   std::vector<void*> allocs;
@@ -582,6 +583,8 @@ int partial_need(oct_plan* p) {
   for (int lv = 1; lv <= 5; ++lv) need = std::max(need, haar_partials(pg, lv));
   need = std::max(need, tv_partials(pg, TV_MAX_TILED_INNER));
   need = std::max(need, tv_partials(pg, TV_MAX_TILED_INNER + 1));
+  if (p->lat_dims == 1)
+    for (int lv = 1; lv <= 5; ++lv) need = std::max(need, dtcwt_partials(pg, lv));
   return need;
 }
 
@@ -600,6 +603,10 @@ oct_status ensure_solver_state(oct_plan* p, int pen, int iters) {
     OCTCHK(dev_alloc(p, &p->tvwork, tv_work_elems(pg)));
     HIPCHK(hipMemset(p->p0, 0, sizeof(float2) * p->n_img() * nd));
     HIPCHK(hipMemset(p->p1, 0, sizeof(float2) * p->n_img() * nd));
+  }
+  if (pen == OCT_PEN_DTCWT && !p->dtwork) {
+    ProxGeom pg{(int)p->B, (int)p->Ny, (int)p->Nx, (int)p->Nz, p->lat_dims};
+    OCTCHK(dev_alloc(p, &p->dtwork, dtcwt_work_elems(pg)));
   }
   if (iters > p->hist_cap) {
     OCTCHK(dev_alloc(p, &p->hist, (size_t)iters));
@@ -640,9 +647,19 @@ oct_status check_bound(double b) {
 }
 float bound_f(double b) { return (b > 0 && std::isfinite(b)) ? (float)b : INFINITY; }
 
-// z = prox(v) with FP64 partials of R(z) in p->partial[0..*np)
+oct_status check_dtcwt(const oct_plan* p, int levels) {
+  if (p->lat_dims != 1) return fail(OCT_E_UNSUPPORTED, "the DT-CWT penalty is built for B-scans");
+  if (levels < 1 || levels > 5) return fail(OCT_E_UNSUPPORTED, "DT-CWT levels must be 1..5");
+  const int64_t bs = (int64_t)1 << levels;
+  if (p->Nz % bs || p->Nx % bs)
+    return fail(OCT_E_UNSUPPORTED, "the DT-CWT needs every image dimension divisible by 2^levels");
+  return OCT_OK;
+}
+
+// z = prox(v) with FP64 partials of R(z) in p->partial[0..*np) (for the DT-CWT
+// only when want_value: R(z) then needs a transform of z of its own)
 oct_status run_prox(oct_plan* p, int pen, float tau, float bound, int tv_inner, int haar_levels, const float2* v,
-                    float2* z, const float2* p_in, float2* p_out, int* np, hipStream_t s) {
+                    float2* z, const float2* p_in, float2* p_out, int* np, hipStream_t s, bool want_value = false) {
   ProxGeom pg = prox_geom(p);
   if (pen == OCT_PEN_L1) {
     const int nb = 1024;
@@ -658,6 +675,17 @@ oct_status run_prox(oct_plan* p, int pen, float tau, float bound, int tv_inner, 
     std::vector<float> mom = fgp_momenta(tv_inner);
     HIPCHK(launch_prox_tv(pg, tv_inner, mom.data(), v, z, p_in, p_out, tau, bound, p->partial, p->tvwork, s));
     *np = tv_partials(pg, tv_inner);
+  } else if (pen == OCT_PEN_DTCWT) {
+    if (bound < INFINITY) return fail(OCT_E_UNSUPPORTED, "a modulus bound with the DT-CWT step has no closed form");
+    OCTCHK(check_dtcwt(p, haar_levels));
+    HIPCHK(launch_prox_dtcwt(pg, haar_levels, v, z, tau, p->dtwork, s));
+    *np = 1;
+    if (want_value) {
+      HIPCHK(launch_dtcwt_value(pg, haar_levels, z, p->dtwork, p->partial, s));
+      *np = dtcwt_partials(pg, haar_levels);
+    } else {
+      HIPCHK(launch_zero(reinterpret_cast<float2*>(p->partial), 1, s));
+    }
   } else {
     return fail(OCT_E_INVALID, "unknown penalty");
   }
@@ -685,6 +713,7 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
     b += (size_t)N * 8 + (size_t)g->n_depth * 16 + (size_t)g->n_k * 16;
   b += (size_t)N * 8 * 2;                        // FISTA iterates
   if (penalty == OCT_PEN_TV) b += (size_t)N * 8 * (2 * nd + 1 + nd);
+  if (penalty == OCT_PEN_DTCWT) b += (size_t)N * 8 * 8;
   b += 64 * 1024 * 8;                            // partials, scalars, history
   return b;
 }
@@ -945,6 +974,15 @@ oct_status oct_prox(oct_plan_t p, int32_t pen, double lambda, double delta, int3
   return run_prox(p, pen, tau, bf, tv_inner, haar_levels, (const float2*)v, (float2*)z, nullptr, nullptr, &np, s);
 }
 
+oct_status oct_dtcwt_filter(int32_t which, float* h0, int32_t* n) {
+  if (!h0 || !n) return fail(OCT_E_INVALID, "null argument");
+  if (which < 0 || which > 3) return fail(OCT_E_INVALID, "which must be 0..3");
+  int m = 0;
+  dtcwt_filter_taps(which, h0, &m);
+  *n = m;
+  return OCT_OK;
+}
+
 oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, int32_t flags, double* L_out, void* stream) {
   if (!p || !L_out || iters < 1) return fail(OCT_E_INVALID, "bad argument");
   if (flags & ~(int32_t)OCT_SOLVE_PAPER_BACKWARD) return fail(OCT_E_INVALID, "unknown flags");
@@ -980,7 +1018,8 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
                           oct_solve_report* rep, void* stream) {
   if (!p || !y || !prm || !x_out) return fail(OCT_E_INVALID, "null argument");
   if (prm->iters < 1) return fail(OCT_E_INVALID, "iters must be >= 1");
-  if (prm->penalty < 0 || prm->penalty > 2) return fail(OCT_E_INVALID, "unknown penalty");
+  if (prm->penalty < 0 || prm->penalty > 3) return fail(OCT_E_INVALID, "unknown penalty");
+  if (prm->penalty == OCT_PEN_DTCWT) OCTCHK(check_dtcwt(p, prm->haar_levels));
   if (!(prm->lambda >= 0)) return fail(OCT_E_INVALID, "lambda must be >= 0");
   if (prm->penalty == OCT_PEN_HAAR) OCTCHK(check_haar(p, prm->haar_levels));
   if (prm->penalty == OCT_PEN_TV && (prm->tv_inner < 1 || prm->tv_inner > 1000))
@@ -988,8 +1027,8 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   if (prm->flags & ~(int32_t)OCT_SOLVE_PAPER_BACKWARD) return fail(OCT_E_INVALID, "unknown solve flags");
   OCTCHK(check_bound(prm->bound));
   const float bf = bound_f(prm->bound);
-  if (prm->penalty == OCT_PEN_HAAR && bf < INFINITY)
-    return fail(OCT_E_UNSUPPORTED, "a modulus bound with the Haar prox has no closed form");
+  if ((prm->penalty == OCT_PEN_HAAR || prm->penalty == OCT_PEN_DTCWT) && bf < INFINITY)
+    return fail(OCT_E_UNSUPPORTED, "a modulus bound with the Haar or DT-CWT step has no closed form");
   const bool paper = (prm->flags & OCT_SOLVE_PAPER_BACKWARD) != 0;
   hipStream_t s = S(stream);
   OCTCHK(ensure_solver_state(p, prm->penalty, prm->iters));
@@ -1083,7 +1122,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
         double* save = p->partial;
         p->partial = pen_part;
         oct_status st = run_prox(p, prm->penalty, tau, bf, prm->tv_inner, prm->haar_levels, p->X1, zo, pin, pout,
-                                 &npen, s);
+                                 &npen, s, want_obj);
         p->partial = save;
         OCTCHK(st);
         if (prm->penalty == OCT_PEN_TV) {
@@ -1110,7 +1149,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
 
 oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* y, void* stream) {
   if (!p) return fail(OCT_E_INVALID, "null plan");
-  if (pen < 0 || pen > 2) return fail(OCT_E_INVALID, "unknown penalty");
+  if (pen < 0 || pen > 3) return fail(OCT_E_INVALID, "unknown penalty");
   hipStream_t s = S(stream);
   OCTCHK(ensure_solver_state(p, pen, 1));
   switch (stage) {

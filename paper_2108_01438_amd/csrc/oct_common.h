@@ -194,6 +194,16 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
                           float2* z, const float2* p_in, float2* p_out, float tau, float bound,
                           double* partial, float2* work, hipStream_t s);
 size_t tv_work_elems(const ProxGeom& g);
+// DT-CWT (B-scans): z = W^T soft_tau(W v); work holds 8 images (four trees and
+// four staging arrays); the value pass writes sum |W x| over the detail bands
+// as dtcwt_partials block partials.
+int dtcwt_partials(const ProxGeom& g, int levels);
+size_t dtcwt_work_elems(const ProxGeom& g);
+hipError_t launch_prox_dtcwt(const ProxGeom& g, int levels, const float2* v, float2* z, float tau,
+                             float2* work, hipStream_t s);
+hipError_t launch_dtcwt_value(const ProxGeom& g, int levels, const float2* x, float2* work,
+                              double* partial, hipStream_t s);
+void dtcwt_filter_taps(int which, float* h0, int* n);
 
 // 2-D TV tile kernel arguments (inner steps up to TV_MAX_TILED_INNER).
 #define TV_MAX_TILED_INNER 27

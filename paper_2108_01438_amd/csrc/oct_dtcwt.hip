@@ -1,0 +1,534 @@
+// Dual-tree complex wavelet transform (Sec. 2.2; the DT-CWT of Selesnick,
+// Baraniuk and Kingsbury) for B-scans, and its shrinkage step.
+//
+// Filters (designed on the host at first use, FP64, rounded once): Selesnick's
+// common-factor construction of approximate Hilbert-transform pairs,
+// h = F D and g = F D~, D the degree-L maximally flat allpass denominator for
+// a half-sample delay (D~(z) = z^-L D(1/z)) and F = Q (1 + 1/z)^K with Q the
+// minimum-phase spectral factor of the symmetric R that makes
+// (z + 2 + 1/z)^K D(z) D(1/z) R(z) halfband.  First level: the 6-tap
+// Daubechies filter (K = 3, L = 0) for tree a and the same one sample later
+// for tree b; later levels: the 12-tap pair (K = 3, L = 3).
+//
+// Transform: four separable orthonormal 2-D DWTs (depth filters of tree a
+// or b x lateral filters of tree a or b), periodic extension, per level a
+// depth pass then a lateral pass, bands kept in place (Mallat layout) in one
+// buffer per tree.  The detail bands of the four trees combine per element
+// into the six oriented complex subbands (u1, v1) = (aa - bb, ab + ba)/sqrt2,
+// (u2, v2) = (aa + bb, ab - ba)/sqrt2.  With the 1/2 scaling of the trees the
+// transform W is a Parseval frame; the shrinkage step W^T soft_tau(W v) is
+// computed on the unscaled trees as 1/4 sum_t T_t^T(C^T soft_{2 tau}(C T v)).
+#include "oct_fft.h"
+
+#include <cmath>
+#include <complex>
+#include <vector>
+
+namespace {
+
+constexpr int DT_MAXT = 16;
+
+struct DtFilt {
+  float h0[DT_MAXT], h1[DT_MAXT];
+  int n;
+};
+
+struct DtGeom {
+  int B, NX, NZ;      // image [B][NX][NZ]
+  int nx, nz;         // current (sub-)array at the top-left of every item
+};
+
+// Periodic one-level filter banks along one axis of the top-left nx x nz
+// sub-array of every image of the batch.  Analysis: lo[i] = sum_k h0[k]
+// x[(2i + k) mod n], hi[i] likewise with h1, lo to the first half of the
+// axis and hi to the second.  Synthesis is its transpose (the analysis is
+// orthogonal): x[m] = sum over k with m - k even of h0[k] lo[i] + h1[k] hi[i],
+// i = ((m - k) mod n) / 2.  blockIdx.y selects one of up to four (source,
+// filter, destination) jobs of a launch (the four trees, or the two depth
+// filters of the first level); ACC makes a synthesis job add the output of
+// job y + 1 (same destination), so two trees that share the next pass are
+// summed on the way.
+
+struct DtJobs {
+  const float2* src[4];
+  float2* dst[4];
+  DtFilt f[4];
+  float scale;      // applied to synthesis outputs
+};
+
+__device__ __forceinline__ void fma2(float2& acc, float w, float2 x) {
+  acc.x = fmaf(w, x.x, acc.x);
+  acc.y = fmaf(w, x.y, acc.y);
+}
+
+__device__ __forceinline__ void afb_line(const DtFilt& f, const float2* __restrict__ src, int64_t stride, int n,
+                                         int i, float2& lo, float2& hi) {
+  lo = make_float2(0.f, 0.f);
+  hi = make_float2(0.f, 0.f);
+  int m = 2 * i;
+  for (int k = 0; k < f.n; ++k) {
+    const float2 x = src[(int64_t)m * stride];
+    fma2(lo, f.h0[k], x);
+    fma2(hi, f.h1[k], x);
+    if (++m == n) m = 0;
+  }
+}
+
+__device__ __forceinline__ float2 sfb_line(const DtFilt& f, const float2* __restrict__ src, int64_t stride, int n,
+                                           int m) {
+  const int h = n / 2;
+  float2 x = make_float2(0.f, 0.f);
+  for (int k = m & 1; k < f.n; k += 2) {
+    int d = m - k;
+    while (d < 0) d += n;
+    const int i = d >> 1;
+    fma2(x, f.h0[k], src[(int64_t)i * stride]);
+    fma2(x, f.h1[k], src[(int64_t)(h + i) * stride]);
+  }
+  return x;
+}
+
+// depth analysis: thread = (batch, lateral l < nx, i < nz/2), i fastest
+__global__ void afb_depth_kernel(DtGeom g, DtJobs J) {
+  const int j = blockIdx.y;
+  const int h = g.nz / 2;
+  const int64_t total = (int64_t)g.B * g.nx * h;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % h);
+    const int64_t r = t / h;
+    const int l = (int)(r % g.nx);
+    const int b = (int)(r / g.nx);
+    const int64_t base = ((int64_t)b * g.NX + l) * g.NZ;
+    float2 lo, hi;
+    afb_line(J.f[j], J.src[j] + base, 1, g.nz, i, lo, hi);
+    J.dst[j][base + i] = lo;
+    J.dst[j][base + h + i] = hi;
+  }
+}
+
+template <bool ACC>
+__global__ void sfb_depth_kernel(DtGeom g, DtJobs J) {
+  const int j = blockIdx.y * (ACC ? 2 : 1);
+  const int64_t total = (int64_t)g.B * g.nx * g.nz;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(t % g.nz);
+    const int64_t r = t / g.nz;
+    const int l = (int)(r % g.nx);
+    const int b = (int)(r / g.nx);
+    const int64_t base = ((int64_t)b * g.NX + l) * g.NZ;
+    float2 x = sfb_line(J.f[j], J.src[j] + base, 1, g.nz, m);
+    if (ACC) {
+      const float2 y = sfb_line(J.f[j + 1], J.src[j + 1] + base, 1, g.nz, m);
+      x = make_float2(x.x + y.x, x.y + y.y);
+    }
+    J.dst[j][base + m] = make_float2(J.scale * x.x, J.scale * x.y);
+  }
+}
+
+template <bool ACC>
+__global__ void sfb_lateral_kernel(DtGeom g, DtJobs J) {
+  const int j = blockIdx.y * (ACC ? 2 : 1);
+  const int64_t total = (int64_t)g.B * g.nx * g.nz;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(t % g.nz);
+    const int64_t r = t / g.nz;
+    const int m = (int)(r % g.nx);
+    const int b = (int)(r / g.nx);
+    const int64_t item = (int64_t)b * g.NX * g.NZ + n;
+    float2 x = sfb_line(J.f[j], J.src[j] + item, g.NZ, g.nx, m);
+    if (ACC) {
+      const float2 y = sfb_line(J.f[j + 1], J.src[j + 1] + item, g.NZ, g.nx, m);
+      x = make_float2(x.x + y.x, x.y + y.y);
+    }
+    J.dst[j][item + (int64_t)m * g.NZ] = make_float2(J.scale * x.x, J.scale * x.y);
+  }
+}
+
+struct Trees {
+  float2* t[4];   // trees aa, ab, ba, bb
+};
+
+__device__ __forceinline__ float2 add2(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 sub2(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// Combination of the four trees at one detail position into the two complex
+// coefficients (u1, v1), (u2, v2); SHRINK shrinks both by tau2 and writes the
+// trees back through the inverse combination, otherwise the moduli are added
+// (scaled by 1/2 for the Parseval normalisation).
+template <bool SHRINK>
+__device__ __forceinline__ void dt_group(float2 (&w)[4], float tau2, double& acc) {
+  const float r2 = 0.70710678118654752440f;
+  float2 u1 = cscale(sub2(w[0], w[3]), r2), v1 = cscale(add2(w[1], w[2]), r2);
+  float2 u2 = cscale(add2(w[0], w[3]), r2), v2 = cscale(sub2(w[1], w[2]), r2);
+  const float m1 = sqrtf(u1.x * u1.x + u1.y * u1.y + v1.x * v1.x + v1.y * v1.y);
+  const float m2 = sqrtf(u2.x * u2.x + u2.y * u2.y + v2.x * v2.x + v2.y * v2.y);
+  if (!SHRINK) {
+    acc += 0.5 * ((double)m1 + (double)m2);
+    return;
+  }
+  const float s1 = m1 > tau2 ? 1.f - tau2 / m1 : 0.f;
+  const float s2 = m2 > tau2 ? 1.f - tau2 / m2 : 0.f;
+  u1 = cscale(u1, s1);
+  v1 = cscale(v1, s1);
+  u2 = cscale(u2, s2);
+  v2 = cscale(v2, s2);
+  w[0] = cscale(add2(u1, u2), r2);
+  w[3] = cscale(sub2(u2, u1), r2);
+  w[1] = cscale(add2(v1, v2), r2);
+  w[2] = cscale(sub2(v1, v2), r2);
+}
+
+// Lateral analysis of all four trees at once (thread = (batch, i < nx/2,
+// depth n < nz)), with the detail bands of the level handled on the spot:
+// lateral-low outputs in the depth-low half are the next level's low band
+// and are written as they are; every other output is a detail coefficient,
+// combined across the trees and shrunk (SHRINK, then written) or summed into
+// FP64 block partials (value pass: only the low band is written).
+template <bool SHRINK>
+__global__ void afb_lateral4_kernel(DtGeom g, DtJobs J, float tau2, double* partial) {
+  __shared__ double sh[16];
+  const int h = g.nx / 2, hz = g.nz / 2;
+  const int64_t total = (int64_t)g.B * h * g.nz;
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(t % g.nz);
+    const int64_t r = t / g.nz;
+    const int i = (int)(r % h);
+    const int b = (int)(r / h);
+    const int64_t item = (int64_t)b * g.NX * g.NZ + n;
+    float2 lo[4], hi[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) afb_line(J.f[k], J.src[k] + item, g.NZ, g.nx, i, lo[k], hi[k]);
+    const int64_t olo = item + (int64_t)i * g.NZ, ohi = item + (int64_t)(h + i) * g.NZ;
+    if (n >= hz) dt_group<SHRINK>(lo, tau2, acc);
+    dt_group<SHRINK>(hi, tau2, acc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (SHRINK || n < hz) J.dst[k][olo] = lo[k];
+      if (SHRINK) J.dst[k][ohi] = hi[k];
+    }
+  }
+  if (!SHRINK) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+      partial[blockIdx.x] = s;
+    }
+  }
+}
+
+int dt_grid(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// ---------------------------------------------------------------------------
+// Host filter design (FP64)
+// ---------------------------------------------------------------------------
+std::vector<double> conv(const std::vector<double>& a, const std::vector<double>& b) {
+  std::vector<double> o(a.size() + b.size() - 1, 0.0);
+  for (size_t i = 0; i < a.size(); ++i)
+    for (size_t j = 0; j < b.size(); ++j) o[i + j] += a[i] * b[j];
+  return o;
+}
+
+double binom(int n, int k) {
+  double v = 1.0;
+  for (int i = 1; i <= k; ++i) v = v * (double)(n - k + i) / (double)i;
+  return v;
+}
+
+// Gaussian elimination with partial pivoting (n x n, row-major), in place.
+bool solve(std::vector<double>& A, std::vector<double>& b, int n) {
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[p * n + c])) p = r;
+    if (std::fabs(A[p * n + c]) < 1e-300) return false;
+    if (p != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[p * n + k], A[c * n + k]);
+      std::swap(b[p], b[c]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    double s = b[c];
+    for (int k = c + 1; k < n; ++k) s -= A[c * n + k] * b[k];
+    b[c] = s / A[c * n + c];
+  }
+  return true;
+}
+
+// Roots of sum_i p[i] z^(deg - i) (p[0] != 0) by the Weierstrass (Durand-Kerner)
+// iteration.
+std::vector<std::complex<double>> roots(const std::vector<double>& p) {
+  const int deg = (int)p.size() - 1;
+  std::vector<std::complex<double>> z(deg);
+  const std::complex<double> seed(0.4, 0.9);
+  for (int i = 0; i < deg; ++i) z[i] = std::pow(seed, i);
+  for (int it = 0; it < 2000; ++it) {
+    double move = 0.0;
+    for (int i = 0; i < deg; ++i) {
+      std::complex<double> num = p[0];
+      for (int k = 1; k <= deg; ++k) num = num * z[i] + p[k];
+      std::complex<double> den = p[0];
+      for (int j = 0; j < deg; ++j)
+        if (j != i) den *= (z[i] - z[j]);
+      const std::complex<double> d = num / den;
+      z[i] -= d;
+      move = std::max(move, std::abs(d));
+    }
+    if (move < 1e-15) break;
+  }
+  return z;
+}
+
+// Lowpass pair (h, g) of the common-factor design with K zeros at z = -1 and a
+// degree-L half-sample allpass (L = 0: Daubechies, h = g).
+void design_pair(int K, int L, std::vector<double>& h, std::vector<double>& g) {
+  std::vector<double> d(L + 1);
+  for (int n = 0; n <= L; ++n) {
+    double v = (n & 1) ? -binom(L, n) : binom(L, n);
+    for (int k = 0; k < n; ++k) v *= (0.5 - L + k) / (1.5 + k);
+    d[n] = v;
+  }
+  std::vector<double> dr(d.rbegin(), d.rend());
+  std::vector<double> q0 = conv(d, dr);
+  for (int k = 0; k < K; ++k) q0 = conv(q0, {1.0, 2.0, 1.0});
+  const int M = K + L - 1, nP = K + L + M;
+  const int neq = (nP + 1) / 2;           // = M + 1
+  std::vector<double> A(neq * neq), rhs(neq, 0.0);
+  rhs[0] = 1.0;
+  for (int i = 0; i <= M; ++i) {
+    std::vector<double> r(2 * M + 1, 0.0);
+    r[M + i] = 1.0;
+    r[M - i] = 1.0;
+    const std::vector<double> col = conv(q0, r);    // centre index nP
+    for (int e = 0; e < neq; ++e) A[e * neq + i] = col[nP + 2 * e];
+  }
+  solve(A, rhs, neq);
+  std::vector<double> f = {1.0};
+  if (M > 0) {
+    std::vector<double> R(2 * M + 1);
+    R[M] = rhs[0];
+    for (int i = 1; i <= M; ++i) R[M + i] = R[M - i] = rhs[i];
+    // minimum-phase factor: the monic polynomial of the roots inside the unit circle
+    std::vector<std::complex<double>> poly = {1.0};
+    for (const auto& z : roots(R))
+      if (std::abs(z) < 1.0) {
+        std::vector<std::complex<double>> nx(poly.size() + 1, 0.0);
+        for (size_t k = 0; k < poly.size(); ++k) {
+          nx[k] += poly[k];
+          nx[k + 1] -= poly[k] * z;
+        }
+        poly = nx;
+      }
+    f.assign(poly.size(), 0.0);
+    for (size_t k = 0; k < poly.size(); ++k) f[k] = poly[k].real();
+  }
+  for (int k = 0; k < K; ++k) f = conv(f, {1.0, 1.0});
+  h = conv(f, d);
+  g = conv(f, dr);
+  double s = 0.0;
+  for (double v : h) s += v;
+  const double sc = std::sqrt(2.0) / s;
+  for (double& v : h) v *= sc;
+  for (double& v : g) v *= sc;
+}
+
+DtFilt make_filt(const std::vector<double>& h) {
+  DtFilt f{};
+  f.n = (int)h.size();
+  for (int k = 0; k < f.n; ++k) {
+    f.h0[k] = (float)h[k];
+    const double hk = h[f.n - 1 - k];
+    f.h1[k] = (float)((k & 1) ? -hk : hk);
+  }
+  return f;
+}
+
+struct DtFilters {
+  DtFilt first[2], later[2];
+  bool ready = false;
+};
+
+DtFilters& filters() {
+  static DtFilters F;
+  if (!F.ready) {
+    std::vector<double> d1, d1g, ha, hb;
+    design_pair(3, 0, d1, d1g);
+    std::vector<double> fa(d1), fb(1, 0.0);
+    fa.push_back(0.0);
+    fa.push_back(0.0);
+    fb.insert(fb.end(), d1.begin(), d1.end());
+    fb.push_back(0.0);
+    design_pair(3, 3, ha, hb);
+    F.first[0] = make_filt(fa);
+    F.first[1] = make_filt(fb);
+    F.later[0] = make_filt(ha);
+    F.later[1] = make_filt(hb);
+    F.ready = true;
+  }
+  return F;
+}
+
+// Workspace: four tree buffers then four staging buffers, one image each.
+struct DtWork {
+  Trees tr;
+  float2* tmp[4];
+};
+
+DtWork dt_work(float2* work, int64_t n) {
+  DtWork w;
+  for (int t = 0; t < 4; ++t) {
+    w.tr.t[t] = work + t * n;
+    w.tmp[t] = work + (4 + t) * n;
+  }
+  return w;
+}
+
+int dt_grid_y(int64_t n, int jobs) {
+  int64_t b = (n + 255) / 256;
+  const int64_t cap = 4096 / jobs;
+  if (b > cap) b = cap;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// Analysis of all trees (level by level) from v into the tree buffers.
+// Level 1: the two depth filters once each (v -> tmp[0], tmp[1]), then the
+// lateral filters of every tree from its depth tree's staging buffer.  Later
+// levels: each tree's low band through tmp[t].
+// mode 0: analysis with the detail bands shrunk by tau2 on the way; mode 1:
+// the value pass (block partials of sum |W x| into partial, nothing but the
+// low bands written).
+hipError_t dt_analysis(const DtGeom& g0, int levels, const float2* v, const DtWork& w, int mode, float tau2,
+                       double* partial, hipStream_t s) {
+  const DtFilters& F = filters();
+  DtGeom g = g0;
+  for (int lev = 0; lev < levels; ++lev) {
+    const DtFilt* fs = lev == 0 ? F.first : F.later;
+    const int64_t nd = (int64_t)g.B * g.nx * (g.nz / 2), nl = (int64_t)g.B * (g.nx / 2) * g.nz;
+    DtJobs jd{}, jl{};
+    int ndj;
+    if (lev == 0) {
+      ndj = 2;
+      for (int p = 0; p < 2; ++p) {
+        jd.src[p] = v;
+        jd.dst[p] = w.tmp[p];
+        jd.f[p] = fs[p];
+      }
+    } else {
+      ndj = 4;
+      for (int t = 0; t < 4; ++t) {
+        jd.src[t] = w.tr.t[t];
+        jd.dst[t] = w.tmp[t];
+        jd.f[t] = fs[t >> 1];
+      }
+    }
+    for (int t = 0; t < 4; ++t) {
+      jl.src[t] = lev == 0 ? w.tmp[t >> 1] : w.tmp[t];
+      jl.dst[t] = w.tr.t[t];
+      jl.f[t] = fs[t & 1];
+    }
+    hipLaunchKernelGGL(afb_depth_kernel, dim3(dt_grid_y(nd, ndj), ndj), dim3(256), 0, s, g, jd);
+    if (mode == 0) {
+      hipLaunchKernelGGL((afb_lateral4_kernel<true>), dim3(dt_grid(nl)), dim3(256), 0, s, g, jl, tau2, nullptr);
+    } else {
+      hipLaunchKernelGGL((afb_lateral4_kernel<false>), dim3(dt_grid(nl)), dim3(256), 0, s, g, jl, 0.f, partial);
+      partial += dt_grid(nl);
+    }
+    g.nx /= 2;
+    g.nz /= 2;
+  }
+  return hipGetLastError();
+}
+
+int dt_level_blocks(const DtGeom& g) { return dt_grid((int64_t)g.B * (g.nx / 2) * g.nz); }
+
+}  // namespace
+
+int dtcwt_partials(const ProxGeom& pg, int levels) {
+  DtGeom g{pg.B, pg.Nx, pg.Nz, pg.Nx, pg.Nz};
+  int n = 0;
+  for (int lev = 0; lev < levels; ++lev) {
+    n += dt_level_blocks(g);
+    g.nx /= 2;
+    g.nz /= 2;
+  }
+  return n;
+}
+
+size_t dtcwt_work_elems(const ProxGeom& pg) { return (size_t)8 * pg.B * pg.Nx * pg.Nz; }
+
+hipError_t launch_prox_dtcwt(const ProxGeom& pg, int levels, const float2* v, float2* z, float tau, float2* work,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)pg.B * pg.Nx * pg.Nz;
+  const DtWork w = dt_work(work, n);
+  const DtGeom g0{pg.B, pg.Nx, pg.Nz, pg.Nx, pg.Nz};
+  hipError_t e = dt_analysis(g0, levels, v, w, 0, 2.f * tau, nullptr, s);
+  if (e != hipSuccess) return e;
+  // synthesis, coarsest level first; level 1 sums the two trees of each depth
+  // filter after their lateral passes and the two depth filters at the end,
+  // with the 1/4 of the Parseval normalisation
+  const DtFilters& F = filters();
+  for (int lev = levels - 1; lev >= 0; --lev) {
+    DtGeom gl = g0;
+    gl.nx = pg.Nx >> lev;
+    gl.nz = pg.Nz >> lev;
+    const DtFilt* fs = lev == 0 ? F.first : F.later;
+    const int64_t nn = (int64_t)gl.B * gl.nx * gl.nz;
+    DtJobs jl{}, jd{};
+    jl.scale = jd.scale = 1.f;
+    for (int t = 0; t < 4; ++t) {
+      jl.src[t] = w.tr.t[t];
+      jl.dst[t] = w.tmp[t];
+      jl.f[t] = fs[t & 1];
+    }
+    if (lev > 0) {
+      for (int t = 0; t < 4; ++t) {
+        jd.src[t] = w.tmp[t];
+        jd.dst[t] = w.tr.t[t];
+        jd.f[t] = fs[t >> 1];
+      }
+      hipLaunchKernelGGL((sfb_lateral_kernel<false>), dim3(dt_grid_y(nn, 4), 4), dim3(256), 0, s, gl, jl);
+      hipLaunchKernelGGL((sfb_depth_kernel<false>), dim3(dt_grid_y(nn, 4), 4), dim3(256), 0, s, gl, jd);
+    } else {
+      // tmp[0] = lat(aa) + lat(ab), tmp[2] = lat(ba) + lat(bb)
+      hipLaunchKernelGGL((sfb_lateral_kernel<true>), dim3(dt_grid_y(nn, 2), 2), dim3(256), 0, s, gl, jl);
+      jd.src[0] = w.tmp[0];
+      jd.src[1] = w.tmp[2];
+      jd.dst[0] = jd.dst[1] = z;
+      jd.f[0] = fs[0];
+      jd.f[1] = fs[1];
+      jd.scale = 0.25f;
+      hipLaunchKernelGGL((sfb_depth_kernel<true>), dim3(dt_grid_y(nn, 1), 1), dim3(256), 0, s, gl, jd);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dtcwt_value(const ProxGeom& pg, int levels, const float2* x, float2* work, double* partial,
+                              hipStream_t s) {
+  const int64_t n = (int64_t)pg.B * pg.Nx * pg.Nz;
+  const DtWork w = dt_work(work, n);
+  const DtGeom g0{pg.B, pg.Nx, pg.Nz, pg.Nx, pg.Nz};
+  return dt_analysis(g0, levels, x, w, 1, 0.f, partial, s);
+}
+
+// Host copies of the designed filters (for the library's own checks).
+void dtcwt_filter_taps(int which, float* h0, int* n) {
+  const DtFilters& F = filters();
+  const DtFilt& f = which == 0 ? F.first[0] : which == 1 ? F.first[1] : which == 2 ? F.later[0] : F.later[1];
+  *n = f.n;
+  for (int k = 0; k < f.n; ++k) h0[k] = f.h0[k];
+}

@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -21,7 +22,7 @@ def test_header_declares_the_entry_points():
     names = _declared()
     for n in ["oct_plan_create", "oct_plan_destroy", "oct_forward", "oct_adjoint", "oct_grad", "oct_prox",
               "oct_mbir_solve", "oct_lipschitz", "oct_last_error", "oct_plan_footprint_bytes", "oct_direct",
-              "oct_adjoint_paper",
+              "oct_adjoint_paper", "oct_dtcwt_filter",
               "oct_ncc"]:
         assert n in names
 
@@ -73,3 +74,19 @@ def test_mask_shape_checked_on_host():
     import paper_2108_01438_amd as P
     with pytest.raises(ValueError):
         P.Plan(_g(), mask=np.ones((1, 8, 63), dtype=np.uint8))
+
+
+def test_dtcwt_filters_designed_by_the_library_match_the_oracle():
+    """The library designs the DT-CWT filters on the host, independently of the
+    oracle (its own halfband solve, Weierstrass root finder and spectral
+    factor); both give the same taps, up to the FP32 rounding of the library's."""
+    import paper_2108_01438_amd as P
+    import oracle as O
+    F = O.dtcwt_filters()
+    ref = [F["first"][0], F["first"][1], F["later"][0], F["later"][1]]
+    for which in range(4):
+        got = P.dtcwt_filter(which)
+        assert got.shape == ref[which].shape
+        np.testing.assert_allclose(got, ref[which], atol=1e-7)
+    with pytest.raises(P.OctError):
+        P.dtcwt_filter(4)
