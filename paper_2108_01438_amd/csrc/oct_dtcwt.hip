@@ -125,25 +125,6 @@ __global__ void sfb_depth_kernel(DtGeom g, DtJobs J) {
   }
 }
 
-template <bool ACC>
-__global__ void sfb_lateral_kernel(DtGeom g, DtJobs J) {
-  const int j = blockIdx.y * (ACC ? 2 : 1);
-  const int64_t total = (int64_t)g.B * g.nx * g.nz;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int n = (int)(t % g.nz);
-    const int64_t r = t / g.nz;
-    const int m = (int)(r % g.nx);
-    const int b = (int)(r / g.nx);
-    const int64_t item = (int64_t)b * g.NX * g.NZ + n;
-    float2 x = sfb_line(J.f[j], J.src[j] + item, g.NZ, g.nx, m);
-    if (ACC) {
-      const float2 y = sfb_line(J.f[j + 1], J.src[j + 1] + item, g.NZ, g.nx, m);
-      x = make_float2(x.x + y.x, x.y + y.y);
-    }
-    J.dst[j][item + (int64_t)m * g.NZ] = make_float2(J.scale * x.x, J.scale * x.y);
-  }
-}
-
 struct Trees {
   float2* t[4];   // trees aa, ab, ba, bb
 };
@@ -176,6 +157,24 @@ __device__ __forceinline__ void dt_group(float2 (&w)[4], float tau2, double& acc
   w[3] = cscale(sub2(u2, u1), r2);
   w[1] = cscale(add2(v1, v2), r2);
   w[2] = cscale(sub2(v1, v2), r2);
+}
+
+// LDS-tiled lateral synthesis.  A workgroup (4 waves) owns 64 consecutive
+// depth samples (one per lane) and a run of lateral output rows; it stages
+// the input rows those outputs need (periodic wrap resolved while staging) in
+// LDS once, so that every tap is an LDS read instead of a strided global one.
+// (The analysis stays untiled: measured faster, its taps hit the caches.)
+constexpr int DT_LANES = 64;
+
+__device__ __forceinline__ void dt_stage(const float2* __restrict__ src, int64_t item, int NZ, int n, int base,
+                                         int nrows, int n0, int nz, int rowoff, float2* __restrict__ lds) {
+  for (int e = threadIdx.x; e < nrows * DT_LANES; e += blockDim.x) {
+    const int r = e / DT_LANES, c = e % DT_LANES;
+    int m = (base + r) % n;
+    if (m < 0) m += n;
+    const int nn = n0 + c;
+    lds[e] = nn < nz ? src[item + (int64_t)(rowoff + m) * NZ + nn] : make_float2(0.f, 0.f);
+  }
 }
 
 // Lateral analysis of all four trees at once (thread = (batch, i < nx/2,
@@ -218,6 +217,51 @@ __global__ void afb_lateral4_kernel(DtGeom g, DtJobs J, float tau2, double* part
       double s = 0.0;
       for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
       partial[blockIdx.x] = s;
+    }
+  }
+}
+
+// Lateral synthesis (the transpose of the analysis along the lateral axis):
+// TS output rows per workgroup; blockIdx.y picks the job (ACC: the job pair
+// summed into one destination).
+template <bool ACC>
+__global__ void __launch_bounds__(256) sfb_lateral_tiled(DtGeom g, DtJobs J) {
+  constexpr int TS = 32;
+  constexpr int NS = ACC ? 2 : 1;
+  constexpr int CNT = (TS + DT_MAXT) / 2 + 1;
+  __shared__ float2 lo_s[NS][CNT * DT_LANES], hi_s[NS][CNT * DT_LANES];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n0 = blockIdx.x * DT_LANES, m0 = blockIdx.z * TS;
+  const int j = blockIdx.y * NS;
+  const int h = g.nx / 2;
+  const int B = g.B;
+  for (int b = 0; b < B; ++b) {
+    const int64_t item = (int64_t)b * g.NX * g.NZ;
+    const int taps = J.f[j].n;
+    const int ibase = (m0 - taps + 1) >> 1;
+    const int cnt = (m0 + TS - 1 - ((m0 - taps + 1) & ~1)) / 2 + 1;
+    if (b > 0) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      dt_stage(J.src[j + q], item, g.NZ, h, ibase, cnt, n0, g.nz, 0, lo_s[q]);
+      dt_stage(J.src[j + q], item, g.NZ, h, ibase, cnt, n0, g.nz, h, hi_s[q]);
+    }
+    __syncthreads();
+    const int n = n0 + lane;
+    for (int r = 0; r < TS / 4; ++r) {
+      const int m = m0 + w * (TS / 4) + r;
+      if (m >= g.nx || n >= g.nz) continue;
+      float2 x = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const DtFilt& f = J.f[j + q];
+        for (int t = m & 1; t < f.n; t += 2) {
+          const int row = ((m - t) >> 1) - ibase;
+          fma2(x, f.h0[t], lo_s[q][row * DT_LANES + lane]);
+          fma2(x, f.h1[t], hi_s[q][row * DT_LANES + lane]);
+        }
+      }
+      J.dst[j][item + (int64_t)m * g.NZ + n] = make_float2(J.scale * x.x, J.scale * x.y);
     }
   }
 }
@@ -404,6 +448,12 @@ int dt_grid_y(int64_t n, int jobs) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// Workgroups of the tiled lateral synthesis (32 output rows each, the batch
+// looped inside).
+dim3 dt_sfb_grid(const DtGeom& g, int jobs) {
+  return dim3((unsigned)((g.nz + DT_LANES - 1) / DT_LANES), (unsigned)jobs, (unsigned)((g.nx + 31) / 32));
+}
+
 // Analysis of all trees (level by level) from v into the tree buffers.
 // Level 1: the two depth filters once each (v -> tmp[0], tmp[1]), then the
 // lateral filters of every tree from its depth tree's staging buffer.  Later
@@ -453,7 +503,7 @@ hipError_t dt_analysis(const DtGeom& g0, int levels, const float2* v, const DtWo
   return hipGetLastError();
 }
 
-int dt_level_blocks(const DtGeom& g) { return dt_grid((int64_t)g.B * (g.nx / 2) * g.nz); }
+
 
 }  // namespace
 
@@ -461,7 +511,7 @@ int dtcwt_partials(const ProxGeom& pg, int levels) {
   DtGeom g{pg.B, pg.Nx, pg.Nz, pg.Nx, pg.Nz};
   int n = 0;
   for (int lev = 0; lev < levels; ++lev) {
-    n += dt_level_blocks(g);
+    n += dt_grid((int64_t)g.B * (g.nx / 2) * g.nz);
     g.nx /= 2;
     g.nz /= 2;
   }
@@ -500,11 +550,11 @@ hipError_t launch_prox_dtcwt(const ProxGeom& pg, int levels, const float2* v, fl
         jd.dst[t] = w.tr.t[t];
         jd.f[t] = fs[t >> 1];
       }
-      hipLaunchKernelGGL((sfb_lateral_kernel<false>), dim3(dt_grid_y(nn, 4), 4), dim3(256), 0, s, gl, jl);
+      hipLaunchKernelGGL((sfb_lateral_tiled<false>), dt_sfb_grid(gl, 4), dim3(256), 0, s, gl, jl);
       hipLaunchKernelGGL((sfb_depth_kernel<false>), dim3(dt_grid_y(nn, 4), 4), dim3(256), 0, s, gl, jd);
     } else {
       // tmp[0] = lat(aa) + lat(ab), tmp[2] = lat(ba) + lat(bb)
-      hipLaunchKernelGGL((sfb_lateral_kernel<true>), dim3(dt_grid_y(nn, 2), 2), dim3(256), 0, s, gl, jl);
+      hipLaunchKernelGGL((sfb_lateral_tiled<true>), dt_sfb_grid(gl, 2), dim3(256), 0, s, gl, jl);
       jd.src[0] = w.tmp[0];
       jd.src[1] = w.tmp[2];
       jd.dst[0] = jd.dst[1] = z;
