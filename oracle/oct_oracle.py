@@ -37,8 +37,12 @@ design notes of the repository):
   ``paper_backward_nx1``), with a FISTA and a power iteration that use it.
 * Regularisers (Sec. 2.2, eq. (12)-(14)): l1 (Psi = I), isotropic TV (complex,
   Neumann forward differences, FGP inner solver with a fixed inner count and a
-  warm-started dual), 3-level orthonormal Haar on the detail bands (the
-  substitute for the DT-CWT, whose filter banks the paper does not give).
+  warm-started dual), 3-level orthonormal Haar on the detail bands, and the
+  2-D DT-CWT (B-scans) with filters designed by Selesnick's common-factor
+  method, since the paper does not give its filter banks.  The constraint set
+  C of eq. (16) is read as a per-pixel modulus bound (l1 and TV).
+* Operator models: 0, the NUFFT evaluated at every detector wavenumber; 1, the
+  paper's literal K, Q, D chain (M_k = 2 N_z).
 * FISTA (Sec. 2.3, eq. (15)-(16)) with x^1 = x0, z^0 = x^1, t^1 = 1; returns
   z^K.  Step 1/(1.05 L) with L from a 50-step power iteration on Phi^H Phi
   whose start vector comes from the SplitMix64 counter generator.
