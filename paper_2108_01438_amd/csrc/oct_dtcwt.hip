@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(256) sfb_lateral_tiled(DtGeom g, DtJobs J) {
   const int B = g.B;
   for (int b = 0; b < B; ++b) {
     const int64_t item = (int64_t)b * g.NX * g.NZ;
-    const int taps = J.f[j].n;
+    const int taps = NS == 2 ? max(J.f[j].n, J.f[j + 1].n) : J.f[j].n;   // rows staged for every job
     const int ibase = (m0 - taps + 1) >> 1;
     const int cnt = (m0 + TS - 1 - ((m0 - taps + 1) & ~1)) / 2 + 1;
     if (b > 0) __syncthreads();

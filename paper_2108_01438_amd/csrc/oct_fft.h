@@ -35,6 +35,14 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) {
   return (t + ((x - t) >> 1)) >> f.s;
 }
 
+// LDS bank swizzle between the first two stages of a transform whose first
+// radix is 8: the first stage writes butterfly j's outputs to 8j + r, eight
+// lanes apart for one r; XOR-ing the low three bits of the index with the
+// next three spreads those writes over the banks.  The map only permutes
+// indices inside aligned groups of eight (n is a multiple of 8), so the
+// second stage, which reads through the same map, sees the same data.
+__device__ __forceinline__ int fft_swz(int i) { return i ^ ((i >> 3) & 7); }
+
 // Element loop with batched loads: every thread first issues the loads of U
 // elements (indices clamped to a valid element, so each load is in bounds
 // and none waits on another), then consumes them in order.  A plain loop
@@ -205,9 +213,14 @@ __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride,
 #pragma unroll
         for (int q = 0; q < NQ; ++q) wq[b][q] = tp[q];
       }
-      const float2* src = buf + row * rowstride + j;
+      const float2* src = buf + row * rowstride;
+      if (Ns == 8) {   // second stage after a first radix-8 stage: swizzled layout
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = src[r * nb];
+        for (int r = 0; r < R; ++r) v[b][r] = src[fft_swz(j + r * nb)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b][r] = src[j + r * nb];
+      }
       off[b] = row * rowstride;
       jj[b] = j;
       kk[b] = k;
@@ -229,9 +242,15 @@ __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride,
         }
       }
       Dft<R, INV>::run(v[b]);
-      float2* dst = buf + off[b] + (j - k) * R + k;
+      if (R == 8 && Ns == 1 && n > 8) {   // first stage of several: swizzled layout
+        float2* dst = buf + off[b];
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns] = v[b][r];
+        for (int r = 0; r < R; ++r) dst[fft_swz(j * R + r)] = v[b][r];
+      } else {
+        float2* dst = buf + off[b] + (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[r * Ns] = v[b][r];
+      }
     }
   }
   __syncthreads();
@@ -326,9 +345,15 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, int nrows, int rowstri
         for (int q = 0; q < NQ; ++q) wq[b][q] = tp[q];
       }
       base[b] = row * rowstride;
-      const float2* src = buf + base[b] + j;
+      if (NS == 8) {   // second stage after a first radix-8 stage: swizzled layout
+        const float2* src = buf + base[b];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = src[r * nb];
+        for (int r = 0; r < R; ++r) v[b][r] = src[fft_swz(j + r * nb)];
+      } else {
+        const float2* src = buf + base[b] + j;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b][r] = src[r * nb];
+      }
       jj[b] = j;
     }
   }
@@ -348,9 +373,15 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, int nrows, int rowstri
         }
       }
       Dft<R, INV>::run(v[b]);
-      float2* dst = buf + base[b] + (j - k) * R + k;
+      if (R == 8 && NS == 1 && N > 8) {   // first stage of several: swizzled layout
+        float2* dst = buf + base[b];
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * NS] = v[b][r];
+        for (int r = 0; r < R; ++r) dst[fft_swz(j * R + r)] = v[b][r];
+      } else {
+        float2* dst = buf + base[b] + (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[r * NS] = v[b][r];
+      }
     }
   }
   __syncthreads();
