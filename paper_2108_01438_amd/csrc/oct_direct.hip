@@ -9,6 +9,8 @@
 //   samples by linear interpolation in k before the ISAM adjoint.
 // * NCC of magnitudes (eq. (17)) in FP64, two passes (means, then centred
 //   sums), deterministic block partials.
+// * The conjugate analytic signal of each A-scan along k, the operator A of
+//   the paper's backward operator (eq. (10)-(11)).
 #include "oct_fft.h"
 
 namespace {

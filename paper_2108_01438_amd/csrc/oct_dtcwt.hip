@@ -403,26 +403,29 @@ DtFilt make_filt(const std::vector<double>& h) {
 
 struct DtFilters {
   DtFilt first[2], later[2];
-  bool ready = false;
 };
 
-DtFilters& filters() {
-  static DtFilters F;
-  if (!F.ready) {
-    std::vector<double> d1, d1g, ha, hb;
-    design_pair(3, 0, d1, d1g);
-    std::vector<double> fa(d1), fb(1, 0.0);
-    fa.push_back(0.0);
-    fa.push_back(0.0);
-    fb.insert(fb.end(), d1.begin(), d1.end());
-    fb.push_back(0.0);
-    design_pair(3, 3, ha, hb);
-    F.first[0] = make_filt(fa);
-    F.first[1] = make_filt(fb);
-    F.later[0] = make_filt(ha);
-    F.later[1] = make_filt(hb);
-    F.ready = true;
-  }
+DtFilters design_filters() {
+  DtFilters F;
+  std::vector<double> d1, d1g, ha, hb;
+  design_pair(3, 0, d1, d1g);
+  std::vector<double> fa(d1), fb(1, 0.0);
+  fa.push_back(0.0);
+  fa.push_back(0.0);
+  fb.insert(fb.end(), d1.begin(), d1.end());
+  fb.push_back(0.0);
+  design_pair(3, 3, ha, hb);
+  F.first[0] = make_filt(fa);
+  F.first[1] = make_filt(fb);
+  F.later[0] = make_filt(ha);
+  F.later[1] = make_filt(hb);
+  return F;
+}
+
+// Designed once per process (the initialisation of a function-local static
+// is thread safe: plans on several host threads may ask at once).
+const DtFilters& filters() {
+  static const DtFilters F = design_filters();
   return F;
 }
 

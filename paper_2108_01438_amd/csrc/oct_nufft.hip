@@ -367,12 +367,10 @@ template <int J, bool ONE>
 hipError_t nufft_adj_t(const NufftArgs& a, const float2* Rh, float2* X, int nthr, hipStream_t s) {
   const size_t lds = nufft_adj_lds_bytes(a);
   if (lds > 64 * 1024 - 1024) {
-    static bool done = false;
-    if (!done) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_adj_kernel<J, ONE>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-      done = true;
-    }
+    // once per instantiation (thread-safe initialisation of a local static)
+    static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_adj_kernel<J, ONE>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    if (set != hipSuccess) return set;
   }
   hipLaunchKernelGGL((nufft_adj_kernel<J, ONE>), dim3(a.n_cols), dim3(nthr), lds, s, a, Rh, X);
   return hipGetLastError();
