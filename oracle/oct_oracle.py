@@ -54,6 +54,7 @@ A B-scan has N_y = 1.
 from __future__ import annotations
 
 from dataclasses import dataclass, replace
+import itertools
 import math
 
 import numpy as np
@@ -72,7 +73,7 @@ __all__ = [
     "power_start", "lipschitz", "step_size", "fista_momenta", "fista",
     "lambda_max", "paper_backward_nx1", "paper_backward", "adjoint_complex", "ncc", "direct_axial", "direct_isam", "interp_fill",
     "interp_isam", "PEN_L1", "PEN_TV", "PEN_HAAR", "PEN_DTCWT",
-    "maxflat_halfband_factor", "dtcwt_filters", "dtcwt_forward", "dtcwt_inverse", "prox_dtcwt", "dtcwt_value",
+    "maxflat_halfband_factor", "dtcwt_filters", "dtcwt_combination", "dtcwt_forward", "dtcwt_inverse", "prox_dtcwt", "dtcwt_value",
 ]
 
 PEN_L1, PEN_TV, PEN_HAAR, PEN_DTCWT = 0, 1, 2, 3
@@ -727,88 +728,133 @@ def _sfb(lo, hi, h0, axis):
     return np.moveaxis(out, -1, axis)
 
 
-_DT_TREES = (("a", "a"), ("a", "b"), ("b", "a"), ("b", "b"))
+def _dt_trees(d: int):
+    """The 2^d trees: one filter tree (a or b) per image axis, in axis order."""
+    return list(itertools.product("ab", repeat=d))
 
 
-def _tree_forward(x, axes, levels, tz, tl, F):
-    """Separable orthonormal 2-D DWT of one tree (depth filters of tree tz,
-    lateral of tree tl): per level, depth then lateral analysis; returns the
-    detail bands [(lh, hl, hh) per level] and the final low band."""
-    az, al = axes
+def dtcwt_combination(d: int) -> np.ndarray:
+    """Orthogonal map from the 2^d tree values of one detail coefficient to the
+    real and imaginary parts (rows u_0, v_0, u_1, v_1, ...) of its complex
+    coefficients.  The 1-D complex wavelet is tree a + j tree b; a d-D complex
+    wavelet is the product over the axes of it or of its conjugate (the first
+    axis never conjugated), expanded into tree products.  2-D:
+    u = (aa - s bb)/sqrt2, v = (s ab + ba)/sqrt2 for s = +1 and (with the sign
+    of v flipped) s = -1.  3-D, for s_x, s_y = +-1:
+    u = (aaa - s_x s_y abb - s_x bba - s_y bab)/2,
+    v = (s_x aba + s_y aab + baa - s_x s_y bbb)/2 (trees named depth, x, y)."""
+    idx = {"".join(t): i for i, t in enumerate(_dt_trees(d))}
+    rows = []
+    if d == 2:
+        r = 1.0 / math.sqrt(2.0)
+        for u, v in (({"aa": 1, "bb": -1}, {"ab": 1, "ba": 1}), ({"aa": 1, "bb": 1}, {"ab": 1, "ba": -1})):
+            for part in (u, v):
+                row = np.zeros(4)
+                for k, c in part.items():
+                    row[idx[k]] = c * r
+                rows.append(row)
+    elif d == 3:
+        for sx, sy in ((1, 1), (1, -1), (-1, 1), (-1, -1)):
+            u = {"aaa": 1, "abb": -sx * sy, "bba": -sx, "bab": -sy}
+            v = {"aba": sx, "aab": sy, "baa": 1, "bbb": -sx * sy}
+            for part in (u, v):
+                row = np.zeros(8)
+                for k, c in part.items():
+                    row[idx[k]] = 0.5 * c
+                rows.append(row)
+    else:
+        raise ValueError("the DT-CWT here is 2-D or 3-D")
+    return np.array(rows)
+
+
+def _tree_forward(x, axes, levels, tree, F):
+    """Separable orthonormal DWT of one tree (filters of tree tree[i] along
+    axes[i]): per level, analysis along every axis in order; band b of a
+    level has bit i (most significant first) set when it is high-pass along
+    axes[i].  Returns ([details of each level: bands 1..2^d - 1], low band)."""
     pick = {"a": 0, "b": 1}
     low = x
     bands = []
     for lev in range(levels):
         key = "first" if lev == 0 else "later"
-        fz, fl = F[key][pick[tz]], F[key][pick[tl]]
-        lz, hz = _afb(low, fz, az)
-        ll, lh = _afb(lz, fl, al)        # low depth: low / high lateral
-        hl, hh = _afb(hz, fl, al)        # high depth: low / high lateral
-        bands.append((lh, hl, hh))
-        low = ll
+        parts = [low]
+        for ax, t in zip(axes, tree):
+            f = F[key][pick[t]]
+            nxt = []
+            for part in parts:
+                lo, hi = _afb(part, f, ax)
+                nxt += [lo, hi]
+            parts = nxt
+        bands.append(parts[1:])
+        low = parts[0]
     return bands, low
 
 
-def _tree_inverse(bands, low, axes, levels, tz, tl, F):
-    az, al = axes
+def _tree_inverse(bands, low, axes, levels, tree, F):
     pick = {"a": 0, "b": 1}
     for lev in reversed(range(levels)):
         key = "first" if lev == 0 else "later"
-        fz, fl = F[key][pick[tz]], F[key][pick[tl]]
-        lh, hl, hh = bands[lev]
-        lz = _sfb(low, lh, fl, al)
-        hz = _sfb(hl, hh, fl, al)
-        low = _sfb(lz, hz, fz, az)
+        parts = [low] + list(bands[lev])
+        for ax, t in reversed(list(zip(axes, tree))):
+            f = F[key][pick[t]]
+            parts = [_sfb(parts[2 * i], parts[2 * i + 1], f, ax) for i in range(len(parts) // 2)]
+        low = parts[0]
     return low
 
 
 def dtcwt_forward(x, axes, levels: int):
-    """2-D DT-CWT of x over (depth axis, lateral axis): the four separable trees
-    (depth filters of tree a or b x lateral filters of tree a or b), each
-    scaled by 1/2, and per level and detail band the orthonormal combination
-    u1 = (aa - bb)/sqrt2, v1 = (ab + ba)/sqrt2, u2 = (aa + bb)/sqrt2,
-    v2 = (ab - ba)/sqrt2: the complex coefficients u1 + j v1 and u2 + j v2 of
-    the six orientations.  For a complex image the trees act on it linearly
-    and a coefficient is the pair (u, v) of complex numbers.  Returns
-    (details [level][band] = ((u1, v1), (u2, v2)), lows {tree: band})."""
+    """DT-CWT of x over axes (depth, lateral) or (depth, x, y): the 2^d
+    separable trees, each scaled by 2^(-d/2), and per level and detail band
+    the orthogonal combination of ``dtcwt_combination`` into the complex
+    coefficients (u_k, v_k): 6 oriented subbands in 2-D, 28 in 3-D.  For a
+    complex image the trees act on it linearly and a coefficient is the pair
+    (u, v) of complex numbers.  Returns (details [level][band] = [(u_k, v_k)],
+    lows {tree: band})."""
     F = dtcwt_filters()
+    d = len(axes)
     x = np.asarray(x, dtype=np.complex128)
-    tr = {t: _tree_forward(0.5 * x, axes, levels, t[0], t[1], F) for t in _DT_TREES}
-    r2 = 1.0 / math.sqrt(2.0)
+    trees = _dt_trees(d)
+    sc = 2.0 ** (-d / 2.0)
+    tr = {t: _tree_forward(sc * x, axes, levels, t, F) for t in trees}
+    C = dtcwt_combination(d)
     details = []
     for lev in range(levels):
         per = []
-        for b in range(3):
-            aa, ab = tr[("a", "a")][0][lev][b], tr[("a", "b")][0][lev][b]
-            ba, bb = tr[("b", "a")][0][lev][b], tr[("b", "b")][0][lev][b]
-            per.append((((aa - bb) * r2, (ab + ba) * r2), ((aa + bb) * r2, (ab - ba) * r2)))
+        for b in range(2 ** d - 1):
+            stack = np.stack([tr[t][0][lev][b] for t in trees])
+            coef = np.tensordot(C, stack, axes=([1], [0]))
+            per.append([(coef[2 * k], coef[2 * k + 1]) for k in range(len(trees) // 2)])
         details.append(per)
-    lows = {t: tr[t][1] for t in _DT_TREES}
+    lows = {t: tr[t][1] for t in trees}
     return details, lows
 
 
 def dtcwt_inverse(details, lows, axes, levels: int):
     """Adjoint of ``dtcwt_forward`` (its inverse: the transform is a Parseval frame)."""
     F = dtcwt_filters()
-    r2 = 1.0 / math.sqrt(2.0)
+    d = len(axes)
+    trees = _dt_trees(d)
+    sc = 2.0 ** (-d / 2.0)
+    C = dtcwt_combination(d)
+    per_tree = {t: [] for t in trees}
+    for lev in range(levels):
+        bands = {t: [] for t in trees}
+        for b in range(2 ** d - 1):
+            coef = np.stack([c for pair in details[lev][b] for c in pair])
+            stack = np.tensordot(C.T, coef, axes=([1], [0]))
+            for i, t in enumerate(trees):
+                bands[t].append(stack[i])
+        for t in trees:
+            per_tree[t].append(bands[t])
     out = 0.0
-    for t in _DT_TREES:
-        bands = []
-        for lev in range(levels):
-            per = []
-            for b in range(3):
-                (u1, v1), (u2, v2) = details[lev][b]
-                aa, bb = (u1 + u2) * r2, (u2 - u1) * r2
-                ab, ba = (v1 + v2) * r2, (v1 - v2) * r2
-                per.append({("a", "a"): aa, ("a", "b"): ab, ("b", "a"): ba, ("b", "b"): bb}[t])
-            bands.append(tuple(per))
-        out = out + 0.5 * _tree_inverse(bands, lows[t], axes, levels, t[0], t[1], F)
+    for t in trees:
+        out = out + sc * _tree_inverse(per_tree[t], lows[t], axes, levels, t, F)
     return out
 
 
 def _dtcwt_axes(x, axes):
-    if len(axes) != 2:
-        raise ValueError("the DT-CWT here is 2-D (B-scans)")
+    if len(axes) not in (2, 3):
+        raise ValueError("the DT-CWT here is 2-D or 3-D")
     return axes
 
 
@@ -822,13 +868,13 @@ def prox_dtcwt(v, tau: float, axes, levels: int):
     out = []
     for per in details:
         pb = []
-        for pair in per:
+        for pairs in per:
             q = []
-            for u, w in pair:
+            for u, w in pairs:
                 mag = np.sqrt(np.abs(u) ** 2 + np.abs(w) ** 2)
                 sc = np.where(mag > tau, 1.0 - tau / np.where(mag > 0, mag, 1.0), 0.0)
                 q.append((u * sc, w * sc))
-            pb.append(tuple(q))
+            pb.append(q)
         out.append(pb)
     return dtcwt_inverse(out, lows, axes, levels)
 
@@ -837,7 +883,7 @@ def dtcwt_value(x, axes, levels: int) -> float:
     """||W x||_1 over the detail bands: the sum of the coefficient moduli."""
     details, _ = dtcwt_forward(x, _dtcwt_axes(x, axes), levels)
     return float(sum(np.sum(np.sqrt(np.abs(u) ** 2 + np.abs(w) ** 2))
-                     for per in details for pair in per for u, w in pair))
+                     for per in details for pairs in per for u, w in pairs))
 
 
 def penalty_value(x: np.ndarray, g: Geometry, pen: int, haar_levels: int = 3) -> float:

@@ -186,3 +186,53 @@ def test_oriented_subbands_occupy_one_quadrant():
             # diagonal bands are analytic in both directions: one quadrant
             if band == 2:
                 assert q.max() > 0.99, (band, which, q)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_combination_is_orthogonal(d):
+    C = O.dtcwt_combination(d)
+    np.testing.assert_allclose(C @ C.T, np.eye(2 ** d), atol=1e-15)
+
+
+@pytest.mark.parametrize("shape,levels", [((1, 8, 8, 16), 2), ((2, 4, 8, 8), 1), ((1, 16, 8, 32), 3)])
+def test_dtcwt_3d_parseval_and_perfect_reconstruction(shape, levels):
+    rng = np.random.default_rng(6)
+    x = cn(rng, shape)
+    axes = (3, 2, 1)
+    det, lows = O.dtcwt_forward(x, axes, levels)
+    assert len(det[0]) == 7 and len(det[0][0]) == 4          # 28 oriented subbands per level
+    e = sum(np.sum(np.abs(u) ** 2 + np.abs(w) ** 2) for per in det for pairs in per for u, w in pairs)
+    e += sum(np.sum(np.abs(v) ** 2) for v in lows.values())
+    assert abs(e / np.sum(np.abs(x) ** 2) - 1.0) < 1e-12
+    np.testing.assert_allclose(O.dtcwt_inverse(det, lows, axes, levels), x, atol=1e-12)
+    np.testing.assert_allclose(O.prox_dtcwt(x, 0.0, axes, levels), x, atol=1e-12)
+
+
+def test_dtcwt_3d_diagonal_subbands_occupy_one_octant():
+    """The four complex subbands of the all-high-pass band of the 3-D transform
+    each lie almost entirely in one octant of the frequency space, four
+    different ones (a sign slip in the combination spreads them over two)."""
+    shape, levels, lev, band = (1, 32, 32, 32), 3, 1, 6
+    x = np.zeros(shape, dtype=complex)
+    det, lows = O.dtcwt_forward(x, (3, 2, 1), levels)
+    zero_lows = {t: np.zeros_like(v) for t, v in lows.items()}
+    best = []
+    for which in range(4):
+        resp = []
+        for comp in range(2):
+            d = [[[(np.zeros_like(u), np.zeros_like(w)) for u, w in pairs] for pairs in per] for per in det]
+            c = np.zeros_like(det[lev][band][which][comp])
+            c[0, c.shape[1] // 2, c.shape[2] // 2, c.shape[3] // 2] = 1.0
+            pair = list(d[lev][band][which])
+            pair[comp] = c
+            d[lev][band][which] = tuple(pair)
+            resp.append(O.dtcwt_inverse(d, zero_lows, (3, 2, 1), levels))
+        psi = (resp[0] + 1j * resp[1])[0]
+        S = np.abs(np.fft.fftn(psi)) ** 2
+        h = [n // 2 for n in S.shape]
+        oct_e = [S[a * h[0]:(a + 1) * h[0], b * h[1]:(b + 1) * h[1], c_ * h[2]:(c_ + 1) * h[2]].sum()
+                 for a in range(2) for b in range(2) for c_ in range(2)]
+        q = np.array(oct_e) / sum(oct_e)
+        assert q.max() > 0.99, (which, np.round(q, 3))
+        best.append(int(np.argmax(q)))
+    assert len(set(best)) == 4
