@@ -435,7 +435,8 @@ def penalties_bench(steps: int = 100, reps: int = 20) -> dict:
     random mask): per penalty the prox alone (HIP events, `reps` calls), one
     FISTA solve of `steps` iterations, and the NCC of its result with the
     specimen.  lambda = 0.01 lambda_max (l1, Haar, DT-CWT), 0.005 (TV);
-    3 wavelet levels, 10 FGP steps."""
+    3 wavelet levels, 10 FGP steps.  Then each step alone on the
+    2048 x 256 x 256 volume."""
     import numpy as np
     import torch
     import paper_2108_01438_amd as P
@@ -475,6 +476,28 @@ def penalties_bench(steps: int = 100, reps: int = 20) -> dict:
         out[pen] = {"lambda_frac": frac, "prox_ms": round(prox_ms, 5),
                     "ms_per_iteration": round(e0.elapsed_time(e1) / steps, 5),
                     "ncc_vs_specimen": round(plan.ncc(z, xt), 5)}
+    # the step alone on the 2048 x 256 x 256 volume (random image, tau = 0.01 of its peak)
+    del plan, v, zbuf, y, yc, xt
+    torch.cuda.empty_cache()
+    gv = P.Geometry(n_depth=2048, n_x=256, n_y=256, lateral_dims=2, n_k=2048)
+    pv = P.Plan(gv)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    vv = torch.randn(gv.img_shape, dtype=torch.complex64, device="cuda", generator=gen)
+    zv = torch.empty_like(vv)
+    tau = 0.01 * float(vv.abs().max().item())
+    vol = {}
+    for pen in ("l1", "tv", "haar", "dtcwt"):
+        for _ in range(2):
+            pv.prox(pen, tau, 1.0, vv, zv, haar_levels=3)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(5):
+            pv.prox(pen, tau, 1.0, vv, zv, haar_levels=3)
+        b.record()
+        torch.cuda.synchronize()
+        vol[pen] = round(a.elapsed_time(b) / 5, 4)
+    out["volume_2048x256x256_prox_ms"] = vol
     return out
 
 

@@ -151,12 +151,14 @@ oct_status oct_grad(oct_plan_t plan, const void* x, const float* y, void* g,
  *   overwritten with the new dual; NULL starts from zero.
  * OCT_PEN_HAAR: haar_levels-level orthonormal Haar over the depth and lateral
  *   axes, soft threshold on the detail bands.
- * OCT_PEN_DTCWT (B-scans; Sec. 2.2): haar_levels-level 2-D dual-tree complex
- *   wavelet transform W (four separable orthonormal trees scaled by 1/2,
- *   combined into six oriented complex subbands; filters of the common-factor
- *   Hilbert-pair design, see oct_dtcwt_filter), z = W^T soft_tau(W v) with
- *   every complex detail coefficient's modulus shrunk by tau, low bands kept.
- *   Dimensions divisible by 2^haar_levels; volumes and a bound give
+ * OCT_PEN_DTCWT (Sec. 2.2): haar_levels-level dual-tree complex wavelet
+ *   transform W over the depth and lateral axes (B-scan: four separable
+ *   orthonormal trees scaled by 1/2, six oriented complex subbands per level;
+ *   volume: eight trees scaled by 2^-3/2, 28 subbands; filters of the
+ *   common-factor Hilbert-pair design, see oct_dtcwt_filter),
+ *   z = W^T soft_tau(W v) with every complex detail coefficient's modulus
+ *   shrunk by tau, low bands kept.  Dimensions divisible by 2^haar_levels
+ *   (levels 1..5 for a B-scan, 1..4 for a volume); a bound gives
  *   OCT_E_UNSUPPORTED.
  * v and z are images and may not alias. */
 oct_status oct_prox(oct_plan_t plan, int32_t penalty, double lambda, double delta,

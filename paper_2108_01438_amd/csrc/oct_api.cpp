@@ -203,7 +203,7 @@ struct oct_plan {
   // solver state, allocated on first use
   float2 *za = nullptr, *zb = nullptr;
   float2 *p0 = nullptr, *p1 = nullptr, *tvwork = nullptr;
-  float2* dtwork = nullptr;      // DT-CWT trees and staging (8 images)
+  float2* dtwork = nullptr;      // DT-CWT trees and staging (8 images; 24 for a volume)
   double* hist = nullptr;
   int hist_cap = 0;
   std::vector<void*> allocs;
@@ -583,8 +583,7 @@ int partial_need(oct_plan* p) {
   for (int lv = 1; lv <= 5; ++lv) need = std::max(need, haar_partials(pg, lv));
   need = std::max(need, tv_partials(pg, TV_MAX_TILED_INNER));
   need = std::max(need, tv_partials(pg, TV_MAX_TILED_INNER + 1));
-  if (p->lat_dims == 1)
-    for (int lv = 1; lv <= 5; ++lv) need = std::max(need, dtcwt_partials(pg, lv));
+  for (int lv = 1; lv <= (p->lat_dims == 1 ? 5 : 4); ++lv) need = std::max(need, dtcwt_partials(pg, lv));
   return need;
 }
 
@@ -648,10 +647,10 @@ oct_status check_bound(double b) {
 float bound_f(double b) { return (b > 0 && std::isfinite(b)) ? (float)b : INFINITY; }
 
 oct_status check_dtcwt(const oct_plan* p, int levels) {
-  if (p->lat_dims != 1) return fail(OCT_E_UNSUPPORTED, "the DT-CWT penalty is built for B-scans");
-  if (levels < 1 || levels > 5) return fail(OCT_E_UNSUPPORTED, "DT-CWT levels must be 1..5");
+  if (levels < 1 || levels > (p->lat_dims == 1 ? 5 : 4))
+    return fail(OCT_E_UNSUPPORTED, "DT-CWT levels must be 1..5 (B-scan) or 1..4 (volume)");
   const int64_t bs = (int64_t)1 << levels;
-  if (p->Nz % bs || p->Nx % bs)
+  if (p->Nz % bs || p->Nx % bs || (p->lat_dims == 2 && p->Ny % bs))
     return fail(OCT_E_UNSUPPORTED, "the DT-CWT needs every image dimension divisible by 2^levels");
   return OCT_OK;
 }
@@ -713,7 +712,7 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
     b += (size_t)N * 8 + (size_t)g->n_depth * 16 + (size_t)g->n_k * 16;
   b += (size_t)N * 8 * 2;                        // FISTA iterates
   if (penalty == OCT_PEN_TV) b += (size_t)N * 8 * (2 * nd + 1 + nd);
-  if (penalty == OCT_PEN_DTCWT) b += (size_t)N * 8 * 8;
+  if (penalty == OCT_PEN_DTCWT) b += (size_t)N * 8 * (g->lateral_dims == 2 ? 24 : 8);
   b += 64 * 1024 * 8;                            // partials, scalars, history
   return b;
 }

@@ -194,9 +194,10 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
                           float2* z, const float2* p_in, float2* p_out, float tau, float bound,
                           double* partial, float2* work, hipStream_t s);
 size_t tv_work_elems(const ProxGeom& g);
-// DT-CWT (B-scans): z = W^T soft_tau(W v); work holds 8 images (four trees and
-// four staging arrays); the value pass writes sum |W x| over the detail bands
-// as dtcwt_partials block partials.
+// DT-CWT: z = W^T soft_tau(W v); work holds dtcwt_work_elems complex values
+// (B-scan: four trees and four staging arrays; volume: eight trees and sixteen
+// staging arrays); the value pass writes sum |W x| over the detail bands as
+// dtcwt_partials block partials.
 int dtcwt_partials(const ProxGeom& g, int levels);
 size_t dtcwt_work_elems(const ProxGeom& g);
 hipError_t launch_prox_dtcwt(const ProxGeom& g, int levels, const float2* v, float2* z, float tau,

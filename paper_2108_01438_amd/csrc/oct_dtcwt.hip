@@ -508,11 +508,273 @@ hipError_t dt_analysis(const DtGeom& g0, int levels, const float2* v, const DtWo
 
 
 
+// ---------------------------------------------------------------------------
+// Volumes: eight trees (depth, x, y filter trees), a pass per axis and level.
+// ---------------------------------------------------------------------------
+struct Dt3Geom {
+  int B, NY, NX, NZ;  // image [B][NY][NX][NZ]
+  int ny, nx, nz;     // current sub-array at the corner of every item
+};
+
+struct DtJobs8 {
+  const float2* src[8];
+  float2* dst[8];
+  DtFilt f[8];
+  float scale;
+};
+
+// Orthogonal combination of the eight tree values (tree index 4 tz + 2 tx +
+// ty, a = 0, b = 1) of one detail coefficient into the real and imaginary
+// parts of four complex coefficients (rows u0, v0, ..., u3, v3): the 3-D
+// complex wavelet is the product over the axes of (tree a + j tree b), with
+// the x and y factors optionally conjugated (signs sx, sy = ++, +-, -+, --):
+// u = (aaa - sx sy abb - sx bba - sy bab)/2, v = (sx aba + sy aab + baa - sx sy bbb)/2.
+__device__ __forceinline__ float dt3_c(int row, int t) {
+  const int k = row >> 1;
+  const float sx = (k & 2) ? -1.f : 1.f, sy = (k & 1) ? -1.f : 1.f;
+  if ((row & 1) == 0) {
+    switch (t) {
+      case 0: return 0.5f;
+      case 3: return -0.5f * sx * sy;
+      case 6: return -0.5f * sx;
+      case 5: return -0.5f * sy;
+      default: return 0.f;
+    }
+  }
+  switch (t) {
+    case 2: return 0.5f * sx;
+    case 1: return 0.5f * sy;
+    case 4: return 0.5f;
+    case 7: return -0.5f * sx * sy;
+    default: return 0.f;
+  }
+}
+
+template <bool SHRINK>
+__device__ __forceinline__ void dt3_group(float2 (&w)[8], float tau2, double& acc) {
+  float2 c[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    c[r] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) fma2(c[r], dt3_c(r, t), w[t]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float2 u = c[2 * k], v = c[2 * k + 1];
+    const float m = sqrtf(u.x * u.x + u.y * u.y + v.x * v.x + v.y * v.y);
+    if (!SHRINK) {
+      acc += 0.35355339059327376220 * (double)m;   // 2^(-3/2): the trees' Parseval scale
+    } else {
+      const float sc = m > tau2 ? 1.f - tau2 / m : 0.f;
+      c[2 * k] = cscale(u, sc);
+      c[2 * k + 1] = cscale(v, sc);
+    }
+  }
+  if (SHRINK) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      w[t] = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) fma2(w[t], dt3_c(r, t), c[r]);
+    }
+  }
+}
+
+__device__ __forceinline__ int64_t dt3_off(const Dt3Geom& g, int b, int y, int x, int n) {
+  return (((int64_t)b * g.NY + y) * g.NX + x) * g.NZ + n;
+}
+
+// Analysis along one axis (0 depth, 1 x, 2 y) of the corner sub-array; the
+// depth index runs fastest for the lateral axes (coalesced).
+template <int AXIS>
+__global__ void afb3_kernel(Dt3Geom g, DtJobs8 J) {
+  const int j = blockIdx.y;
+  const int len = AXIS == 0 ? g.nz : AXIS == 1 ? g.nx : g.ny;
+  const int h = len / 2;
+  const int64_t stride = AXIS == 0 ? 1 : AXIS == 1 ? (int64_t)g.NZ : (int64_t)g.NX * g.NZ;
+  const int a0 = AXIS == 0 ? h : g.nz;                 // fastest index range
+  const int a1 = AXIS == 1 ? h : g.nx;
+  const int a2 = AXIS == 2 ? h : g.ny;
+  const int64_t total = (int64_t)g.B * a2 * a1 * a0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int i0 = (int)(t % a0);
+    int64_t r = t / a0;
+    const int i1 = (int)(r % a1);
+    r /= a1;
+    const int i2 = (int)(r % a2);
+    const int b = (int)(r / a2);
+    const int n = AXIS == 0 ? 0 : i0, x = AXIS == 1 ? 0 : i1, y = AXIS == 2 ? 0 : i2;
+    const int i = AXIS == 0 ? i0 : AXIS == 1 ? i1 : i2;
+    const int64_t base = dt3_off(g, b, y, x, n);
+    float2 lo, hi;
+    afb_line(J.f[j], J.src[j] + base, stride, len, i, lo, hi);
+    J.dst[j][base + (int64_t)i * stride] = lo;
+    J.dst[j][base + (int64_t)(h + i) * stride] = hi;
+  }
+}
+
+// Synthesis along one axis; ACC sums job pairs (2y, 2y + 1) into dst[2y].
+template <int AXIS, bool ACC>
+__global__ void sfb3_kernel(Dt3Geom g, DtJobs8 J) {
+  const int j = blockIdx.y * (ACC ? 2 : 1);
+  const int len = AXIS == 0 ? g.nz : AXIS == 1 ? g.nx : g.ny;
+  const int64_t stride = AXIS == 0 ? 1 : AXIS == 1 ? (int64_t)g.NZ : (int64_t)g.NX * g.NZ;
+  const int64_t total = (int64_t)g.B * g.ny * g.nx * g.nz;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(t % g.nz);
+    int64_t r = t / g.nz;
+    const int x = (int)(r % g.nx);
+    r /= g.nx;
+    const int y = (int)(r % g.ny);
+    const int b = (int)(r / g.ny);
+    const int m = AXIS == 0 ? n : AXIS == 1 ? x : y;
+    const int64_t base = dt3_off(g, b, AXIS == 2 ? 0 : y, AXIS == 1 ? 0 : x, AXIS == 0 ? 0 : n);
+    float2 v = sfb_line(J.f[j], J.src[j] + base, stride, len, m);
+    if (ACC) {
+      const float2 w = sfb_line(J.f[j + 1], J.src[j + 1] + base, stride, len, m);
+      v = make_float2(v.x + w.x, v.y + w.y);
+    }
+    J.dst[j][base + (int64_t)m * stride] = make_float2(J.scale * v.x, J.scale * v.y);
+  }
+}
+
+// y analysis of all eight trees in one thread with the level's detail bands
+// combined and shrunk (or summed) on the spot, as afb_lateral4_kernel.
+template <bool SHRINK>
+__global__ void afb3_y8_kernel(Dt3Geom g, DtJobs8 J, float tau2, double* partial) {
+  __shared__ double sh[16];
+  const int h = g.ny / 2, hx = g.nx / 2, hz = g.nz / 2;
+  const int64_t total = (int64_t)g.B * h * g.nx * g.nz;
+  const int64_t stride = (int64_t)g.NX * g.NZ;
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(t % g.nz);
+    int64_t r = t / g.nz;
+    const int x = (int)(r % g.nx);
+    r /= g.nx;
+    const int i = (int)(r % h);
+    const int b = (int)(r / h);
+    const int64_t base = dt3_off(g, b, 0, x, n);
+    float2 lo[8], hi[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) afb_line(J.f[k], J.src[k] + base, stride, g.ny, i, lo[k], hi[k]);
+    const bool low3 = n < hz && x < hx;   // y-low output of the all-low band continues to the next level
+    if (!low3) dt3_group<SHRINK>(lo, tau2, acc);
+    dt3_group<SHRINK>(hi, tau2, acc);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (SHRINK || low3) J.dst[k][base + (int64_t)i * stride] = lo[k];
+      if (SHRINK) J.dst[k][base + (int64_t)(h + i) * stride] = hi[k];
+    }
+  }
+  if (!SHRINK) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+      partial[blockIdx.x] = s;
+    }
+  }
+}
+
+// Workspace of the volume transform: 8 trees, then staging buffers S (8) and
+// U (8), one image each.
+struct Dt3Work {
+  float2* tree[8];
+  float2* S[8];
+  float2* U[8];
+};
+
+Dt3Work dt3_work(float2* work, int64_t n) {
+  Dt3Work w;
+  for (int t = 0; t < 8; ++t) {
+    w.tree[t] = work + t * n;
+    w.S[t] = work + (8 + t) * n;
+    w.U[t] = work + (16 + t) * n;
+  }
+  return w;
+}
+
+// Analysis of the eight trees; mode 0 shrinks the details by tau2, mode 1
+// writes the block partials of sum |W x| (value pass).
+hipError_t dt3_analysis(const Dt3Geom& g0, int levels, const float2* v, const Dt3Work& w, int mode, float tau2,
+                        double* partial, hipStream_t s) {
+  const DtFilters& F = filters();
+  Dt3Geom g = g0;
+  for (int lev = 0; lev < levels; ++lev) {
+    const DtFilt* fs = lev == 0 ? F.first : F.later;
+    DtJobs8 jz{}, jx{}, jy{};
+    int nz_jobs, nx_jobs;
+    if (lev == 0) {
+      // depth filters once per depth tree, x filters once per (depth, x) pair
+      nz_jobs = 2;
+      for (int p = 0; p < 2; ++p) {
+        jz.src[p] = v;
+        jz.dst[p] = w.S[p];
+        jz.f[p] = fs[p];
+      }
+      nx_jobs = 4;
+      for (int p = 0; p < 4; ++p) {
+        jx.src[p] = w.S[p >> 1];
+        jx.dst[p] = w.U[p];
+        jx.f[p] = fs[p & 1];
+      }
+      for (int t = 0; t < 8; ++t) {
+        jy.src[t] = w.U[t >> 1];
+        jy.dst[t] = w.tree[t];
+        jy.f[t] = fs[t & 1];
+      }
+    } else {
+      nz_jobs = nx_jobs = 8;
+      for (int t = 0; t < 8; ++t) {
+        jz.src[t] = w.tree[t];
+        jz.dst[t] = w.S[t];
+        jz.f[t] = fs[t >> 2];
+        jx.src[t] = w.S[t];
+        jx.dst[t] = w.U[t];
+        jx.f[t] = fs[(t >> 1) & 1];
+        jy.src[t] = w.U[t];
+        jy.dst[t] = w.tree[t];
+        jy.f[t] = fs[t & 1];
+      }
+    }
+    const int64_t nzw = (int64_t)g.B * g.ny * g.nx * (g.nz / 2), nxw = (int64_t)g.B * g.ny * (g.nx / 2) * g.nz;
+    const int64_t nyw = (int64_t)g.B * (g.ny / 2) * g.nx * g.nz;
+    hipLaunchKernelGGL(afb3_kernel<0>, dim3(dt_grid_y(nzw, nz_jobs), nz_jobs), dim3(256), 0, s, g, jz);
+    hipLaunchKernelGGL(afb3_kernel<1>, dim3(dt_grid_y(nxw, nx_jobs), nx_jobs), dim3(256), 0, s, g, jx);
+    if (mode == 0) {
+      hipLaunchKernelGGL((afb3_y8_kernel<true>), dim3(dt_grid(nyw)), dim3(256), 0, s, g, jy, tau2, nullptr);
+    } else {
+      hipLaunchKernelGGL((afb3_y8_kernel<false>), dim3(dt_grid(nyw)), dim3(256), 0, s, g, jy, 0.f, partial);
+      partial += dt_grid(nyw);
+    }
+    g.ny /= 2;
+    g.nx /= 2;
+    g.nz /= 2;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int dtcwt_partials(const ProxGeom& pg, int levels) {
-  DtGeom g{pg.B, pg.Nx, pg.Nz, pg.Nx, pg.Nz};
   int n = 0;
+  if (pg.lateral_dims == 2) {
+    int64_t ny = pg.Ny, nx = pg.Nx, nz = pg.Nz;
+    for (int lev = 0; lev < levels; ++lev) {
+      n += dt_grid((int64_t)pg.B * (ny / 2) * nx * nz);
+      ny /= 2;
+      nx /= 2;
+      nz /= 2;
+    }
+    return n;
+  }
+  DtGeom g{pg.B, pg.Nx, pg.Nz, pg.Nx, pg.Nz};
   for (int lev = 0; lev < levels; ++lev) {
     n += dt_grid((int64_t)g.B * (g.nx / 2) * g.nz);
     g.nx /= 2;
@@ -521,10 +783,74 @@ int dtcwt_partials(const ProxGeom& pg, int levels) {
   return n;
 }
 
-size_t dtcwt_work_elems(const ProxGeom& pg) { return (size_t)8 * pg.B * pg.Nx * pg.Nz; }
+size_t dtcwt_work_elems(const ProxGeom& pg) {
+  const size_t n = (size_t)pg.B * pg.Ny * pg.Nx * pg.Nz;
+  return (pg.lateral_dims == 2 ? 24 : 8) * n;
+}
+
+hipError_t launch_prox_dtcwt3(const ProxGeom& pg, int levels, const float2* v, float2* z, float tau, float2* work,
+                              hipStream_t s) {
+  const int64_t n = (int64_t)pg.B * pg.Ny * pg.Nx * pg.Nz;
+  const Dt3Work w = dt3_work(work, n);
+  const Dt3Geom g0{pg.B, pg.Ny, pg.Nx, pg.Nz, pg.Ny, pg.Nx, pg.Nz};
+  // unscaled trees: soft threshold 2^(3/2) tau, synthesis sum scaled by 1/8
+  hipError_t e = dt3_analysis(g0, levels, v, w, 0, 2.8284271247461900976f * tau, nullptr, s);
+  if (e != hipSuccess) return e;
+  const DtFilters& F = filters();
+  for (int lev = levels - 1; lev >= 0; --lev) {
+    Dt3Geom gl = g0;
+    gl.ny = pg.Ny >> lev;
+    gl.nx = pg.Nx >> lev;
+    gl.nz = pg.Nz >> lev;
+    const DtFilt* fs = lev == 0 ? F.first : F.later;
+    const int64_t nn = (int64_t)gl.B * gl.ny * gl.nx * gl.nz;
+    DtJobs8 jy{}, jx{}, jz{};
+    jy.scale = jx.scale = jz.scale = 1.f;
+    if (lev > 0) {
+      for (int t = 0; t < 8; ++t) {
+        jy.src[t] = w.tree[t];
+        jy.dst[t] = w.S[t];
+        jy.f[t] = fs[t & 1];
+        jx.src[t] = w.S[t];
+        jx.dst[t] = w.U[t];
+        jx.f[t] = fs[(t >> 1) & 1];
+        jz.src[t] = w.U[t];
+        jz.dst[t] = w.tree[t];
+        jz.f[t] = fs[t >> 2];
+      }
+      hipLaunchKernelGGL((sfb3_kernel<2, false>), dim3(dt_grid_y(nn, 8), 8), dim3(256), 0, s, gl, jy);
+      hipLaunchKernelGGL((sfb3_kernel<1, false>), dim3(dt_grid_y(nn, 8), 8), dim3(256), 0, s, gl, jx);
+      hipLaunchKernelGGL((sfb3_kernel<0, false>), dim3(dt_grid_y(nn, 8), 8), dim3(256), 0, s, gl, jz);
+    } else {
+      // y: trees (p, ty = a) + (p, ty = b) -> S[2q], p = 4 tz + 2 tx = 2q; x: S[4 tz] + S[4 tz + 2] -> U[tz];
+      // depth: U[a] + U[b], times 1/8, -> z
+      for (int t = 0; t < 8; ++t) {
+        jy.src[t] = w.tree[t];
+        jy.dst[t] = w.S[t];
+        jy.f[t] = fs[t & 1];
+      }
+      for (int q = 0; q < 4; ++q) {
+        jx.src[q] = w.S[2 * q];
+        jx.dst[q] = w.U[q];
+        jx.f[q] = fs[q & 1];
+      }
+      jz.src[0] = w.U[0];
+      jz.src[1] = w.U[2];
+      jz.dst[0] = z;
+      jz.f[0] = fs[0];
+      jz.f[1] = fs[1];
+      jz.scale = 0.125f;
+      hipLaunchKernelGGL((sfb3_kernel<2, true>), dim3(dt_grid_y(nn, 4), 4), dim3(256), 0, s, gl, jy);
+      hipLaunchKernelGGL((sfb3_kernel<1, true>), dim3(dt_grid_y(nn, 2), 2), dim3(256), 0, s, gl, jx);
+      hipLaunchKernelGGL((sfb3_kernel<0, true>), dim3(dt_grid_y(nn, 1), 1), dim3(256), 0, s, gl, jz);
+    }
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_prox_dtcwt(const ProxGeom& pg, int levels, const float2* v, float2* z, float tau, float2* work,
                              hipStream_t s) {
+  if (pg.lateral_dims == 2) return launch_prox_dtcwt3(pg, levels, v, z, tau, work, s);
   const int64_t n = (int64_t)pg.B * pg.Nx * pg.Nz;
   const DtWork w = dt_work(work, n);
   const DtGeom g0{pg.B, pg.Nx, pg.Nz, pg.Nx, pg.Nz};
@@ -572,6 +898,11 @@ hipError_t launch_prox_dtcwt(const ProxGeom& pg, int levels, const float2* v, fl
 
 hipError_t launch_dtcwt_value(const ProxGeom& pg, int levels, const float2* x, float2* work, double* partial,
                               hipStream_t s) {
+  if (pg.lateral_dims == 2) {
+    const int64_t n = (int64_t)pg.B * pg.Ny * pg.Nx * pg.Nz;
+    const Dt3Geom g0{pg.B, pg.Ny, pg.Nx, pg.Nz, pg.Ny, pg.Nx, pg.Nz};
+    return dt3_analysis(g0, levels, x, dt3_work(work, n), 1, 0.f, partial, s);
+  }
   const int64_t n = (int64_t)pg.B * pg.Nx * pg.Nz;
   const DtWork w = dt_work(work, n);
   const DtGeom g0{pg.B, pg.Nx, pg.Nz, pg.Nx, pg.Nz};

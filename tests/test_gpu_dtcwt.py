@@ -1,7 +1,7 @@
-"""The DT-CWT penalty of Sec. 2.2 (B-scans) through the C ABI against the FP64
-oracle on the same float32 inputs: the shrinkage step at several sizes and
-levels (and the full B-scan), perfect reconstruction at tau = 0, FISTA with
-its objective history, and the rejected cases."""
+"""The DT-CWT penalty of Sec. 2.2 (B-scans and volumes) through the C ABI
+against the FP64 oracle on the same float32 inputs: the shrinkage step at
+several sizes and levels (and the full B-scan), perfect reconstruction at
+tau = 0, FISTA with its objective history, and the rejected cases."""
 import numpy as np
 import pytest
 
@@ -50,13 +50,56 @@ def test_prox_dtcwt_full_bscan():
     plan.close()
 
 
+VOL_CASES = [
+    (dict(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=32), 2, 0.3),
+    (dict(n_depth=64, n_x=32, n_y=16, lateral_dims=2, n_k=32, batch=2), 3, 0.2),
+    (dict(n_depth=16, n_x=16, n_y=16, lateral_dims=2, n_k=16), 4, 0.1),
+]
+
+
+@pytest.mark.parametrize("kw,levels,tau", VOL_CASES)
+def test_prox_dtcwt_volume_matches_oracle(kw, levels, tau):
+    import paper_2108_01438_amd as P
+    flush(f"[dtcwt prox volume] {kw} levels={levels}")
+    og, pg = both_geoms(**kw)
+    rng = np.random.default_rng(93)
+    v32, v64 = rand_image(rng, O.img_shape(og))
+    plan = P.Plan(pg)
+    z = to_host(plan.prox("dtcwt", tau, 1.0, to_dev(v32), haar_levels=levels))
+    assert rel(z, O.prox_dtcwt(v64, tau, (3, 2, 1), levels)) <= PROX_TOL
+    z0 = to_host(plan.prox("dtcwt", 0.0, 1.0, to_dev(v32), haar_levels=levels))
+    assert rel(z0, v64) <= 2e-6
+    plan.close()
+
+
+def test_fista_dtcwt_volume_matches_oracle():
+    import paper_2108_01438_amd as P
+    flush("[dtcwt fista volume]")
+    og, pg = both_geoms(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=48)
+    rng = np.random.default_rng(94)
+    x_true = synth.scatterers(rng, O.img_shape(og), 30)
+    y_clean = O.forward(x_true, og)
+    y32 = synth.noisy(y_clean, synth.standard_normal(rng, y_clean.shape), None, 0.01).astype(np.float32)
+    y64 = y32.astype(np.float64)
+    lam = 0.01 * O.lambda_max(y64, og)
+    delta = O.step_size(O.lipschitz(og, None, iters=50))
+    zo, ho = O.fista(y64, og, None, O.PEN_DTCWT, lam, delta, 12, haar_levels=2)
+    plan = P.Plan(pg)
+    z, info = plan.mbir_solve(to_dev(y32), "dtcwt", lam, 12, delta=delta, haar_levels=2, objective=True)
+    assert rel(to_host(z), zo) <= SOLVE_TOL
+    np.testing.assert_allclose(info["objective"], ho, rtol=1e-5)
+    plan.close()
+
+
 def test_dtcwt_rejections():
     import paper_2108_01438_amd as P
     og, pg = both_geoms(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=32)
     plan = P.Plan(pg)
     v = to_dev(np.zeros(O.img_shape(og), np.complex64))
-    with pytest.raises(P.OctError, match="B-scans"):
-        plan.prox("dtcwt", 0.1, 1.0, v)
+    with pytest.raises(P.OctError, match="levels"):
+        plan.prox("dtcwt", 0.1, 1.0, v, haar_levels=5)
+    with pytest.raises(P.OctError, match="divisible"):
+        plan.prox("dtcwt", 0.1, 1.0, v, haar_levels=4)
     plan.close()
     og, pg = both_geoms(n_depth=36, n_x=16, n_k=32)
     plan = P.Plan(pg)
