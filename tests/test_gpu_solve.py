@@ -166,3 +166,39 @@ def test_fista_warm_start_resume():
     z, _ = plan.mbir_solve(to_dev(y32), "l1", lam, 3, delta=delta, x0=to_dev(x032))
     zo, _ = O.fista(y32.astype(np.float64), og, None, O.PEN_L1, lam, delta, 3, x0=x064)
     assert rel(to_host(z), zo) <= SOLVE_TOL
+
+
+def test_solve_replays_bitwise_from_a_graph():
+    """A whole solve (TV, batch of two) captured in a graph replays bitwise
+    equal to the eager solve, with the caller's own work (zeroing the output)
+    and synchronisation between the replays."""
+    import torch
+    import paper_2108_01438_amd as P
+    flush("[fista] graph capture")
+    og, pg = both_geoms(n_depth=128, n_x=48, n_k=128, batch=2)
+    rng = np.random.default_rng(12)
+    mask = synth.mask_random_exact(rng, (1, og.n_x), og.n_k, og.n_k // 2)
+    _, y = _problem(og, rng, 20, mask)
+    plan = P.Plan(pg, mask)
+    yd = to_dev(y.astype(np.float32))
+    lam, delta = 0.005 * O.lambda_max(y, og, mask), O.step_size(O.lipschitz(og, mask, iters=20))
+    z = torch.empty(O.img_shape(og), dtype=torch.complex64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.mbir_solve(yd, "tv", lam, 8, delta=delta, tv_inner=10, x_out=z)   # allocates the solver state
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    plan.mbir_solve(yd, "tv", lam, 8, delta=delta, tv_inner=10, x_out=z)
+    torch.cuda.synchronize()
+    ref = to_host(z).copy()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.mbir_solve(yd, "tv", lam, 8, delta=delta, tv_inner=10, x_out=z)
+    for _ in range(3):
+        z.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(z), ref)
+    plan.close()
