@@ -410,7 +410,7 @@ __global__ void tv_value_kernel(TvIdx d, const float2* __restrict__ z, double* p
 // n_inner + 1 the dual is exact on the core grown by one sample, which is
 // what z = v + tau div p and TV(z) on the core need.
 // ---------------------------------------------------------------------------
-constexpr int TV_S = 6;
+constexpr int TV_S = 8;
 constexpr int TV_WAVES = 16;
 
 // Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1, zero filled at the
@@ -436,7 +436,9 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   __shared__ float2 xr[TV_WAVES + 1][64];
   __shared__ float2 xd[TV_WAVES + 1][64];
   __shared__ double sh[16];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the wave index is uniform: strip positions and lateral edge weights stay in
+  // scalar registers
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int bid = blockIdx.x;
   const int G = gridDim.x;
   if ((G & 7) == 0) {  // neighbouring tiles (shared halos) on the same XCD
@@ -467,7 +469,8 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   // FGP state per pixel: the extrapolated dual r and the previous dual P,
   // kept pre-multiplied by the momentum of the step that consumes it, so that
   // r = (1 + mom_k) p_k - mom_k p_{k-1} is one fused multiply-add per
-  // component (mom after the last step is 1: P ends as the plain dual).
+  // component (mom after the last step is 1: P ends as the plain dual).  P is
+  // updated in place: each pixel reads its old P before writing the new one.
   float2 v[TV_S], Pz[TV_S], Pl[TV_S], rz[TV_S], rl[TV_S];
   float sl[TV_S];
   const float mom0 = a.mom[0];
@@ -484,11 +487,7 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
     Pz[s] = cscale(rz[s], mom0);
     Pl[s] = cscale(rl[s], mom0);
   }
-  // One FGP step from the previous dual Pi into Po.  The loop below runs the
-  // steps in pairs with the two dual sets swapping roles, so that no
-  // register copies are carried around the loop.
-  auto fgp_step = [&](int k, float2 (&Piz)[TV_S], float2 (&Pil)[TV_S], float2 (&Poz)[TV_S],
-                      float2 (&Pol)[TV_S]) __attribute__((always_inline)) {
+  for (int k = 0; k < a.n_inner; ++k) {
     const float mom1 = 1.f + a.mom[k];
     const float mnext = a.mom[k + 1];
     xr[w + 1][lane] = rl[TV_S - 1];
@@ -513,24 +512,10 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
       // projection onto |p| <= 1: 1/sqrt(m2) when m2 > 1, else 1 (m2 = 0 included)
       const float sc = fminf(1.f, __builtin_amdgcn_rsqf(m2));
       const float ca = mom1 * sc, cb = mnext * sc;
-      rz[s] = make_float2(fmaf(ca, qz.x, -Piz[s].x), fmaf(ca, qz.y, -Piz[s].y));
-      rl[s] = make_float2(fmaf(ca, ql.x, -Pil[s].x), fmaf(ca, ql.y, -Pil[s].y));
-      Poz[s] = cscale(qz, cb);
-      Pol[s] = cscale(ql, cb);
-    }
-  };
-  float2 Qz[TV_S], Ql[TV_S];
-  int k = 0;
-  for (; k + 1 < a.n_inner; k += 2) {
-    fgp_step(k, Pz, Pl, Qz, Ql);
-    fgp_step(k + 1, Qz, Ql, Pz, Pl);
-  }
-  if (k < a.n_inner) {
-    fgp_step(k, Pz, Pl, Qz, Ql);
-#pragma unroll
-    for (int s = 0; s < TV_S; ++s) {
-      Pz[s] = Qz[s];
-      Pl[s] = Ql[s];
+      rz[s] = make_float2(fmaf(ca, qz.x, -Pz[s].x), fmaf(ca, qz.y, -Pz[s].y));
+      rl[s] = make_float2(fmaf(ca, ql.x, -Pl[s].x), fmaf(ca, ql.y, -Pl[s].y));
+      Pz[s] = cscale(qz, cb);
+      Pl[s] = cscale(ql, cb);
     }
   }
   // z = v + tau div p  (P holds p after the last step)
