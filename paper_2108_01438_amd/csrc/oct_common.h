@@ -5,7 +5,7 @@
 #include <stdint.h>
 
 #define OCT_MAX_STAGES 16
-#define OCT_KB_DEG 9             // degree of each KB polynomial piece
+#define OCT_KB_DEG 7             // degree of each KB polynomial piece
 #define OCT_MAX_J 8
 // transform lengths with compile-time FFT code: oversampled grids (sigma = 2
 // on 512 .. 4096 depth samples) and lateral lengths of the common scan sizes

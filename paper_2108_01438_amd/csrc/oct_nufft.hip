@@ -12,7 +12,7 @@
 // is bitwise reproducible.
 //
 // Coordinates are formed in FP64 (t reaches ~1e4 cells and its fraction
-// must be good to ~1e-7); the KB weights come from degree-9 polynomial
+// must be good to ~1e-7); the KB weights come from degree-7 polynomial
 // pieces, one per tap, in x = 2 frac(t) - 1, evaluated in FP32.
 #include "oct_fft.h"
 
