@@ -364,6 +364,7 @@ NufftArgs nufft_args(const oct_plan* p) {
   a.Nlat = (int)p->Nlat;
   a.n_cols = (int)(p->B * p->Nlat);
   a.ct = p->ct;
+  a.invK = 1.0 / (double)p->K;
   a.df = p->df;
   a.k_min = p->g.k_min;
   a.dk = p->dk;

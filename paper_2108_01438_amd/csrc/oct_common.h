@@ -125,6 +125,7 @@ struct NufftArgs {
   int Nz, Mk, K, nc, J, Nlat;
   int n_cols;
   double ct;             // K dz / (2 pi): oversampled-grid coordinate per unit beta
+  double invK;           // 1 / K
   double df;             // z_f - n_c dz (focus offset); 0 skips its phase
   double k_min, dk;      // linear wavenumber grid k_m = k_min + m dk
   const double* k2x4;    // [Mk] 4 k_m^2

@@ -13,12 +13,24 @@
 //
 // Coordinates are formed in FP64 (t reaches ~1e4 cells and its fraction
 // must be good to ~1e-7); the KB weights come from degree-7 polynomial
-// pieces, one per tap, in x = 2 frac(t) - 1, evaluated in FP32.
+// pieces, one per tap, in x = 2 frac(t) - 1, evaluated in FP32.  The forward
+// kernel keeps KPAD wrapped copies of the grid on each side of it in LDS, so
+// that a sample's J taps are J consecutive cells with no per-tap wrap.
 #include "oct_fft.h"
 
 namespace {
 
 constexpr int KBD = OCT_KB_DEG;
+constexpr int KPAD = 8;   // wrapped cells on each side of the forward grid (>= J/2 + 1)
+
+// beta = sqrt(arg), arg > 0: the FP32 reciprocal square root refined by one
+// Newton step in FP64 (relative error ~2e-14, i.e. ~3e-10 cells at t ~ 1e4).
+__device__ __forceinline__ double beta_of(double arg) {
+  const double r0 = (double)__builtin_amdgcn_rsqf(fmaxf((float)arg, 1e-30f));
+  const double h = arg * r0;            // sqrt(arg) to FP32 accuracy
+  const double e = fma(-h, r0, 1.0);    // 1 - arg r0^2
+  return fma(0.5 * h, e, h);
+}
 
 // Tap jj < J/2 is P(x) = E(x^2) + x O(x^2); the mirrored tap J-1-jj is
 // P(-x) = E(x^2) - x O(x^2) (the window is even).  c holds E then O, each
@@ -124,7 +136,8 @@ struct KPR {
 template <int J, bool ONE>
 __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const float2* __restrict__ X1,
                                                          float2* __restrict__ W) {
-  extern __shared__ float2 grid[];
+  extern __shared__ float2 gridp[];
+  float2* grid = gridp + KPAD;   // cells [-KPAD, K + KPAD)
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int col = blockIdx.x;
   const int lat = col % a.Nlat;
@@ -142,6 +155,11 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
               });
   __syncthreads();
   fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(grid, 1, K, a.fK, twl, tid, nthr);
+  if (tid < 2 * KPAD) {   // cells -KPAD..-1 and K..K+KPAD-1 (K >= 2J >= KPAD)
+    const int c = tid < KPAD ? tid - KPAD : K + tid - KPAD;
+    grid[c] = grid[tid < KPAD ? c + K : c - K];
+  }
+  __syncthreads();
 
   const double q2 = a.q2[lat];
   const float bq = a.beam[lat];
@@ -151,22 +169,22 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
     const double arg = kp.k2 - q2;
     float2 res = make_float2(0.f, 0.f);
     if (arg > 0.0) {
-      const double beta = sqrt(arg);
+      const double beta = beta_of(arg);
       const double t = a.ct * beta;
-      const double fl = floor(t);
-      const float x = (float)(2.0 * (t - fl) - 1.0);
-      int c0 = ((int)fl - J / 2 + 1) % K;
-      if (c0 < 0) c0 += K;
+      // t mod K (exact: the product is an integer and the difference is
+      // representable; a misrounded quotient leaves it one ulp outside [0, K),
+      // which the pads absorb); frac(t mod K) = frac(t)
+      const double tw = fma(-(double)K, floor(t * a.invK), t);
+      const double fl = floor(tw);
+      const float x = (float)(2.0 * (tw - fl) - 1.0);
+      const int c0 = (int)fl - J / 2 + 1;   // in [-J/2, K - J/2 + 1]
       float2 acc = make_float2(0.f, 0.f);
       const float x2 = x * x;
 #pragma unroll
       for (int jj = 0; jj < J / 2; ++jj) {
         float wlo, whi;
         kb_pair(a.kbc + jj * 2 * KBH, x, x2, wlo, whi);
-        int i0 = c0 + jj, i1 = c0 + J - 1 - jj;
-        if (i0 >= K) i0 -= K;
-        if (i1 >= K) i1 -= K;
-        const float2 g0 = grid[i0], g1 = grid[i1];
+        const float2 g0 = grid[c0 + jj], g1 = grid[c0 + J - 1 - jj];
         acc.x = fmaf(wlo, g0.x, acc.x);
         acc.y = fmaf(wlo, g0.y, acc.y);
         acc.x = fmaf(whi, g1.x, acc.x);
@@ -211,7 +229,7 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
     const KPR v{a.k2x4[m], a.phase[m], rin[m]};
     const double arg = v.k2 - q2;
     if (arg > 0.0) {
-      const double beta = sqrt(arg);
+      const double beta = beta_of(arg);
       const double t = a.ct * beta;
       const double fl = floor(t);
       bm[m] = (short)(int)fl;               // t < 32000 (checked at plan creation)
@@ -348,7 +366,13 @@ int nufft_adj_threads(const NufftArgs& a) {
 
 template <int J, bool ONE>
 hipError_t nufft_fwd_t(const NufftArgs& a, const float2* X1, float2* W, int nthr, hipStream_t s) {
-  const size_t lds = (size_t)a.K * sizeof(float2);
+  const size_t lds = (size_t)(a.K + 2 * KPAD) * sizeof(float2);
+  if (lds > 64 * 1024) {
+    // once per instantiation (thread-safe initialisation of a local static)
+    static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_fwd_kernel<J, ONE>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    if (set != hipSuccess) return set;
+  }
   hipLaunchKernelGGL((nufft_fwd_kernel<J, ONE>), dim3(a.n_cols), dim3(nthr), lds, s, a, X1, W);
   return hipGetLastError();
 }
