@@ -77,6 +77,10 @@ struct YM {
   uint32_t ma, mb;
 };
 
+// float2 slots of the tile in LDS, rounded up to keep the twiddle rows that
+// follow it 16-byte aligned
+__host__ __device__ inline int lat_tile_f2(int T, int rs) { return (T * rs + 1) & ~1; }
+
 template <int MODE, bool ONE>
 __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   extern __shared__ float2 lds[];
@@ -99,7 +103,15 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   const int n = L * T;
   const int lt = a.log2T;
 
-  const float2* __restrict__ twl = a.tw;
+  // The transform's twiddle rows are copied next to the tile, so the
+  // transform waits on no global load (the late loads below stay in flight
+  // through it).
+  float2* twl = lds + lat_tile_f2(T, rs);
+  {
+    const float4* __restrict__ s4 = reinterpret_cast<const float4*>(a.tw);
+    float4* d4 = reinterpret_cast<float4*>(twl);
+    for (int i = tid; i < (a.fd.tw_total >> 1); i += nthr) d4[i] = s4[i];
+  }
   // modes that need only real parts (or transform real rows) pair rows p and p + H
   constexpr bool REAL_PAIRS = MODE == LAT_FWD_MEAS || MODE == LAT_ADJ_MEAS || MODE == LAT_NORMAL ||
                                MODE == LAT_RESID;
@@ -114,6 +126,39 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   };
   auto mword = [&](int l, int row) -> uint32_t {
     return a.mask ? a.mask[(int64_t)(latb + l) * a.mask_words + (row >> 5)] : ~0u;
+  };
+
+  // Loads consumed after the transform (the iterate pair z, z_prev of the
+  // gradient step; the data and mask of the normal seam).  When they fit
+  // PF per thread they are issued right after the tile's own loads and stream
+  // in while the tile is transformed (load counters retire in order, so they
+  // must come after every load the transform waits for).
+  constexpr bool LATE_Z = MODE == LAT_UPDATE || MODE == LAT_UPDATE_L1;
+  constexpr bool LATE_Y = MODE == LAT_NORMAL;
+  constexpr int PF = 8;
+  const int log2H = lt - 1;
+  auto load_z = [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; };
+  auto load_y = [&](int idx) {
+    const int l = idx >> log2H, p = idx & (H - 1);
+    const int pa = min(p, nr - 1), pb = min(p + H, nr - 1);
+    const int64_t oa = base + (int64_t)l * lg.es + pa, ob = base + (int64_t)l * lg.es + pb;
+    return YM{a.y ? a.y[oa] : 0.f, a.y ? a.y[ob] : 0.f, mword(l, r0 + pa), mword(l, r0 + pb)};
+  };
+  using Late = std::conditional_t<LATE_Y, YM, Z2>;
+  const int n_late = LATE_Y ? (n >> 1) : n;
+  const bool early = (LATE_Z || (LATE_Y && pair)) && n_late <= PF * nthr;
+  Late pf[PF];
+  // run use(idx, value) over the late elements, prefetched or loaded now
+  auto late_for = [&](auto load, auto use) __attribute__((always_inline)) {
+    if (early) {
+#pragma unroll
+      for (int i = 0; i < PF; ++i) {
+        const int idx = tid + i * nthr;
+        if (idx < n_late) use(idx, pf[i]);
+      }
+    } else {
+      batched_for(n_late, tid, nthr, load, use);
+    }
   };
 
   // ---- load the tile: element (row t, lateral l) -> lds[t * rs + l]
@@ -144,6 +189,19 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
         const int l = idx >> lt, t = idx & (T - 1);
         lds[t * rs + l] = t < nr ? v : make_float2(0.f, 0.f);
       });
+  }
+  // retire the tile's loads (including the clamped ones nobody reads), so
+  // that no register the transform reuses waits on the late loads
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+  if (early) {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int idx = tid + i * nthr;
+      if (idx < n_late) {
+        if constexpr (LATE_Y) pf[i] = load_y(idx);
+        else pf[i] = load_z(idx);
+      }
+    }
   }
   __syncthreads();
   if ((MODE == LAT_FWD_MEAS || MODE == LAT_NORMAL || MODE == LAT_RESID) && pair) {
@@ -177,9 +235,8 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       });
     return;
   }
-  if (MODE == LAT_UPDATE) {
-    batched_for(n, tid, nthr,
-      [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; },
+  if constexpr (MODE == LAT_UPDATE) {
+    late_for(load_z,
       [&](int idx, Z2 v) {
         const int l = idx >> lt, t = idx & (T - 1);
         if (t < nr) {
@@ -210,17 +267,10 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     if (tid == 0 && a.partial) a.partial[bid] = s;
     return;
   }
-  if (MODE == LAT_NORMAL && pair) {
+  if constexpr (MODE == LAT_NORMAL) if (pair) {
     // residual of rows p and p + H from the real and imaginary parts of row p
     double acc = 0.0;
-    const int log2H = lt - 1;
-    batched_for(n >> 1, tid, nthr,
-      [&](int idx) {
-        const int l = idx >> log2H, p = idx & (H - 1);
-        const int pa = min(p, nr - 1), pb = min(p + H, nr - 1);
-        const int64_t oa = base + (int64_t)l * lg.es + pa, ob = base + (int64_t)l * lg.es + pb;
-        return YM{a.y ? a.y[oa] : 0.f, a.y ? a.y[ob] : 0.f, mword(l, r0 + pa), mword(l, r0 + pb)};
-      },
+    late_for(load_y,
       [&](int idx, YM v) {
         const int l = idx >> log2H, p = idx & (H - 1);
         const float2 vv = lds[p * rs + l];
@@ -263,10 +313,9 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     if (tid == 0 && a.partial) a.partial[bid] = s;
     return;
   }
-  if (MODE == LAT_UPDATE_L1) {
+  if constexpr (MODE == LAT_UPDATE_L1) {
     double acc = 0.0;
-    batched_for(n, tid, nthr,
-      [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; },
+    late_for(load_z,
       [&](int idx, Z2 v) {
         const int l = idx >> lt, t = idx & (T - 1);
         float2 xn = make_float2(0.f, 0.f);
@@ -321,20 +370,31 @@ int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* row
   return 0;
 }
 
+template <int MODE, bool ONE>
+hipError_t launch_lateral_m(const LatArgs& a, int nthr, hipStream_t s) {
+  const size_t lds = ((size_t)lat_tile_f2(a.T, a.rowstride) + (size_t)a.fd.tw_total) * sizeof(float2);
+  if (lds > 64 * 1024) {
+    // once per instantiation (thread-safe initialisation of a local static)
+    static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void*>(&lat_kernel<MODE, ONE>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    if (set != hipSuccess) return set;
+  }
+  hipLaunchKernelGGL((lat_kernel<MODE, ONE>), dim3(a.lg.n_lines * a.n_tiles), dim3(nthr), lds, s, a);
+  return hipGetLastError();
+}
+
 template <bool ONE>
 hipError_t launch_lateral_t(LatMode mode, const LatArgs& a, int nthr, hipStream_t s) {
-  const size_t lds = (size_t)a.T * a.rowstride * sizeof(float2);
-  const int grid = a.lg.n_lines * a.n_tiles;
   switch (mode) {
-    case LAT_FFT: hipLaunchKernelGGL((lat_kernel<LAT_FFT, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_FWD_MEAS: hipLaunchKernelGGL((lat_kernel<LAT_FWD_MEAS, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_ADJ_MEAS: hipLaunchKernelGGL((lat_kernel<LAT_ADJ_MEAS, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_NORMAL: hipLaunchKernelGGL((lat_kernel<LAT_NORMAL, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_UPDATE: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_UPDATE_L1: hipLaunchKernelGGL((lat_kernel<LAT_UPDATE_L1, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
-    case LAT_RESID: hipLaunchKernelGGL((lat_kernel<LAT_RESID, ONE>), dim3(grid), dim3(nthr), lds, s, a); break;
+    case LAT_FFT: return launch_lateral_m<LAT_FFT, ONE>(a, nthr, s);
+    case LAT_FWD_MEAS: return launch_lateral_m<LAT_FWD_MEAS, ONE>(a, nthr, s);
+    case LAT_ADJ_MEAS: return launch_lateral_m<LAT_ADJ_MEAS, ONE>(a, nthr, s);
+    case LAT_NORMAL: return launch_lateral_m<LAT_NORMAL, ONE>(a, nthr, s);
+    case LAT_UPDATE: return launch_lateral_m<LAT_UPDATE, ONE>(a, nthr, s);
+    case LAT_UPDATE_L1: return launch_lateral_m<LAT_UPDATE_L1, ONE>(a, nthr, s);
+    case LAT_RESID: return launch_lateral_m<LAT_RESID, ONE>(a, nthr, s);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_lateral(LatMode mode, const LatArgs& a, hipStream_t s) {

@@ -20,6 +20,10 @@ CASES = {
     "bscan_j4_128x30": dict(n_depth=128, n_x=30, n_k=128, kb_width=4),
     "bscan_j8_128x42_k256": dict(n_depth=128, n_x=42, n_k=256, kb_width=8),
     "bscan_sigma25_96x24": dict(n_depth=96, n_x=24, n_k=100, oversamp=2.5),
+    # sample spacing below one grid cell: the adjoint gathers cell by cell
+    "bscan_sigma15_128x32": dict(n_depth=128, n_x=32, n_k=128, oversamp=1.5),
+    # more samples than grid cells in a column: several phases of the gather
+    "bscan_k3n_64x24": dict(n_depth=64, n_x=24, n_k=192),
     "ascan_single_256": dict(n_depth=256, n_x=1, n_k=256),
     "evanescent_64x32": dict(n_depth=64, n_x=32, n_k=64, k_min=0.3, k_max=0.9, dx=0.5),
     "volume_64x16x12_b2": dict(n_depth=64, n_x=16, n_y=12, lateral_dims=2, n_k=96, batch=2),
