@@ -221,13 +221,19 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
   short* bm = reinterpret_cast<short*>(xm + Mk);
   short* first = bm + Mk;                   // [K] first contributing sample of each cell
 
+  // first propagating sample (the evanescent ones form a prefix: lowest k),
+  // written by that sample alone; Mk when there is none
+  __shared__ int s_mf;
+  if (tid == 0) s_mf = Mk;
   for (int i = tid; i < J * KBH; i += nthr) kc[i] = a.kbc[i];
   const double q2 = a.q2[lat];
   const float bq = a.beam[lat];
   const float2* __restrict__ rin = Rh + (int64_t)col * Mk;
+  __syncthreads();
   for (int m = tid; m < Mk; m += nthr) {
     const KPR v{a.k2x4[m], a.phase[m], rin[m]};
     const double arg = v.k2 - q2;
+    if (arg > 0.0 && (m == 0 || a.k2x4[m - 1] - q2 <= 0.0)) s_mf = m;
     if (arg > 0.0) {
       const double beta = beta_of(arg);
       const double t = a.ct * beta;
@@ -243,13 +249,7 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
   }
   __syncthreads();
 
-  // first propagating sample (evanescent ones form a prefix: lowest k)
-  int lo = 0, hi = Mk;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (bm[mid] == EVANESCENT16) lo = mid + 1; else hi = mid;
-  }
-  const int mf = lo;
+  const int mf = s_mf;
   int umin = 0, umax = -1;
   if (mf < Mk) {
     umin = bm[mf] - J / 2 + 1;
