@@ -358,8 +358,10 @@ size_t nufft_adj_lds_bytes(const NufftArgs& a) {
 }
 
 int nufft_adj_threads(const NufftArgs& a) {
-  // every thread keeps at most ADJ_MAXC grid cells in registers
-  int nt = nufft_threads(a, 512);
+  // every thread keeps at most ADJ_MAXC grid cells in registers; with many
+  // columns (batches, volumes) narrower groups keep more columns in flight
+  // per CU, which hides their barrier-separated phases better
+  int nt = nufft_threads(a, a.n_cols >= 4096 ? 256 : 512);
   while (nt < 1024 && (a.K + nt - 1) / nt > ADJ_MAXC) nt <<= 1;
   return nt;
 }

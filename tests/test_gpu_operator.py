@@ -29,6 +29,8 @@ CASES = {
     "volume_64x16x12_b2": dict(n_depth=64, n_x=16, n_y=12, lateral_dims=2, n_k=96, batch=2),
     "volume_128x8x8": dict(n_depth=128, n_x=8, n_y=8, lateral_dims=2, n_k=128),
     "wide_2000x64": dict(n_depth=64, n_x=2000, n_k=64),
+    # 4096 columns: the adjoint runs narrower workgroups
+    "many_columns_64x1024_b4": dict(n_depth=64, n_x=1024, n_k=64, batch=4),
 }
 
 
