@@ -57,16 +57,11 @@ struct FftDesc {
 __host__ __device__ constexpr int fft_tw_pad(int R) { return R & ~1; }
 
 // butterflies per thread the kernels may use for a transform of this shape
-inline int fft_maxb(const FftDesc& d) {
-  for (int s = 0; s < d.nstages; ++s)
-    if (d.radix[s] == 7) return 1;
-  return 2;
-}
-inline bool fft_has7(const FftDesc& d) { return fft_maxb(d) == 1; }
-// the one-butterfly variant serves radix 7 and every launch whose threads
-// cover a stage of the narrowest radix
+inline int fft_maxb(const FftDesc&) { return 2; }
+// the one-butterfly variant serves every launch whose threads cover a stage
+// of the narrowest radix
 inline bool fft_one(const FftDesc& d, int64_t rows, int nthr) {
-  return fft_has7(d) || rows * (d.n / d.min_radix) <= nthr;
+  return rows * (d.n / d.min_radix) <= nthr;
 }
 
 // Lines of a lateral transform.  Element (line o, lateral index l, row i) of a

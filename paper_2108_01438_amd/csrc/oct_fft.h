@@ -257,9 +257,8 @@ __device__ __forceinline__ void fft_stage(float2* buf, int nrows, int rowstride,
 }
 
 // Full transform of `nrows` rows in LDS; all threads of the block participate.
-// ONE selects the variant with one butterfly per thread and stage, which
-// also carries the radix-7 stages (their register footprint is larger); the
-// other variant runs up to two butterflies per thread.
+// ONE selects the variant with one butterfly per thread and stage (fewer
+// registers); the other variant runs up to two butterflies per thread.
 template <bool ONE>
 struct FftCfg {
   static constexpr int MAXB = ONE ? 1 : 2;
@@ -278,9 +277,7 @@ __device__ __forceinline__ void fft_rows(float2* buf, int nrows, int rowstride, 
       case 2: fft_stage<2, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr); break;
       case 5: fft_stage<5, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr); break;
       case 3: fft_stage<3, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr); break;
-      default:
-        if (ONE) fft_stage<7, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr);
-        break;
+      default: fft_stage<7, MB, INV>(buf, nrows, rowstride, d.n, Ns, d.div_nb[s], d.div_ns[s], t, tid, nthr); break;
     }
   }
 }

@@ -55,7 +55,6 @@ int literal_dq_threads(const FftDesc& fN, const FftDesc& fM, bool* one) {
       *one = true;
       return nt;
     }
-  if (fft_has7(fN) || fft_has7(fM)) return 0;
   for (int nt = 256; nt <= 1024; nt <<= 1)
     if (bN <= 2 * nt && bM <= 2 * nt) {
       *one = false;

@@ -19,6 +19,7 @@ GEOMS = [
     dict(n_depth=96, n_x=24, n_k=192, batch=2, model=1),           # radix 3 in both transforms
     dict(n_depth=32, n_x=12, n_y=10, lateral_dims=2, n_k=64, model=1),
     dict(n_depth=1024, n_x=64, n_k=2048, model=1),                 # compile-time transforms
+    dict(n_depth=2016, n_x=8, n_k=4032, model=1),                  # radix 7, two butterflies per thread
 ]
 
 

@@ -29,6 +29,10 @@ CASES = {
     "volume_64x16x12_b2": dict(n_depth=64, n_x=16, n_y=12, lateral_dims=2, n_k=96, batch=2),
     "volume_128x8x8": dict(n_depth=128, n_x=8, n_y=8, lateral_dims=2, n_k=128),
     "wide_2000x64": dict(n_depth=64, n_x=2000, n_k=64),
+    # K = 4032 = 2^6 3^2 7 and N_x = 3528 = 2^3 3^2 7^2: radix-7 transforms with
+    # more radix-3 butterflies per stage than threads (two per thread)
+    "radix7_k4032_2016x8": dict(n_depth=2016, n_x=8, n_k=2016),
+    "radix7_nx3528_16x3528": dict(n_depth=16, n_x=3528, n_k=16),
     # 4096 columns: the adjoint runs narrower workgroups
     "many_columns_64x1024_b4": dict(n_depth=64, n_x=1024, n_k=64, batch=4),
 }
