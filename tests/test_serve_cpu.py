@@ -145,3 +145,26 @@ def test_cancel_queued_request():
     f1.result(timeout=10)
     srv.close()
     assert len(srv.completed) == 1
+
+
+def test_serving_mix_geometries_pass_plan_validation():
+    """Every geometry the serving mix draws (7-smooth sizes, some with radix-7
+    and many radix-3 butterflies per stage) passes the plan's shape checks.
+    Without a GPU a valid plan stops at the device query (status 3); a shape
+    the kernels do not support would stop earlier with status 4."""
+    import paper_2108_01438_amd as P
+    import synth
+    seen = set()
+    for seed in (4, 5, 6):
+        for spec in synth.serving_mix(np.random.default_rng(seed), 200):
+            key = tuple(sorted(spec["geom"].items()))
+            if key in seen:
+                continue
+            seen.add(key)
+            geo = dict(synth.OPTICS)
+            geo.update(spec["geom"])
+            try:
+                P.Plan(P.Geometry.from_dict(geo)).close()
+            except P.OctError as e:
+                assert e.status != 4, (spec["geom"], str(e))
+    assert len(seen) > 100
