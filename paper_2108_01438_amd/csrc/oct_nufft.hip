@@ -319,12 +319,13 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
     }
   }
   __syncthreads();   // sample arrays are dead from here: the grid takes their place
+  int g0 = umin % K;   // grid cell of u = umin; the thread's cells follow it
+  if (g0 < 0) g0 += K;
 #pragma unroll
   for (int i = 0; i < ADJ_MAXC; ++i) {
-    const int u = umin + tid + i * nthr;
     if (tid + i * nthr < K) {
-      int g = u % K;
-      if (g < 0) g += K;
+      int g = g0 + tid + i * nthr;
+      if (g >= K) g -= K;
       grid[g] = acc[i];
     }
   }
