@@ -305,9 +305,18 @@ hipError_t haar_launch(const ProxGeom& g, const float2* v, float2* z, float tau,
 struct TvIdx {
   int Nz, Nx, Ny, nd;
   int64_t n;
+  bool fast;              // n < 2^32: coordinates by 32-bit magic divisions
+  FastDiv fz, fx, fy;
 };
 
 __device__ __forceinline__ void tv_coords(const TvIdx& d, int64_t i, int& iz, int& ix, int& iy) {
+  if (d.fast) {
+    const uint32_t u = (uint32_t)i, q1 = fdiv(u, d.fz), q2 = fdiv(q1, d.fx);
+    iz = (int)(u - q1 * (uint32_t)d.Nz);
+    ix = (int)(q1 - q2 * (uint32_t)d.Nx);
+    iy = (int)(q2 - fdiv(q2, d.fy) * (uint32_t)d.Ny);
+    return;
+  }
   iz = (int)(i % d.Nz);
   const int64_t r = i / d.Nz;
   ix = (int)(r % d.Nx);
@@ -710,6 +719,10 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
   d.Ny = (g.lateral_dims == 2) ? g.Ny : 1;
   d.nd = g.lateral_dims + 1;
   d.n = (int64_t)g.B * g.Ny * g.Nx * g.Nz;
+  d.fast = d.n < (int64_t(1) << 32);
+  d.fz = make_fastdiv((uint32_t)d.Nz);
+  d.fx = make_fastdiv((uint32_t)d.Nx);
+  d.fy = make_fastdiv((uint32_t)d.Ny);
   // batch items are independent: the y index wraps per item only for volumes;
   // for B-scans Ny = 1 and the x index never crosses a batch boundary because
   // coordinates are taken modulo each axis length.
