@@ -206,6 +206,7 @@ void dtcwt_filter_taps(int which, float* h0, int* n);
 #define TV_MAX_TILED_INNER 27
 struct Tv2dArgs {
   int Nz, Nx, H, n_inner, CZ, CL, ntz, ntl;
+  int ntiles;               // ntz * ntl * batch (the launch is padded to a multiple of 8)
   int64_t n_total;          // image elements (stride between dual components)
   float tau, step;
   float bound;              // modulus bound of the constraint set (used when the kernel is built for it)

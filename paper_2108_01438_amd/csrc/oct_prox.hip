@@ -448,12 +448,12 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
   // the wave index is uniform: strip positions and lateral edge weights stay in
   // scalar registers
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int bid = blockIdx.x;
-  const int G = gridDim.x;
-  if ((G & 7) == 0) {  // neighbouring tiles (shared halos) on the same XCD
-    const int per = G >> 3;
-    bid = (bid & 7) * per + (bid >> 3);
-  }
+  // Consecutive blocks go to the eight XCDs in turn; tile numbers are dealt
+  // so that each XCD runs a run of consecutive tiles (depth neighbours, whose
+  // halos overlap, share its L2).  The grid is padded to a multiple of 8.
+  const int per = gridDim.x >> 3;
+  const int bid = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (bid >= a.ntiles) return;
   const int tz = bid % a.ntz;
   const int tl = (bid / a.ntz) % a.ntl;
   const int b = bid / (a.ntz * a.ntl);
@@ -708,7 +708,8 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
     a.pin = p_in;
     a.pout = p_out;
     a.partial = partial;
-    const int nb = a.ntz * a.ntl * g.B;
+    a.ntiles = a.ntz * a.ntl * g.B;
+    const int nb = (a.ntiles + 7) & ~7;
     if (bound < INFINITY) hipLaunchKernelGGL(tv2d_tile_kernel<true>, dim3(nb), dim3(TV_WAVES * 64), 0, s, a);
     else hipLaunchKernelGGL(tv2d_tile_kernel<false>, dim3(nb), dim3(TV_WAVES * 64), 0, s, a);
     return hipGetLastError();
