@@ -86,12 +86,12 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   extern __shared__ float2 lds[];
   __shared__ double red[16];
   const int tid = threadIdx.x, nthr = blockDim.x;
-  int bid = blockIdx.x;
-  const int G = gridDim.x;
-  if ((G & 7) == 0) {  // consecutive tiles of a line on the same XCD (shared L2)
-    const int per = G >> 3;
-    bid = (bid & 7) * per + (bid >> 3);
-  }
+  // Consecutive blocks go to the eight XCDs in turn; tile numbers are dealt
+  // so that each XCD runs consecutive tiles of a line (their rows share cache
+  // lines in its L2).  The grid is padded to a multiple of 8.
+  const int per = gridDim.x >> 3;
+  const int bid = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (bid >= a.lg.n_lines * a.n_tiles) return;
   const LineGeom lg = a.lg;
   const int line = bid / a.n_tiles;
   const int tile = bid - line * a.n_tiles;
@@ -379,7 +379,7 @@ hipError_t launch_lateral_m(const LatArgs& a, int nthr, hipStream_t s) {
                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
     if (set != hipSuccess) return set;
   }
-  hipLaunchKernelGGL((lat_kernel<MODE, ONE>), dim3(a.lg.n_lines * a.n_tiles), dim3(nthr), lds, s, a);
+  hipLaunchKernelGGL((lat_kernel<MODE, ONE>), dim3((a.lg.n_lines * a.n_tiles + 7) & ~7), dim3(nthr), lds, s, a);
   return hipGetLastError();
 }
 
