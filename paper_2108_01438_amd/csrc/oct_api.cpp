@@ -202,6 +202,7 @@ struct oct_plan {
   float* yfill = nullptr;        // [batch][lat][Mk] real spectra (filled / residual), allocated on first use
   // solver state, allocated on first use
   float2 *za = nullptr, *zb = nullptr;
+  float2* xext = nullptr;        // the extrapolated point x of the current iteration (lat_fwd -> update)
   float2 *p0 = nullptr, *p1 = nullptr, *tvwork = nullptr;
   float2* dtwork = nullptr;      // DT-CWT trees and staging (8 images; 24 for a volume)
   double* hist = nullptr;
@@ -416,13 +417,16 @@ oct_status run_cols_adj(oct_plan* p, hipStream_t s) {
   return OCT_OK;
 }
 
-// x (image, or z + mu (z - zo) when z != NULL) -> X1 = F_lat x
-oct_status run_lat_forward(oct_plan* p, const float2* x, const float2* z, const float2* zo, float mu, hipStream_t s) {
+// x (image, or z + mu (z - zo) when z != NULL, then also stored to xout when
+// that is not NULL) -> X1 = F_lat x
+oct_status run_lat_forward(oct_plan* p, const float2* x, const float2* z, const float2* zo, float mu, hipStream_t s,
+                           float2* xout = nullptr) {
   LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
   a.src = x;
   a.z = z;
   a.zo = const_cast<float2*>(zo);
   a.mu = mu;
+  a.xout = xout;
   a.dst = p->X1;
   HIPCHK(launch_lateral(LAT_FFT, a, s));
   if (p->lat_dims == 2) {
@@ -595,6 +599,10 @@ oct_status ensure_solver_state(oct_plan* p, int pen, int iters) {
     HIPCHK(hipMemset(p->za, 0, sizeof(float2) * p->n_img()));
     HIPCHK(hipMemset(p->zb, 0, sizeof(float2) * p->n_img()));
   }
+  if (!p->xext) {
+    OCTCHK(dev_alloc(p, &p->xext, p->n_img()));
+    HIPCHK(hipMemset(p->xext, 0, sizeof(float2) * p->n_img()));
+  }
   if (pen == OCT_PEN_TV && !p->p0) {
     const int nd = p->lat_dims + 1;
     OCTCHK(dev_alloc(p, &p->p0, (size_t)p->n_img() * nd));
@@ -711,7 +719,7 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   b += (size_t)N * 8 + (size_t)M * 8;            // workspace X1, W
   if (g->model == OCT_MODEL_LITERAL)             // K's samples and the literal chain's tables
     b += (size_t)N * 8 + (size_t)g->n_depth * 16 + (size_t)g->n_k * 16;
-  b += (size_t)N * 8 * 2;                        // FISTA iterates
+  b += (size_t)N * 8 * 3;                        // FISTA iterates and the extrapolated point
   if (penalty == OCT_PEN_TV) b += (size_t)N * 8 * (2 * nd + 1 + nd);
   if (penalty == OCT_PEN_DTCWT) b += (size_t)N * 8 * (g->lateral_dims == 2 ? 24 : 8);
   b += 64 * 1024 * 8;                            // partials, scalars, history
@@ -1073,7 +1081,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   float mu_prev = 0.f;
   if (fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, 0.f, s));
   for (int k = 0; k < prm->iters; ++k) {
-    if (!fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s));
+    if (!fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s, p->xext));
     OCTCHK(run_cols_fwd(p, s));
     int nres = 0, npen = 0;
     if (paper) OCTCHK(run_normal_paper(p, y, res_part, &nres, s));
@@ -1106,9 +1114,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
       a.src = p->X1;
       a.dst = p->X1;
       a.inverse = 1;
-      a.z = zc;
-      a.zo = zo;
-      a.mu = mu_prev;
+      a.z = p->xext;   // x as the forward pass formed it
       a.delta = (float)delta;
       HIPCHK(launch_lateral(LAT_UPDATE, a, s));
       // z^k -> zo (z^{k-2} is no longer needed)
@@ -1154,7 +1160,7 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
   OCTCHK(ensure_solver_state(p, pen, 1));
   switch (stage) {
     case OCT_STAGE_LAT_FWD:
-      return run_lat_forward(p, nullptr, p->za, p->zb, 0.5f, s);
+      return run_lat_forward(p, nullptr, p->za, p->zb, 0.5f, s, p->xext);
     case OCT_STAGE_NUFFT_FWD:
       OCTCHK(run_cols_fwd(p, s));
       return OCT_OK;
@@ -1178,9 +1184,7 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
       a.src = p->X1;
       a.dst = p->X1;
       a.inverse = 1;
-      a.z = p->za;
-      a.zo = p->zb;
-      a.mu = 0.5f;
+      a.z = p->xext;
       a.delta = 1e-3f;
       HIPCHK(launch_lateral(LAT_UPDATE, a, s));
       return OCT_OK;

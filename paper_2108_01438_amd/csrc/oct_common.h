@@ -106,8 +106,9 @@ struct LatArgs {
   const float* y;
   const uint32_t* mask;  // [lat][mask_words] bits, NULL = all observed
   int mask_words;
-  const float2* z;       // current iterate z^{k-1}
+  const float2* z;       // current iterate z^{k-1} (UPDATE: the extrapolated x itself when zo is NULL)
   float2* zo;            // previous iterate z^{k-2}; receives z^k in UPDATE_L1
+  float2* xout;          // FFT with z: also stores x = z + mu (z - zo) here (nullable)
   float mu;              // momentum forming x from (z, zo)
   float mu_next;         // momentum forming the next x (UPDATE_L1)
   float delta;

@@ -137,7 +137,10 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   constexpr bool LATE_Y = MODE == LAT_NORMAL;
   constexpr int PF = 8;
   const int log2H = lt - 1;
-  auto load_z = [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; };
+  auto load_z = [&](int idx) {
+    const int64_t o = goff(idx);
+    return Z2{a.z[o], a.zo ? a.zo[o] : make_float2(0.f, 0.f)};
+  };
   auto load_y = [&](int idx) {
     const int l = idx >> log2H, p = idx & (H - 1);
     const int pa = min(p, nr - 1), pb = min(p + H, nr - 1);
@@ -179,8 +182,9 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; },
       [&](int idx, Z2 v) {
         const int l = idx >> lt, t = idx & (T - 1);
-        lds[t * rs + l] = t < nr ? make_float2(v.a.x + a.mu * (v.a.x - v.b.x), v.a.y + a.mu * (v.a.y - v.b.y))
-                                 : make_float2(0.f, 0.f);
+        const float2 x = make_float2(v.a.x + a.mu * (v.a.x - v.b.x), v.a.y + a.mu * (v.a.y - v.b.y));
+        lds[t * rs + l] = t < nr ? x : make_float2(0.f, 0.f);
+        if (a.xout && t < nr) a.xout[base + (int64_t)l * lg.es + t] = x;
       });
   } else {
     batched_for(n, tid, nthr,
