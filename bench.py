@@ -41,11 +41,11 @@ def stage_bytes(g, masked: bool) -> dict:
     M = g.batch * g.n_y * g.n_x * g.n_k
     mbits = M / 8.0 if masked else 0.0
     return {
-        "lat_fwd": 24.0 * N,                 # z, z_prev in; X1 out
+        "lat_fwd": 32.0 * N,                 # z, z_prev in; X1 and the extrapolated x out
         "nufft_fwd": 8.0 * N + 8.0 * M,      # X1 in; W out
         "normal": 20.0 * M + mbits,          # W, y, mask in; R out
         "nufft_adj": 8.0 * M + 8.0 * N,      # R in; X1 out
-        "lat_update": 32.0 * N,              # X1, z, z_prev in; v out
+        "lat_update": 24.0 * N,              # X1, x in; v out
         "prox": 48.0 * N,                    # v, dual in; z, dual out
     }
 
