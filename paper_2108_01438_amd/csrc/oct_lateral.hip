@@ -128,8 +128,9 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     return a.mask ? a.mask[(int64_t)(latb + l) * a.mask_words + (row >> 5)] : ~0u;
   };
 
-  // Loads consumed after the transform (the iterate pair z, z_prev of the
-  // gradient step; the data and mask of the normal seam).  When they fit
+  // Loads consumed after the transform (the extrapolated point, or the
+  // iterate pair z, z_prev it comes from, of the gradient step; the data and
+  // mask of the normal seam).  When they fit
   // PF per thread they are issued right after the tile's own loads and stream
   // in while the tile is transformed (load counters retire in order, so they
   // must come after every load the transform waits for).
