@@ -63,3 +63,30 @@ def test_random_geometry_matches_oracle(i):
         zo, _ = O.prox_tv(x64, 0.3, axes, inner)
         assert rel(z, zo) <= PROX_TOL
     plan.close()
+
+
+SOLVE_TOL = 1e-4
+
+
+@pytest.mark.parametrize("i", range(0, len(CASES), 8))
+@pytest.mark.parametrize("pen", ["l1", "tv"])
+def test_random_geometry_fista_matches_oracle(i, pen):
+    """Five FISTA iterations (power-iteration step from the oracle) on every
+    eighth geometry of the list, with the objective history."""
+    import paper_2108_01438_amd as P
+    kw = CASES[i]
+    flush(f"[random shape fista {i} {pen}] {kw}")
+    og, pg = both_geoms(**kw)
+    rng = np.random.default_rng(2000 + i)
+    x_true = synth.scatterers(rng, O.img_shape(og), 10)
+    y32 = O.forward(x_true, og).astype(np.float32)
+    y64 = y32.astype(np.float64)
+    lam = (0.01 if pen == "l1" else 0.005) * O.lambda_max(y64, og)
+    delta = O.step_size(O.lipschitz(og, None, iters=30))
+    penc = {"l1": O.PEN_L1, "tv": O.PEN_TV}[pen]
+    zo, ho = O.fista(y64, og, None, penc, lam, delta, 5, tv_inner=10)
+    plan = P.Plan(pg)
+    z, info = plan.mbir_solve(to_dev(y32), pen, lam, 5, delta=delta, tv_inner=10, objective=True)
+    assert rel(to_host(z), zo) <= SOLVE_TOL
+    np.testing.assert_allclose(info["objective"], ho, rtol=1e-5)
+    plan.close()
