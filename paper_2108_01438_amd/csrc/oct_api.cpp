@@ -681,8 +681,10 @@ oct_status run_prox(oct_plan* p, int pen, float tau, float bound, int tv_inner, 
   } else if (pen == OCT_PEN_TV) {
     if (tv_inner < 1 || tv_inner > 1000) return fail(OCT_E_INVALID, "tv_inner must be 1..1000");
     std::vector<float> mom = fgp_momenta(tv_inner);
-    HIPCHK(launch_prox_tv(pg, tv_inner, mom.data(), v, z, p_in, p_out, tau, bound, p->partial, p->tvwork, s));
-    *np = tv_partials(pg, tv_inner);
+    // TV(z) partials only when the value is wanted (the kernels skip it otherwise)
+    HIPCHK(launch_prox_tv(pg, tv_inner, mom.data(), v, z, p_in, p_out, tau, bound,
+                          want_value ? p->partial : nullptr, p->tvwork, s));
+    *np = want_value ? tv_partials(pg, tv_inner) : 0;
   } else if (pen == OCT_PEN_DTCWT) {
     if (bound < INFINITY) return fail(OCT_E_UNSUPPORTED, "a modulus bound with the DT-CWT step has no closed form");
     OCTCHK(check_dtcwt(p, haar_levels));

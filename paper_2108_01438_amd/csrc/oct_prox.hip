@@ -538,28 +538,36 @@ __global__ void __launch_bounds__(1024) tv2d_tile_kernel(Tv2dArgs a) {
     const float dy = (Pz[s].y - lane_prev(Pz[s].y)) + (Pl[s].y - lp.y);
     z[s] = proj(make_float2(fmaf(tau, dx, v[s].x), fmaf(tau, dy, v[s].y)));
   }
-  xd[w][lane] = z[0];
-  __syncthreads();
-  double acc = 0.0;
   const bool zcore = nin && n >= cz0 && n < cz0 + a.CZ;
+  if (a.partial) {   // TV(z) on the core as well, when the caller asks for it
+    xd[w][lane] = z[0];
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < TV_S; ++s) {
+      const int l = l0 + s;
+      const float dnx = lane_next(z[s].x), dny = lane_next(z[s].y);
+      const float2 zl = (s < TV_S - 1) ? z[s + 1] : xd[w + 1][lane];
+      if (zcore && l >= cl0 && l < cl0 + a.CL && l < Nx) {
+        float m2 = 0.f;
+        if (zedge) m2 += (dnx - z[s].x) * (dnx - z[s].x) + (dny - z[s].y) * (dny - z[s].y);
+        if (l < Nx - 1) m2 += (zl.x - z[s].x) * (zl.x - z[s].x) + (zl.y - z[s].y) * (zl.y - z[s].y);
+        acc += (double)sqrtf(m2);
+      }
+    }
+    const double sum = block_sum(acc, sh);
+    if (threadIdx.x == 0) a.partial[bid] = sum;
+  }
 #pragma unroll
   for (int s = 0; s < TV_S; ++s) {
     const int l = l0 + s;
-    const float dnx = lane_next(z[s].x), dny = lane_next(z[s].y);
-    const float2 zl = (s < TV_S - 1) ? z[s + 1] : xd[w + 1][lane];
     if (zcore && l >= cl0 && l < cl0 + a.CL && l < Nx) {
-      float m2 = 0.f;
-      if (zedge) m2 += (dnx - z[s].x) * (dnx - z[s].x) + (dny - z[s].y) * (dny - z[s].y);
-      if (l < Nx - 1) m2 += (zl.x - z[s].x) * (zl.x - z[s].x) + (zl.y - z[s].y) * (zl.y - z[s].y);
-      acc += (double)sqrtf(m2);
       const int64_t idx = ib + (int64_t)l * Nz + n;
       a.z[idx] = z[s];
       a.pout[idx] = Pz[s];
       a.pout[N + idx] = Pl[s];
     }
   }
-  const double sum = block_sum(acc, sh);
-  if (threadIdx.x == 0 && a.partial) a.partial[bid] = sum;
 }
 
 int grid_for(int64_t n, int nt) {
@@ -686,7 +694,8 @@ int tv_partials(const ProxGeom& g, int n_inner) {
   return grid_for(n, 256);
 }
 
-// p_in (nullable = zero) -> p_out; z = v + tau div p_out; partial = TV(z).
+// p_in (nullable = zero) -> p_out; z = v + tau div p_out; partial (nullable:
+// not computed) = TV(z).
 hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, const float2* v, float2* z,
                           const float2* p_in, float2* p_out, float tau, float bound, double* partial,
                           float2* work, hipStream_t s) {
@@ -743,6 +752,6 @@ hipError_t launch_prox_tv(const ProxGeom& g, int n_inner, const float* mom, cons
     hipLaunchKernelGGL(tv_step_kernel, dim3(gb), dim3(256), 0, s, d, dd, r, p_out, step, mom[k]);
   }
   hipLaunchKernelGGL(tv_div_kernel, dim3(gb), dim3(256), 0, s, d, v, p_out, tau, bound, z);
-  hipLaunchKernelGGL(tv_value_kernel, dim3(gb), dim3(256), 0, s, d, z, partial);
+  if (partial) hipLaunchKernelGGL(tv_value_kernel, dim3(gb), dim3(256), 0, s, d, z, partial);
   return hipGetLastError();
 }
