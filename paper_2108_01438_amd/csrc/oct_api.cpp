@@ -1086,8 +1086,9 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
     if (!fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s, p->xext));
     OCTCHK(run_cols_fwd(p, s));
     int nres = 0, npen = 0;
-    if (paper) OCTCHK(run_normal_paper(p, y, res_part, &nres, s));
-    else OCTCHK(run_normal(p, y, res_part, &nres, s));
+    // residual partials only for the objective
+    if (paper) OCTCHK(run_normal_paper(p, y, want_obj ? res_part : nullptr, &nres, s));
+    else OCTCHK(run_normal(p, y, want_obj ? res_part : nullptr, &nres, s));
     OCTCHK(run_cols_adj(p, s));
     if (fused_l1) {
       LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
@@ -1101,7 +1102,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
       a.delta = (float)delta;
       a.tau = tau;
       a.bound = bf;
-      a.partial = pen_part;
+      a.partial = want_obj ? pen_part : nullptr;   // |z| partials only for the objective
       npen = lat_blocks(a);
       HIPCHK(launch_lateral(LAT_UPDATE_L1, a, s));
     } else {
@@ -1169,7 +1170,7 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
     case OCT_STAGE_NORMAL: {
       if (!y) return fail(OCT_E_INVALID, "OCT_STAGE_NORMAL needs y");
       int np = 0;
-      return run_normal(p, y, p->partial, &np, s);
+      return run_normal(p, y, nullptr, &np, s);   // as in a solve without the objective
     }
     case OCT_STAGE_NUFFT_ADJ:
       OCTCHK(run_cols_adj(p, s));

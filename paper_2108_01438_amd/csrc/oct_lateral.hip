@@ -268,8 +268,10 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
           a.dstf[base + (int64_t)l * lg.es + t] = r;
         }
       });
-    const double s = block_sum_d(acc, red);
-    if (tid == 0 && a.partial) a.partial[bid] = s;
+    if (a.partial) {
+      const double s = block_sum_d(acc, red);
+      if (tid == 0) a.partial[bid] = s;
+    }
     return;
   }
   if constexpr (MODE == LAT_NORMAL) if (pair) {
@@ -282,8 +284,10 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
         float ra = 0.f, rb = 0.f;
         if (p < nr && ((v.ma >> ((r0 + p) & 31)) & 1u)) ra = vv.x * a.scale - v.ya;
         if (p + H < nr && ((v.mb >> ((r0 + p + H) & 31)) & 1u)) rb = vv.y * a.scale - v.yb;
-        acc += (double)ra * (double)ra;
-        acc += (double)rb * (double)rb;
+        if (a.partial) {
+          acc += (double)ra * (double)ra;
+          acc += (double)rb * (double)rb;
+        }
         lds[p * rs + l] = make_float2(ra, rb);
       });
     __syncthreads();
@@ -292,8 +296,10 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(unpack_real_pair(lds, rs, L, H, t, l), a.scale2);
     }
-    const double s = block_sum_d(acc, red);
-    if (tid == 0 && a.partial) a.partial[bid] = s;
+    if (a.partial) {   // the residual norm only when the caller asks for it
+      const double s = block_sum_d(acc, red);
+      if (tid == 0) a.partial[bid] = s;
+    }
     return;
   }
   if (MODE == LAT_NORMAL) {
@@ -314,8 +320,10 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
     }
-    const double s = block_sum_d(acc, red);
-    if (tid == 0 && a.partial) a.partial[bid] = s;
+    if (a.partial) {
+      const double s = block_sum_d(acc, red);
+      if (tid == 0) a.partial[bid] = s;
+    }
     return;
   }
   if constexpr (MODE == LAT_UPDATE_L1) {
@@ -345,8 +353,10 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = lds[t * rs + l];
     }
-    const double s = block_sum_d(acc, red);
-    if (tid == 0 && a.partial) a.partial[bid] = s;
+    if (a.partial) {
+      const double s = block_sum_d(acc, red);
+      if (tid == 0) a.partial[bid] = s;
+    }
     return;
   }
 }
