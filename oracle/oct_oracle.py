@@ -71,7 +71,7 @@ __all__ = [
     "prox_tv", "tv_value", "haar_forward", "haar_inverse", "haar_detail_mask",
     "prox_haar", "haar_value", "penalty_value", "splitmix64", "counter_uniform",
     "power_start", "lipschitz", "step_size", "fista_momenta", "fista",
-    "lambda_max", "paper_backward_nx1", "paper_backward", "adjoint_complex", "ncc", "direct_axial", "direct_isam", "interp_fill",
+    "lambda_max", "set_workers", "get_workers", "paper_backward_nx1", "paper_backward", "adjoint_complex", "ncc", "direct_axial", "direct_isam", "interp_fill",
     "interp_isam", "PEN_L1", "PEN_TV", "PEN_HAAR", "PEN_DTCWT",
     "maxflat_halfband_factor", "dtcwt_filters", "dtcwt_combination", "dtcwt_forward", "dtcwt_inverse", "prox_dtcwt", "dtcwt_value",
 ]
@@ -390,17 +390,52 @@ def _chunks(total: int, per: int):
         yield s, min(total, s + per)
 
 
+# Host threads for the large workloads.  With n > 1 the independent column
+# chunks of forward / adjoint run concurrently (each chunk is the same code on
+# its own slice, so the result is bitwise the one-thread result) and the
+# lateral transforms use scipy.fft's own workers.  Default: one thread.
+_WORKERS = 1
+
+
+def set_workers(n: int) -> int:
+    """Set the host threads of forward / adjoint; returns the previous value."""
+    global _WORKERS
+    prev = _WORKERS
+    _WORKERS = max(1, int(n))
+    return prev
+
+
+def get_workers() -> int:
+    return _WORKERS
+
+
+def _for_chunks(total: int, per: int, body):
+    """body(a, b) for every chunk [a, b) of range(total): in order on one
+    thread, or spread over _WORKERS threads (bodies write disjoint slices)."""
+    spans = list(_chunks(total, per))
+    if _WORKERS <= 1 or len(spans) <= 1:
+        for a, b in spans:
+            body(a, b)
+        return
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=_WORKERS) as ex:
+        for f in [ex.submit(body, a, b) for a, b in spans]:
+            f.result()
+
+
 def forward(x: np.ndarray, g: Geometry, mask=None, exact: bool = False,
             chunk: int = 256) -> np.ndarray:
     """y = diag(s) Re{ ifft_lat( H . NUFFT_q( fft_lat(x) ) ) }  (eq. (7))."""
     x = np.asarray(x, dtype=np.complex128).reshape(img_shape(g))
-    X1 = sfft.fftn(x, axes=_lat_axes(g))
+    X1 = sfft.fftn(x, axes=_lat_axes(g), workers=_WORKERS)
     cols = X1.reshape(-1, g.n_depth)
     q2 = np.broadcast_to(q_squared(g)[None], img_shape(g)[:3]).reshape(-1)
     W = np.empty((cols.shape[0], g.n_k), dtype=np.complex128)
-    for a, b in _chunks(cols.shape[0], chunk):
+
+    def body(a, b):
         W[a:b] = columns_forward(cols[a:b], q2[a:b], g, exact=exact)
-    V = sfft.ifftn(W.reshape(meas_shape(g)), axes=_lat_axes(g))
+    _for_chunks(cols.shape[0], chunk, body)
+    V = sfft.ifftn(W.reshape(meas_shape(g)), axes=_lat_axes(g), workers=_WORKERS)
     y = V.real
     if mask is not None:
         y = y * np.asarray(mask, dtype=np.float64)[None]
@@ -420,13 +455,15 @@ def adjoint_complex(R: np.ndarray, g: Geometry, exact: bool = False, chunk: int 
     """Adjoint of the model before its real part, K^H (D Q)^H diag(e^{-j Omega}),
     applied to complex spectra R (shape of the measurement)."""
     R = np.asarray(R, dtype=np.complex128).reshape(meas_shape(g))
-    Rh = sfft.fftn(R, axes=_lat_axes(g)) / _n_lat(g)
+    Rh = sfft.fftn(R, axes=_lat_axes(g), workers=_WORKERS) / _n_lat(g)
     rows = Rh.reshape(-1, g.n_k)
     q2 = np.broadcast_to(q_squared(g)[None], img_shape(g)[:3]).reshape(-1)
     X = np.empty((rows.shape[0], g.n_depth), dtype=np.complex128)
-    for a, b in _chunks(rows.shape[0], chunk):
+
+    def body(a, b):
         X[a:b] = columns_adjoint(rows[a:b], q2[a:b], g, exact=exact)
-    return sfft.ifftn(X.reshape(img_shape(g)), axes=_lat_axes(g)) * _n_lat(g)
+    _for_chunks(rows.shape[0], chunk, body)
+    return sfft.ifftn(X.reshape(img_shape(g)), axes=_lat_axes(g), workers=_WORKERS) * _n_lat(g)
 
 
 def grad(x: np.ndarray, y: np.ndarray, g: Geometry, mask=None, exact: bool = False):

@@ -352,6 +352,83 @@ def test_fista_l1_kkt_and_rate():
         assert hist[-1] >= lam * np.sum(np.abs(zk)) - 1e-12
 
 
+def _tv_fixed_point_error(g, mask, y, z, lam, delta):
+    """How far z is from a minimiser of 1/2||Phi z - y||^2 + lam TV(z)
+    (eq. (2), (14)): (1) the fixed-point residual of the FISTA map with the TV
+    prox solved to 5000 inner steps, and (2) the KKT residual with the dual
+    certificate p of that prox: grad D(z) = lam div p, |p_i| <= 1 and
+    <p, grad z> = TV(z) (so that -div p is a subgradient of TV at z)."""
+    axes = (3, 2)
+    gr, _ = O.grad(z, y, g, mask)
+    zp, p = O.prox_tv(z - delta * gr, lam * delta, axes, 5000)
+    fp = np.linalg.norm(zp - z) / np.linalg.norm(z)
+    kkt = np.linalg.norm(gr - lam * O.tv_div(p, axes)) / np.linalg.norm(gr)
+    pmax = float(np.sqrt(np.sum(np.abs(p) ** 2, axis=0)).max())
+    tv = O.tv_value(z, axes)
+    gap = (tv - float(np.real(np.sum(np.conj(p) * O.tv_grad(z, axes))))) / tv
+    return fp, kkt, pmax, gap
+
+
+def test_fista_tv_converges_to_the_tv_minimiser():
+    """Long-run FISTA-TV (10 warm-started inner steps) on the dense problem
+    reaches the minimiser of eq. (2) + lambda TV (eq. (14)): a fixed point of
+    the map with an exactly solved prox, and a KKT point with a feasible dual
+    certificate."""
+    g, mask, A, y = _dense_problem()
+    L = np.linalg.svd(A, compute_uv=False)[0] ** 2
+    delta = 1 / (1.05 * L)
+    lam = 0.02
+    z, _ = O.fista(y, g, mask, O.PEN_TV, lam, delta, 3000, tv_inner=10)
+    fp, kkt, pmax, gap = _tv_fixed_point_error(g, mask, y, z, lam, delta)
+    assert fp < 1e-8 and kkt < 1e-6
+    assert pmax <= 1 + 1e-12 and abs(gap) < 1e-9
+
+
+@pytest.mark.parametrize("mistake", ["tau_x2", "depth_axis_only", "no_warm_start"])
+def test_fista_tv_fixed_point_catches_planted_mistakes(monkeypatch, mistake):
+    """Negative controls of the pin above: the same long run with a planted
+    mistake in the TV branch of the oracle's FISTA (a doubled tau, TV along
+    depth only, the dual warm start dropped) is not at the minimiser."""
+    import oracle.oct_oracle as OO
+    real = OO.prox_tv
+
+    def planted(v, tau, axes, n_inner, p0=None, bound=None):
+        if mistake == "tau_x2":
+            return real(v, 2 * tau, axes, n_inner, p0=p0, bound=bound)
+        if mistake == "depth_axis_only":
+            x, p = real(v, tau, axes[:1], n_inner, p0=None if p0 is None else p0[:1], bound=bound)
+            return x, np.concatenate([p, np.zeros_like(p)])
+        return real(v, tau, axes, n_inner, p0=None, bound=bound)
+    monkeypatch.setattr(OO, "prox_tv", planted)
+    g, mask, A, y = _dense_problem()
+    L = np.linalg.svd(A, compute_uv=False)[0] ** 2
+    delta = 1 / (1.05 * L)
+    lam = 0.02
+    z, _ = O.fista(y, g, mask, O.PEN_TV, lam, delta, 3000, tv_inner=10)
+    monkeypatch.setattr(OO, "prox_tv", real)
+    fp, kkt, _, _ = _tv_fixed_point_error(g, mask, y, z, lam, delta)
+    assert fp > 1e-5 and kkt > 1e-3
+
+
+def test_lambda_max_is_the_zero_solution_threshold():
+    """lambda_max = ||Phi^H (s y)||_inf is the l1 weight at and above which
+    x = 0 solves eq. (2) + lambda ||x||_1: FISTA from zero stays exactly zero
+    at lambda_max (1 + 1e-9) and leaves it at 0.99 lambda_max.  The case is
+    masked and y is nonzero on the unobserved pixels, so a threshold that
+    ignored the mask would fail one of the two."""
+    g = O.Geometry(n_depth=16, n_x=8, n_k=24)
+    rng = np.random.default_rng(41)
+    mask = (rng.random((1, 8, 24)) < 0.6).astype(np.uint8)
+    y = rng.standard_normal(O.meas_shape(g))
+    lmax = O.lambda_max(y, g, mask)
+    assert lmax != pytest.approx(O.lambda_max(y, g, None), rel=1e-3)
+    delta = O.step_size(O.lipschitz(g, mask, iters=100))
+    z, _ = O.fista(y, g, mask, O.PEN_L1, lmax * (1 + 1e-9), delta, 40)
+    assert np.all(z == 0)
+    z, _ = O.fista(y, g, mask, O.PEN_L1, 0.99 * lmax, delta, 40)
+    assert np.count_nonzero(z) > 0
+
+
 def test_fista_tv_reduces_objective():
     g, mask, A, y = _dense_problem()
     L = np.linalg.svd(A, compute_uv=False)[0] ** 2
