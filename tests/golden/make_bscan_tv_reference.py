@@ -3,11 +3,15 @@
 Workload: 2048 spectral pixels x 1000 A-scans, 500 scatterers + 3 layers
 (seed 1), exactly half the pixels of each A-scan kept, 1% noise, isotropic TV
 with lambda = 0.005 lambda_max, 10 FGP steps, 100 FISTA iterations, step
-1 / (1.05 L) from a 50-step power iteration.  Only the oracle and the seeded
-generators are used.  Stores lambda, delta, the objective history, the norm of
-z^100 and z^100 at 4096 seeded pixel positions.
+1 / (1.05 L) from a 50-step power iteration.  Only the oracle, the seeded
+generators and the summary helpers are used.  Stores lambda, delta, the
+objective history, ||z^100||, z^100 at 2^18 seeded pixels and on the image
+border (first and last A-scan, first and last depth row), the norms of its
+40 x 64 (lateral x depth) tiles and a 2^16-bucket CountSketch of it
+(refstats.py).
 
-Run: python tests/golden/make_bscan_tv_reference.py   (about 10 minutes on one core)
+Run: python tests/golden/make_bscan_tv_reference.py [threads]
+(about 10 minutes on one core)
 """
 import os
 import sys
@@ -18,10 +22,16 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
+sys.path.insert(0, HERE)
+
 import oracle as O  # noqa: E402
 import synth  # noqa: E402
+import refstats  # noqa: E402
 
 OUT = os.path.join(HERE, "bscan_2048x1000_tv100.npz")
+BLOCK = (40, 64)              # (lateral, depth) tile edges of the stored tile norms
+SAMPLES, SAMPLE_SEED = 1 << 18, 13
+SKETCH_BUCKETS, SKETCH_SEED = 1 << 16, 17
 
 
 def inputs():
@@ -42,7 +52,15 @@ def measurements(pr, g, x_true, mask, noise):
     return y.astype(np.float32)
 
 
+def border(z):
+    """z^K on the image border: first and last A-scan, first and last depth row."""
+    im = z[0, 0]
+    return np.concatenate([im[0], im[-1], im[:, 0], im[:, -1]])
+
+
 def main():
+    if len(sys.argv) > 1:
+        O.set_workers(int(sys.argv[1]))
     t0 = time.time()
     pr, g, x_true, mask, noise = inputs()
     y32 = measurements(pr, g, x_true, mask, noise)
@@ -52,9 +70,13 @@ def main():
     delta = O.step_size(L)
     print(f"lambda {lam:.6g}  L {L:.6g}  ({time.time() - t0:.0f} s)", flush=True)
     z, hist = O.fista(y, g, mask, O.PEN_TV, lam, delta, pr["iters"], tv_inner=10)
-    idx = np.random.default_rng(12345).choice(z.size, size=4096, replace=False)
-    np.savez(OUT, lam=lam, L=L, delta=delta, hist=hist, znorm=np.linalg.norm(z), idx=idx,
-             zsample=z.reshape(-1)[idx], ynorm=np.linalg.norm(y))
+    idx = refstats.sample_index(z.size, SAMPLES, SAMPLE_SEED)
+    np.savez(OUT, lam=lam, L=L, delta=delta, hist=hist, ynorm=np.linalg.norm(y),
+             sample_count=SAMPLES, sample_seed=SAMPLE_SEED, sketch_buckets=SKETCH_BUCKETS,
+             sketch_seed=SKETCH_SEED, block=np.array(BLOCK), znorm=np.linalg.norm(z),
+             zs=z.reshape(-1)[idx].astype(np.complex64), border=border(z),
+             blocks=refstats.block_norms(z[0, 0], BLOCK),
+             sketch=refstats.count_sketch(z, SKETCH_BUCKETS, SKETCH_SEED).astype(np.complex64))
     print(f"wrote {OUT} ({time.time() - t0:.0f} s)")
 
 
