@@ -273,6 +273,22 @@ oct_status oct_direct(oct_plan_t plan, int32_t kind, const float* y, void* x, vo
  * either image has zero magnitude variance), OCT_E_DEVICE. */
 oct_status oct_ncc(oct_plan_t plan, const void* x, const void* z, double* r_out, void* stream);
 
+/* oct_ncc without a plan and without allocating: for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same sums and block count as oct_ncc, so
+ * the result agrees with it to rounding of the final division.
+ * x, z: device complex64 arrays of n elements (read); r_out: DEVICE double
+ * (written): the NCC of eq. (17), NaN when either image has constant
+ * magnitude.  n in 1..OCT_NCC_NOALLOC_MAX_N, else OCT_E_INVALID.
+ * Scratch: a static device array of (3 * 1024 + 8) doubles (24.6 KB) per GPU,
+ * held until the process ends and shared by every call on that GPU; it needs
+ * no clearing (every read is of a value the same call wrote).  Calls that
+ * overlap on one GPU (two streams, two threads) race on it: serialise them.
+ * Asynchronous on `stream`; no allocation, no host synchronisation.
+ * Errors: OCT_E_INVALID, OCT_E_DEVICE. */
+#define OCT_NCC_NOALLOC_MAX_N ((int64_t)1 << 40)
+oct_status oct_ncc_noalloc(const void* x, const void* z, int64_t n, double* r_out, void* stream);
+
 /* Message for the last non-OK status returned to the calling thread. */
 const char* oct_last_error(void);
 

@@ -80,6 +80,7 @@ def _load():
         "oct_run_stage": ([P, ctypes.c_int32, ctypes.c_int32, P, P], ctypes.c_int),
         "oct_direct": ([P, ctypes.c_int32, P, P, P], ctypes.c_int),
         "oct_ncc": ([P, P, P, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
+        "oct_ncc_noalloc": ([P, P, ctypes.c_int64, P, P], ctypes.c_int),
         "oct_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -174,6 +175,21 @@ def _dev(t, dtype, shape, name):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def ncc_noalloc(x, z, r_out, stream=None):
+    """NCC of magnitudes (eq. (17)) of the device complex64 arrays x and z
+    (same number of elements) into the float64 device scalar r_out, without a
+    plan and without any allocation in the library (oct_ncc_noalloc).
+    Asynchronous; returns r_out."""
+    import torch
+    if x.shape != z.shape:
+        raise ValueError("x and z must have the same shape")
+    n = x.numel()
+    _check(_lib.oct_ncc_noalloc(_dev(x, torch.complex64, x.shape, "x"), _dev(z, torch.complex64, x.shape, "z"),
+                                ctypes.c_int64(n), _dev(r_out, torch.float64, (), "r_out"),
+                                ctypes.c_void_p(_stream_ptr(stream))))
+    return r_out
 
 
 class Plan:
@@ -332,5 +348,5 @@ class Plan:
         return x_out, dict(delta=rep.delta_used, lipschitz=rep.lipschitz_est, objective=obj)
 
 
-__all__ = ["Geometry", "Plan", "OctError", "footprint_bytes", "last_error", "LIB_PATH",
+__all__ = ["Geometry", "Plan", "OctError", "footprint_bytes", "last_error", "LIB_PATH", "ncc_noalloc",
            "PEN_L1", "PEN_TV", "PEN_HAAR", "PEN_DTCWT", "PENALTIES", "dtcwt_filter", "DIRECT", "SOLVE_PAPER_BACKWARD"]

@@ -944,6 +944,22 @@ oct_status oct_ncc(oct_plan_t p, const void* x, const void* z, double* r_out, vo
   return OCT_OK;
 }
 
+oct_status oct_ncc_noalloc(const void* x, const void* z, int64_t n, double* r_out, void* stream) {
+  if (!x || !z || !r_out) return fail(OCT_E_INVALID, "null argument");
+  if (n < 1 || n > OCT_NCC_NOALLOC_MAX_N) return fail(OCT_E_INVALID, "n must be in 1..2^40");
+  // same block count as oct_ncc (its plan-held partial buffer never caps it
+  // below NCC_NOALLOC_MAX_BLOCKS), so the sums run in the same order
+  const int nb = ncc_blocks(n, 3 * NCC_NOALLOC_MAX_BLOCKS);
+  if (3 * nb + 5 > NCC_NOALLOC_SCRATCH_DOUBLES) return fail(OCT_E_INVALID, "internal: NCC partials exceed the scratch");
+  double* scr = nullptr;
+  HIPCHK(ncc_noalloc_scratch(&scr));
+  hipStream_t s = S(stream);
+  double* dsc = scr + 3 * NCC_NOALLOC_MAX_BLOCKS;
+  HIPCHK(launch_ncc_sums((const float2*)x, (const float2*)z, n, scr, nb, dsc, s));
+  HIPCHK(launch_ncc_finish(dsc, r_out, s));
+  return OCT_OK;
+}
+
 oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, double* half_resid_sq, void* stream) {
   if (!p || !x || !y || !gout) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);

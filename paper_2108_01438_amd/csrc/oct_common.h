@@ -171,6 +171,12 @@ hipError_t launch_meas_to_complex(const float* y, const uint32_t* mask, int word
 hipError_t launch_interp_fill(const float* y, const uint32_t* mask, int words, int Mk, int Nlat, int64_t rows,
                               float* out, hipStream_t s);
 int ncc_blocks(int64_t n, int cap);
+// allocation-free NCC: block partials of at most NCC_NOALLOC_MAX_BLOCKS blocks
+// (the count oct_ncc uses for any n) and the five sums, in a static device array
+constexpr int NCC_NOALLOC_MAX_BLOCKS = 1024;
+constexpr int NCC_NOALLOC_SCRATCH_DOUBLES = 3 * NCC_NOALLOC_MAX_BLOCKS + 8;
+hipError_t ncc_noalloc_scratch(double** out);
+hipError_t launch_ncc_finish(const double* dsc, double* r, hipStream_t s);
 // means -> dsc[0..1], centred sums (xz, xx, zz) -> dsc[2..4]; partial holds 3 * nb doubles
 hipError_t launch_ncc_sums(const float2* x, const float2* z, int64_t n, double* partial, int nb, double* dsc,
                            hipStream_t s);

@@ -13,6 +13,15 @@
 //   the paper's backward operator (eq. (10)-(11)).
 #include "oct_fft.h"
 
+#include <mutex>
+
+// Scratch of the allocation-free NCC (oct_ncc_noalloc): the block partials of
+// the two passes (3 x NCC_NOALLOC_MAX_BLOCKS doubles) followed by the five
+// FP64 sums.  One copy per GPU, alive until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (ncc_noalloc_scratch below).
+static __device__ __align__(256) double scratch[NCC_NOALLOC_SCRATCH_DOUBLES];
+
 namespace {
 
 __device__ __forceinline__ bool observed(const uint32_t* __restrict__ mask, int words, int64_t lat, int m) {
@@ -147,6 +156,16 @@ __global__ void __launch_bounds__(256) ncc_reduce_kernel(const double* __restric
   }
 }
 
+// r = sum_xz / (sqrt(sum_xx) sqrt(sum_zz)) from the five sums of
+// launch_ncc_sums (means, then the centred sums); NaN when either image has
+// constant magnitude.
+__global__ void ncc_finish_kernel(const double* __restrict__ dsc, double* __restrict__ r) {
+  if (threadIdx.x == 0) {
+    const double sxz = dsc[2], sxx = dsc[3], szz = dsc[4];
+    r[0] = (sxx > 0.0 && szz > 0.0) ? sxz / (sqrt(sxx) * sqrt(szz)) : __builtin_nan("");
+  }
+}
+
 // One block per A-scan: W = conj(analytic signal of s . r) along k, the
 // operator A(z) = Re z - j H(z) of the paper's backward operator.  The
 // analytic signal is the discrete one: forward FFT, negative frequencies
@@ -226,4 +245,30 @@ hipError_t launch_ncc_sums(const float2* x, const float2* z, int64_t n, double* 
   hipLaunchKernelGGL(ncc_partial_kernel, dim3(nb), dim3(256), 0, s, x, z, n, 1, (const double*)dsc, partial);
   hipLaunchKernelGGL(ncc_reduce_kernel, dim3(1), dim3(256), 0, s, (const double*)partial, nb, 1.0, dsc + 2);
   return hipGetLastError();
+}
+
+hipError_t launch_ncc_finish(const double* dsc, double* r, hipStream_t s) {
+  hipLaunchKernelGGL(ncc_finish_kernel, dim3(1), dim3(64), 0, s, dsc, r);
+  return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and cached; no allocation.
+hipError_t ncc_noalloc_scratch(double** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* ptrs[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    double* p = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
 }
