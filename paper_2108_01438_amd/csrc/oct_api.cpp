@@ -176,6 +176,12 @@ struct oct_plan {
   float2* twM = nullptr;         // spectral-axis transform (analytic signal; literal chain's D)
   // literal K, Q, D chain (model 1): even-pixel NUFFT tables, the N-point transform, e^{j Omega}
   int model = OCT_MODEL_DIRECT;
+  // half-spectrum path (direct model): the forward NUFFT keeps W_h(q) =
+  // (W(q) + conj W(-q)) / 2 for q_x <= n_x / 2 only; column pairs (q, -q)
+  bool hs = false;
+  int64_t Nxh = 0;               // n_x / 2 + 1
+  int4* pairs = nullptr;
+  int n_pairs = 0;
   FftDesc fN{};
   float2* twN = nullptr;
   double* k2x4e = nullptr;       // [N] 4 k_{2j}^2
@@ -334,6 +340,16 @@ LineGeom lines_y(const oct_plan* p, int rows) {
   return lg;
 }
 
+// y lines of a half-spectrum array [batch][n_y][n_x/2 + 1][rows]
+LineGeom lines_y_half(const oct_plan* p, int rows) {
+  LineGeom lg = lines_y(p, rows);
+  lg.n_lines = (int)(p->B * p->Nxh);
+  lg.ocnt = (int)p->Nxh;
+  lg.sa = p->Ny * p->Nxh * rows;
+  lg.es = p->Nxh * rows;
+  return lg;
+}
+
 LatArgs lat_args(const oct_plan* p, const LineGeom& lg, bool yaxis) {
   LatArgs a{};
   a.lg = lg;
@@ -377,6 +393,9 @@ NufftArgs nufft_args(const oct_plan* p) {
   a.kbc = p->kbc;
   a.fK = p->fK;
   a.twK = p->twK;
+  a.pairs = p->pairs;
+  a.n_pairs = p->n_pairs;
+  a.n_half = (int)(p->Ny * p->Nxh);
   return a;
 }
 
@@ -394,7 +413,11 @@ NufftArgs even_args(const oct_plan* p) {
 }
 
 // X1 (lateral spectra of the image) -> W (spectra at the detector pixels)
-oct_status run_cols_fwd(oct_plan* p, hipStream_t s) {
+oct_status run_cols_fwd(oct_plan* p, hipStream_t s, bool half) {
+  if (half) {
+    HIPCHK(launch_nufft_fwd_pair(nufft_args(p), p->X1, p->W, s));
+    return OCT_OK;
+  }
   if (p->model == OCT_MODEL_DIRECT) {
     HIPCHK(launch_nufft_fwd(nufft_args(p), p->X1, p->W, s));
     return OCT_OK;
@@ -406,7 +429,11 @@ oct_status run_cols_fwd(oct_plan* p, hipStream_t s) {
 }
 
 // W -> X1 (the exact adjoint of run_cols_fwd)
-oct_status run_cols_adj(oct_plan* p, hipStream_t s) {
+oct_status run_cols_adj(oct_plan* p, hipStream_t s, bool half) {
+  if (half) {
+    HIPCHK(launch_nufft_adj_pair(nufft_args(p), p->W, p->X1, s));
+    return OCT_OK;
+  }
   if (p->model == OCT_MODEL_DIRECT) {
     HIPCHK(launch_nufft_adj(nufft_args(p), p->W, p->X1, s));
     return OCT_OK;
@@ -439,16 +466,18 @@ oct_status run_lat_forward(oct_plan* p, const float2* x, const float2* z, const 
 }
 
 // W (after the NUFFT) -> y = s . Re(F_lat^{-1} W)
-oct_status run_meas_forward(oct_plan* p, float* y, hipStream_t s) {
+oct_status run_meas_forward(oct_plan* p, float* y, hipStream_t s, bool half) {
+  const int rows = (int)p->Mk;
   if (p->lat_dims == 2) {
-    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    LatArgs b = lat_args(p, half ? lines_y_half(p, rows) : lines_y(p, rows), true);
     b.src = p->W;
     b.dst = p->W;
     b.inverse = 1;
     b.scale = 1.f / (float)p->Ny;
     HIPCHK(launch_lateral(LAT_FFT, b, s));
   }
-  LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+  LatArgs a = lat_args(p, lines_x(p, rows), false);
+  if (half) a.sa_half = p->Nxh * rows;
   a.src = p->W;
   a.dstf = y;
   a.inverse = 1;
@@ -458,15 +487,17 @@ oct_status run_meas_forward(oct_plan* p, float* y, hipStream_t s) {
 }
 
 // r -> W = F_lat(s . r) / N_lat
-oct_status run_meas_adjoint(oct_plan* p, const float* r, hipStream_t s, bool use_mask = true) {
-  LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+oct_status run_meas_adjoint(oct_plan* p, const float* r, hipStream_t s, bool half, bool use_mask = true) {
+  const int rows = (int)p->Mk;
+  LatArgs a = lat_args(p, lines_x(p, rows), false);
+  if (half) a.sa_half = p->Nxh * rows;
   if (!use_mask) a.mask = nullptr;
   a.srcf = r;
   a.dst = p->W;
   a.scale = 1.f / (float)p->Nx;
   HIPCHK(launch_lateral(LAT_ADJ_MEAS, a, s));
   if (p->lat_dims == 2) {
-    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    LatArgs b = lat_args(p, half ? lines_y_half(p, rows) : lines_y(p, rows), true);
     b.src = p->W;
     b.dst = p->W;
     b.scale = 1.f / (float)p->Ny;
@@ -532,16 +563,18 @@ oct_status run_normal_paper(oct_plan* p, const float* y, double* partial, int* n
 }
 
 // W -> W = F_lat(s . (Re F_lat^{-1} W - y)) / N_lat with per-block sum r^2; returns #partials
-oct_status run_normal(oct_plan* p, const float* y, double* partial, int* nparts, hipStream_t s) {
+oct_status run_normal(oct_plan* p, const float* y, double* partial, int* nparts, hipStream_t s, bool half) {
+  const int rows = (int)p->Mk;
   if (p->lat_dims == 2) {
-    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    LatArgs b = lat_args(p, half ? lines_y_half(p, rows) : lines_y(p, rows), true);
     b.src = p->W;
     b.dst = p->W;
     b.inverse = 1;
     b.scale = 1.f / (float)p->Ny;
     HIPCHK(launch_lateral(LAT_FFT, b, s));
   }
-  LatArgs a = lat_args(p, lines_x(p, (int)p->Mk), false);
+  LatArgs a = lat_args(p, lines_x(p, rows), false);
+  if (half) a.sa_half = p->Nxh * rows;
   a.src = p->W;
   a.dst = p->W;
   a.y = y;
@@ -552,7 +585,7 @@ oct_status run_normal(oct_plan* p, const float* y, double* partial, int* nparts,
   if (nparts) *nparts = lat_blocks(a);
   HIPCHK(launch_lateral(LAT_NORMAL, a, s));
   if (p->lat_dims == 2) {
-    LatArgs b = lat_args(p, lines_y(p, (int)p->Mk), true);
+    LatArgs b = lat_args(p, half ? lines_y_half(p, rows) : lines_y(p, rows), true);
     b.src = p->W;
     b.dst = p->W;
     b.scale = 1.f / (float)p->Ny;
@@ -719,6 +752,7 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   b += (size_t)(K + g->n_x + g->n_y) * 8 + (size_t)g->n_depth * 4 + (size_t)g->n_k * (8 + 8) +
        (size_t)Nlat * (8 + 4) * 2 + (size_t)g->n_k * 8 + (size_t)Nlat * ((g->n_k + 31) / 32) * 4;
   b += (size_t)N * 8 + (size_t)M * 8;            // workspace X1, W
+  b += (size_t)Nlat * 16;                        // column-pair table of the half-spectrum path
   if (g->model == OCT_MODEL_LITERAL)             // K's samples and the literal chain's tables
     b += (size_t)N * 8 + (size_t)g->n_depth * 16 + (size_t)g->n_k * 16;
   b += (size_t)N * 8 * 3;                        // FISTA iterates and the extrapolated point
@@ -852,6 +886,30 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
         if (mask[l * p->Mk + m]) bits[(size_t)l * p->mask_words + (m >> 5)] |= 1u << (m & 31);
     if ((st = upload(p, &p->mask, bits)) != OCT_OK) return cleanup(st);
   }
+  // column pairs (q, -q) of the half-spectrum path: q is canonical when
+  // q_x != -q_x (mod n_x) and q_x <= n_x / 2, or q_x = -q_x and q_y <= -q_y
+  // (mod n_y); a pair writes the half-spectrum slot of q and, when -q has a
+  // slot too (q_x = -q_x, q_y != -q_y), that one
+  p->Nxh = p->Nx / 2 + 1;
+  if (p->model == OCT_MODEL_DIRECT) {
+    std::vector<int4> pr;
+    for (int64_t iy = 0; iy < p->Ny; ++iy) {
+      for (int64_t ix = 0; ix < p->Nxh; ++ix) {
+        const int64_t jx = (p->Nx - ix) % p->Nx, jy = (p->Ny - iy) % p->Ny;
+        const bool xself = jx == ix;
+        if (xself && iy > jy) continue;   // the partner of a canonical column
+        int4 e;
+        e.x = (int)(iy * p->Nx + ix);
+        e.y = (int)(jy * p->Nx + jx);
+        e.z = (int)(iy * p->Nxh + ix);
+        e.w = (xself && jy != iy) ? (int)(jy * p->Nxh + ix) : -1;
+        pr.push_back(e);
+      }
+    }
+    p->n_pairs = (int)pr.size();
+    if ((st = upload(p, &p->pairs, pr)) != OCT_OK) return cleanup(st);
+    p->hs = nufft_pair_supported(nufft_args(p));
+  }
   if ((st = dev_alloc(p, &p->X1, p->n_img())) != OCT_OK) return cleanup(st);
   if ((st = dev_alloc(p, &p->W, p->n_meas())) != OCT_OK) return cleanup(st);
   if (hipMemset(p->X1, 0, sizeof(float2) * p->n_img()) != hipSuccess ||
@@ -877,16 +935,16 @@ oct_status oct_forward(oct_plan_t p, const void* x, float* y, void* stream) {
   if (!p || !x || !y) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
   OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
-  OCTCHK(run_cols_fwd(p, s));
-  OCTCHK(run_meas_forward(p, y, s));
+  OCTCHK(run_cols_fwd(p, s, p->hs));
+  OCTCHK(run_meas_forward(p, y, s, p->hs));
   return OCT_OK;
 }
 
 oct_status oct_adjoint(oct_plan_t p, const float* r, void* x, void* stream) {
   if (!p || !r || !x) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
-  OCTCHK(run_meas_adjoint(p, r, s));
-  OCTCHK(run_cols_adj(p, s));
+  OCTCHK(run_meas_adjoint(p, r, s, p->hs));
+  OCTCHK(run_cols_adj(p, s, p->hs));
   OCTCHK(run_lat_adjoint(p, (float2*)x, s));
   return OCT_OK;
 }
@@ -895,7 +953,7 @@ oct_status oct_adjoint_paper(oct_plan_t p, const float* r, void* x, void* stream
   if (!p || !r || !x) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
   OCTCHK(run_meas_backward_paper(p, r, s));
-  OCTCHK(run_cols_adj(p, s));
+  OCTCHK(run_cols_adj(p, s, false));
   OCTCHK(run_lat_adjoint(p, (float2*)x, s));
   return OCT_OK;
 }
@@ -920,8 +978,8 @@ oct_status oct_direct(oct_plan_t p, int32_t kind, const float* y, void* x, void*
     case OCT_DIRECT_INTERP_ISAM: {
       if (!p->yfill) OCTCHK(dev_alloc(p, &p->yfill, (size_t)p->n_meas()));
       HIPCHK(launch_interp_fill(y, p->mask, p->mask_words, (int)p->Mk, (int)p->Nlat, p->B * p->Nlat, p->yfill, s));
-      OCTCHK(run_meas_adjoint(p, p->yfill, s, false));
-      OCTCHK(run_cols_adj(p, s));
+      OCTCHK(run_meas_adjoint(p, p->yfill, s, p->hs, false));
+      OCTCHK(run_cols_adj(p, s, p->hs));
       return run_lat_adjoint(p, (float2*)x, s);
     }
     default:
@@ -964,11 +1022,11 @@ oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, dou
   if (!p || !x || !y || !gout) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
   OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
-  OCTCHK(run_cols_fwd(p, s));
+  OCTCHK(run_cols_fwd(p, s, p->hs));
   int np = 0;
-  OCTCHK(run_normal(p, y, p->partial, &np, s));
+  OCTCHK(run_normal(p, y, p->partial, &np, s, p->hs));
   if (half_resid_sq) HIPCHK(launch_reduce_sum(p->partial, np, half_resid_sq, 0.5, 0, s));
-  OCTCHK(run_cols_adj(p, s));
+  OCTCHK(run_cols_adj(p, s, p->hs));
   OCTCHK(run_lat_adjoint(p, (float2*)gout, s));
   return OCT_OK;
 }
@@ -1024,10 +1082,10 @@ oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, int32_t fla
   HIPCHK(launch_scale_by_inv_sqrt(p->za, p->za, n, p->dscal, s));
   for (int it = 0; it < iters; ++it) {
     OCTCHK(run_lat_forward(p, p->za, nullptr, nullptr, 0.f, s));
-    OCTCHK(run_cols_fwd(p, s));
+    OCTCHK(run_cols_fwd(p, s, p->hs && !paper));
     if (paper) OCTCHK(run_normal_paper(p, nullptr, nullptr, nullptr, s));
-    else OCTCHK(run_normal(p, nullptr, nullptr, nullptr, s));
-    OCTCHK(run_cols_adj(p, s));
+    else OCTCHK(run_normal(p, nullptr, nullptr, nullptr, s, p->hs));
+    OCTCHK(run_cols_adj(p, s, p->hs && !paper));
     OCTCHK(run_lat_adjoint(p, p->zb, s));
     HIPCHK(launch_norm2_partial(p->zb, n, p->partial, nb, s));
     HIPCHK(launch_reduce_sum(p->partial, nb, p->dscal, 1.0, 0, s));
@@ -1100,12 +1158,12 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   if (fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, 0.f, s));
   for (int k = 0; k < prm->iters; ++k) {
     if (!fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s, p->xext));
-    OCTCHK(run_cols_fwd(p, s));
+    OCTCHK(run_cols_fwd(p, s, p->hs && !paper));
     int nres = 0, npen = 0;
     // residual partials only for the objective
     if (paper) OCTCHK(run_normal_paper(p, y, want_obj ? res_part : nullptr, &nres, s));
-    else OCTCHK(run_normal(p, y, want_obj ? res_part : nullptr, &nres, s));
-    OCTCHK(run_cols_adj(p, s));
+    else OCTCHK(run_normal(p, y, want_obj ? res_part : nullptr, &nres, s, p->hs));
+    OCTCHK(run_cols_adj(p, s, p->hs && !paper));
     if (fused_l1) {
       LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
       a.src = p->X1;
@@ -1181,15 +1239,15 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
     case OCT_STAGE_LAT_FWD:
       return run_lat_forward(p, nullptr, p->za, p->zb, 0.5f, s, p->xext);
     case OCT_STAGE_NUFFT_FWD:
-      OCTCHK(run_cols_fwd(p, s));
+      OCTCHK(run_cols_fwd(p, s, p->hs));
       return OCT_OK;
     case OCT_STAGE_NORMAL: {
       if (!y) return fail(OCT_E_INVALID, "OCT_STAGE_NORMAL needs y");
       int np = 0;
-      return run_normal(p, y, nullptr, &np, s);   // as in a solve without the objective
+      return run_normal(p, y, nullptr, &np, s, p->hs);   // as in a solve without the objective
     }
     case OCT_STAGE_NUFFT_ADJ:
-      OCTCHK(run_cols_adj(p, s));
+      OCTCHK(run_cols_adj(p, s, p->hs));
       return OCT_OK;
     case OCT_STAGE_LAT_UPDATE: {
       if (p->lat_dims == 2) {

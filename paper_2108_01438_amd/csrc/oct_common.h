@@ -106,6 +106,11 @@ struct LatArgs {
   const float* y;
   const uint32_t* mask;  // [lat][mask_words] bits, NULL = all observed
   int mask_words;
+  // Half-spectrum storage of the spectral operand (x lines of the modes
+  // FWD_MEAS, ADJ_MEAS and NORMAL): only lateral indices l <= L/2 are stored,
+  // with line stride sa_half (0: full rows, line stride lg.sa).  The rows are
+  // spectra of real rows, so l > L/2 holds conj(row[L - l]).
+  int64_t sa_half;
   const float2* z;       // current iterate z^{k-1} (UPDATE: the extrapolated x itself when zo is NULL)
   float2* zo;            // previous iterate z^{k-2}; receives z^k in UPDATE_L1
   float2* xout;          // FFT with z: also stores x = z + mu (z - zo) here (nullable)
@@ -132,6 +137,12 @@ struct NufftArgs {
   const float* kbc;      // [J/2][even, odd][(OCT_KB_DEG+1)/2] KB pieces in x = 2f - 1
   FftDesc fK;
   const float2* twK;     // per-stage twiddle rows of the K-point transform
+  // Column pairs (q, -q) of the half-spectrum kernels: {column of q, column of
+  // -q, half-spectrum slot of q, half-spectrum slot of -q or -1}, per batch
+  // item; n_half = half-spectrum columns per batch item (n_y (n_x / 2 + 1)).
+  const int4* pairs;
+  int n_pairs;
+  int n_half;
 };
 
 // Launchers (kernels in the .hip files; all asynchronous on `s`).
@@ -140,6 +151,12 @@ int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* row
 hipError_t launch_nufft_fwd(const NufftArgs& a, const float2* X1, float2* W, hipStream_t s);
 hipError_t launch_nufft_adj(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s);
 size_t nufft_adj_lds_bytes(const NufftArgs& a);
+// Half-spectrum column kernels: W_h(q) = (W(q) + conj W(-q)) / 2 from the
+// columns q and -q of X1, and both image columns from R^(q) (R^(-q) = conj R^(q)).
+hipError_t launch_nufft_fwd_pair(const NufftArgs& a, const float2* X1, float2* Wh, hipStream_t s);
+hipError_t launch_nufft_adj_pair(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s);
+size_t nufft_pair_lds_bytes(const NufftArgs& a, bool adjoint);
+bool nufft_pair_supported(const NufftArgs& a);   // LDS and thread limits of the pair kernels
 
 // Reductions and elementwise helpers.
 hipError_t launch_reduce_sum(const double* partial, int n, double* out, double scale,

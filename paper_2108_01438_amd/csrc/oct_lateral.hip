@@ -99,6 +99,10 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   const int nr = min(a.T, lg.rows - r0);
   const int64_t base = (int64_t)(line / lg.ocnt) * lg.sa + (int64_t)(line % lg.ocnt) * lg.sb + r0;
   const int L = lg.L, T = a.T, rs = a.rowstride;
+  // spectral operand in half-spectrum storage (x lines only: ocnt = 1, sb = 0)
+  const bool half = a.sa_half != 0;
+  const int Lh = L / 2 + 1;
+  const int64_t hbase = half ? (int64_t)line * a.sa_half + r0 : base;
   const int latb = (line % lg.lat_lines) * L;
   const int n = L * T;
   const int lt = a.log2T;
@@ -187,6 +191,38 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
         lds[t * rs + l] = t < nr ? x : make_float2(0.f, 0.f);
         if (a.xout && t < nr) a.xout[base + (int64_t)l * lg.es + t] = x;
       });
+  } else if ((MODE == LAT_FWD_MEAS || MODE == LAT_NORMAL) && half) {
+    // half rows of Hermitian spectra, extended: row[L - l] = conj(row[l]); at
+    // l = 0 (and L/2) only the real part belongs to the Hermitian row.
+    // Paired: row p <- row_p + j row_{p+H}, so that one inverse transform
+    // gives the real rows p and p + H (in .x and .y).
+    auto hoff = [&](int l, int t) -> int64_t { return hbase + (int64_t)l * lg.es + min(t, nr - 1); };
+    if (pair) {
+      const int log2H = lt - 1;
+      batched_for(Lh * H, tid, nthr,
+        [&](int idx) { const int l = idx >> log2H, p = idx & (H - 1);
+                       return Z2{a.src[hoff(l, p)], a.src[hoff(l, p + H)]}; },
+        [&](int idx, Z2 v) {
+          const int l = idx >> log2H, p = idx & (H - 1);
+          float2 va = p < nr ? v.a : make_float2(0.f, 0.f), vb = p + H < nr ? v.b : make_float2(0.f, 0.f);
+          const bool self = l == 0 || 2 * l == L;
+          if (self) { va.y = 0.f; vb.y = 0.f; }
+          float2* ra = lds + p * rs;
+          ra[l] = make_float2(va.x - vb.y, va.y + vb.x);
+          if (!self) ra[L - l] = make_float2(va.x + vb.y, vb.x - va.y);
+        });
+    } else {
+      batched_for(Lh * T, tid, nthr,
+        [&](int idx) { return a.src[hoff(idx >> lt, idx & (T - 1))]; },
+        [&](int idx, float2 v) {
+          const int l = idx >> lt, t = idx & (T - 1);
+          if (t >= nr) v = make_float2(0.f, 0.f);
+          const bool self = l == 0 || 2 * l == L;
+          if (self) v.y = 0.f;
+          lds[t * rs + l] = v;
+          if (!self) lds[t * rs + L - l] = cconj(v);
+        });
+    }
   } else {
     batched_for(n, tid, nthr,
       [&](int idx) { return a.src[goff(idx)]; },
@@ -209,7 +245,7 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
     }
   }
   __syncthreads();
-  if ((MODE == LAT_FWD_MEAS || MODE == LAT_NORMAL || MODE == LAT_RESID) && pair) {
+  if ((MODE == LAT_FWD_MEAS || MODE == LAT_NORMAL || MODE == LAT_RESID) && pair && !half) {
     pack_real_pairs(lds, H, rs, L, tid, nthr);
     __syncthreads();
   }
@@ -218,11 +254,12 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   else fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, nrow_t, rs, a.fd, twl, tid, nthr);
 
   if (MODE == LAT_FFT || MODE == LAT_ADJ_MEAS) {
-    for (int idx = tid; idx < n; idx += nthr) {
+    const int nout = (MODE == LAT_ADJ_MEAS && half) ? Lh * T : n;   // spectra of real rows: l <= L/2 suffices
+    for (int idx = tid; idx < nout; idx += nthr) {
       const int l = idx >> lt, t = idx & (T - 1);
       if (t < nr) {
         const float2 v = (MODE == LAT_ADJ_MEAS && pair) ? unpack_real_pair(lds, rs, L, H, t, l) : lds[t * rs + l];
-        a.dst[base + (int64_t)l * lg.es + t] = cscale(v, a.scale);
+        a.dst[hbase + (int64_t)l * lg.es + t] = cscale(v, a.scale);
       }
     }
     return;
@@ -292,9 +329,9 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       });
     __syncthreads();
     fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, H, rs, a.fd, twl, tid, nthr);
-    for (int idx = tid; idx < n; idx += nthr) {
+    for (int idx = tid; idx < (half ? Lh * T : n); idx += nthr) {
       const int l = idx >> lt, t = idx & (T - 1);
-      if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(unpack_real_pair(lds, rs, L, H, t, l), a.scale2);
+      if (t < nr) a.dst[hbase + (int64_t)l * lg.es + t] = cscale(unpack_real_pair(lds, rs, L, H, t, l), a.scale2);
     }
     if (a.partial) {   // the residual norm only when the caller asks for it
       const double s = block_sum_d(acc, red);
@@ -316,9 +353,9 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       });
     __syncthreads();
     fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, T, rs, a.fd, twl, tid, nthr);
-    for (int idx = tid; idx < n; idx += nthr) {
+    for (int idx = tid; idx < (half ? Lh * T : n); idx += nthr) {
       const int l = idx >> lt, t = idx & (T - 1);
-      if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
+      if (t < nr) a.dst[hbase + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
     }
     if (a.partial) {
       const double s = block_sum_d(acc, red);

@@ -103,6 +103,25 @@ __device__ __forceinline__ void adj_cell_taps(const float* __restrict__ kbc, con
   }
 }
 
+// adj_cell_taps for two columns that share their samples' coordinates: each
+// weight is evaluated once and applied to both.
+template <int J, int I>
+__device__ __forceinline__ void adj_cell_taps2(const float* __restrict__ kbc, const short* F, const float* xm,
+                                               const float2* us0, const float2* us1, float2& s0, float2& s1) {
+  if constexpr (I < J) {
+    constexpr int j = J - 1 - I;
+    for (int m = F[I]; m < F[I + 1]; ++m) {
+      const float w = kb_tap_ct<J, j>(kbc, xm[m]);
+      const float2 u0 = us0[m], u1 = us1[m];
+      s0.x = fmaf(w, u0.x, s0.x);
+      s0.y = fmaf(w, u0.y, s0.y);
+      s1.x = fmaf(w, u1.x, s1.x);
+      s1.y = fmaf(w, u1.y, s1.y);
+    }
+    adj_cell_taps2<J, I + 1>(kbc, F, xm, us0, us1, s0, s1);
+  }
+}
+
 // Filter H(m, q) = beam(q) e^{j(-2 k_m z_f + Omega_m)} e^{j beta (z_f - n_c dz)}.
 // ph = a.phase[m] (read by the caller, batched with the sample's other loads)
 __device__ __forceinline__ float2 filter_h(const NufftArgs& a, float2 ph, float bq, double beta) {
@@ -131,6 +150,10 @@ struct KP {
 struct KPR {
   double k2;
   float2 ph, r;
+};
+struct VD2 {
+  float2 a, b;
+  float d;
 };
 
 template <int J, bool ONE>
@@ -340,6 +363,235 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
   });
 }
 
+// ---------------------------------------------------------------------------
+// Half-spectrum column pairs.  Only Re F_lat^{-1} W reaches the measurements
+// (eq. (7)), and Re F^{-1} W = F^{-1} W_h with the Hermitian part
+// W_h(q) = (W(q) + conj W(-q)) / 2, so W_h is kept for the lateral
+// frequencies of one half-plane only.  Columns q and -q have the same |q|^2,
+// hence the same beta_m(q), grid coordinates, KB weights and filter: one
+// workgroup takes both, forms those once per sample, and runs the two K-point
+// transforms as one two-row pass.  The adjoint reads R^(q) once: the residual
+// is real, so R^(-q) = conj R^(q), and both image columns come out of one
+// gather (one weight evaluation per cell-sample pair for the two columns).
+// ---------------------------------------------------------------------------
+template <int J, bool ONE>
+__global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const float2* __restrict__ X1,
+                                                              float2* __restrict__ Wh) {
+  extern __shared__ float2 gridp[];
+  const int K = a.K, Nz = a.Nz, nc = a.nc;
+  const int rs = K + 2 * KPAD;   // row stride: [KPAD pads | K cells | KPAD pads]
+  float2* g0 = gridp + KPAD;
+  float2* g1 = g0 + rs;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int b = blockIdx.x / a.n_pairs;
+  const int4 pr = a.pairs[blockIdx.x - b * a.n_pairs];
+  const float2* __restrict__ s0 = X1 + ((int64_t)b * a.Nlat + pr.x) * Nz;
+  const float2* __restrict__ s1 = X1 + ((int64_t)b * a.Nlat + pr.y) * Nz;
+
+  // n' = n - n_c placed at n' mod K; cells [Nz - nc, K - nc) stay zero
+  for (int i = tid; i < K - Nz; i += nthr) {
+    g0[Nz - nc + i] = make_float2(0.f, 0.f);
+    g1[Nz - nc + i] = make_float2(0.f, 0.f);
+  }
+  batched_for(Nz, tid, nthr, [&](int n) { return VD2{s0[n], s1[n], a.deap[n]}; },
+              [&](int n, VD2 v) {
+                int idx = n - nc;
+                if (idx < 0) idx += K;
+                g0[idx] = cscale(v.a, v.d);
+                g1[idx] = cscale(v.b, v.d);
+              });
+  __syncthreads();
+  fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(g0, 2, rs, a.fK, a.twK, tid, nthr);
+  if (tid < 4 * KPAD) {   // wrapped copies, cells -KPAD..-1 and K..K+KPAD-1 of both rows
+    float2* g = tid < 2 * KPAD ? g0 : g1;
+    const int t = tid & (2 * KPAD - 1);
+    const int c = t < KPAD ? t - KPAD : K + t - KPAD;
+    g[c] = g[t < KPAD ? c + K : c - K];
+  }
+  __syncthreads();
+
+  const double q2 = a.q2[pr.x];
+  const float bq = a.beam[pr.x];
+  float2* __restrict__ out = Wh + ((int64_t)b * a.n_half + pr.z) * a.Mk;
+  float2* __restrict__ outp = pr.w >= 0 ? Wh + ((int64_t)b * a.n_half + pr.w) * a.Mk : nullptr;
+  for (int m = tid; m < a.Mk; m += nthr) {
+    const KP kp{a.k2x4[m], a.phase[m]};
+    const double arg = kp.k2 - q2;
+    float2 res = make_float2(0.f, 0.f);
+    if (arg > 0.0) {
+      const double beta = beta_of(arg);
+      const double t = a.ct * beta;
+      const double tw = fma(-(double)K, floor(t * a.invK), t);
+      const double fl = floor(tw);
+      const float x = (float)(2.0 * (tw - fl) - 1.0);
+      const int c0 = (int)fl - J / 2 + 1;
+      float2 u0 = make_float2(0.f, 0.f), u1 = make_float2(0.f, 0.f);
+      const float x2 = x * x;
+#pragma unroll
+      for (int jj = 0; jj < J / 2; ++jj) {
+        float wlo, whi;
+        kb_pair(a.kbc + jj * 2 * KBH, x, x2, wlo, whi);
+        const float2 a0 = g0[c0 + jj], a1 = g0[c0 + J - 1 - jj];
+        const float2 b0 = g1[c0 + jj], b1 = g1[c0 + J - 1 - jj];
+        u0.x = fmaf(wlo, a0.x, u0.x);
+        u0.y = fmaf(wlo, a0.y, u0.y);
+        u0.x = fmaf(whi, a1.x, u0.x);
+        u0.y = fmaf(whi, a1.y, u0.y);
+        u1.x = fmaf(wlo, b0.x, u1.x);
+        u1.y = fmaf(wlo, b0.y, u1.y);
+        u1.x = fmaf(whi, b1.x, u1.x);
+        u1.y = fmaf(whi, b1.y, u1.y);
+      }
+      const float2 h = filter_h(a, kp.ph, bq, beta);
+      const float2 w0 = cmul(h, u0), w1 = cmul(h, u1);
+      res = make_float2(0.5f * (w0.x + w1.x), 0.5f * (w0.y - w1.y));   // (W(q) + conj W(-q)) / 2
+    }
+    out[m] = res;
+    if (outp) outp[m] = cconj(res);
+  }
+}
+
+template <int J, bool ONE>
+__global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_pair_kernel(NufftArgs a, const float2* __restrict__ Rh,
+                                                                           float2* __restrict__ X) {
+  extern __shared__ float4 smem4[];
+  __shared__ float kc[J * KBH];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int K = a.K, Mk = a.Mk, Nz = a.Nz, nc = a.nc;
+  const int b = blockIdx.x / a.n_pairs;
+  const int4 pr = a.pairs[blockIdx.x - b * a.n_pairs];
+  float2* region = reinterpret_cast<float2*>(smem4);
+  float2* grid = region;                    // after the gather: two rows of K cells
+  float2* us0 = region;                     // before: filtered samples of column q
+  float2* us1 = us0 + Mk;                   // and of column -q
+  float* xm = reinterpret_cast<float*>(us1 + Mk);
+  short* bm = reinterpret_cast<short*>(xm + Mk);
+  short* first = bm + Mk;                   // [K] first contributing sample of each cell
+
+  __shared__ int s_mf;
+  if (tid == 0) s_mf = Mk;
+  for (int i = tid; i < J * KBH; i += nthr) kc[i] = a.kbc[i];
+  const double q2 = a.q2[pr.x];
+  const float bq = a.beam[pr.x];
+  const float2* __restrict__ rin = Rh + ((int64_t)b * a.n_half + pr.z) * Mk;
+  __syncthreads();
+  for (int m = tid; m < Mk; m += nthr) {
+    const KPR v{a.k2x4[m], a.phase[m], rin[m]};
+    const double arg = v.k2 - q2;
+    if (arg > 0.0 && (m == 0 || a.k2x4[m - 1] - q2 <= 0.0)) s_mf = m;
+    if (arg > 0.0) {
+      const double beta = beta_of(arg);
+      const double t = a.ct * beta;
+      const double fl = floor(t);
+      bm[m] = (short)(int)fl;
+      xm[m] = (float)(2.0 * (t - fl) - 1.0);
+      const float2 hc = cconj(filter_h(a, v.ph, bq, beta));
+      us0[m] = cmul(hc, v.r);
+      us1[m] = cmul(hc, cconj(v.r));
+    } else {
+      bm[m] = EVANESCENT16;
+      xm[m] = 0.f;
+      us0[m] = make_float2(0.f, 0.f);
+      us1[m] = make_float2(0.f, 0.f);
+    }
+  }
+  __syncthreads();
+
+  const int mf = s_mf;
+  int umin = 0, umax = -1;
+  if (mf < Mk) {
+    umin = bm[mf] - J / 2 + 1;
+    umax = bm[Mk - 1] + J / 2;
+  }
+  const int span = umax - umin + 1;
+  const int nph = span > K ? (span + K - 1) / K : 1;
+  if (nph == 1) {
+    for (int m = mf + tid; m < Mk; m += nthr) {
+      const int ulo = (m == mf) ? umin : bm[m - 1] + J / 2 + 1;
+      const int uhi = bm[m] + J / 2;
+      for (int u = ulo; u <= uhi; ++u) first[u - umin] = (short)m;
+    }
+    __syncthreads();
+  }
+  float2 acc0[ADJ_MAXC], acc1[ADJ_MAXC];
+#pragma unroll
+  for (int i = 0; i < ADJ_MAXC; ++i) {
+    acc0[i] = make_float2(0.f, 0.f);
+    acc1[i] = make_float2(0.f, 0.f);
+  }
+  for (int ph = 0; ph < nph; ++ph) {
+    const int pbeg = umin + ph * K;
+    int pend = pbeg + K;
+    if (ph > 0) pend = min(pend, umax + 1);
+#pragma unroll
+    for (int i = 0; i < ADJ_MAXC; ++i) {
+      const int u = pbeg + tid + i * nthr;
+      if (u < pend) {
+        const int key = u - J / 2;
+        if (nph == 1) {
+          if (u <= umax) {
+            const int c = u - umin;
+            short F[J + 1];
+#pragma unroll
+            for (int q = 0; q <= J; ++q) F[q] = (c + q < span) ? first[c + q] : (short)Mk;
+            float2 t0 = acc0[i], t1 = acc1[i];
+            adj_cell_taps2<J, 0>(a.kbc, F, xm, us0, us1, t0, t1);
+            acc0[i] = t0;
+            acc1[i] = t1;
+          }
+          continue;
+        }
+        int p = mf;
+        if (mf < Mk) {
+          const double bta = fmax((double)key, 0.0) / a.ct;
+          const double km = 0.5 * sqrt(bta * bta + q2);
+          double mstar = floor((km - a.k_min) / a.dk);
+          mstar = fmin(fmax(mstar, (double)mf), (double)Mk);
+          p = (int)mstar;
+          while (p > mf && bm[p - 1] >= key) --p;
+          while (p < Mk && bm[p] < key) ++p;
+        }
+        float2 t0 = acc0[i], t1 = acc1[i];
+        for (int m = p; m < Mk && bm[m] <= u + J / 2 - 1; ++m) {
+          const int j = u - (bm[m] - J / 2 + 1);
+          const float w = kb_tap<J>(kc, j, xm[m]);
+          const float2 u0 = us0[m], u1 = us1[m];
+          t0.x = fmaf(w, u0.x, t0.x);
+          t0.y = fmaf(w, u0.y, t0.y);
+          t1.x = fmaf(w, u1.x, t1.x);
+          t1.y = fmaf(w, u1.y, t1.y);
+        }
+        acc0[i] = t0;
+        acc1[i] = t1;
+      }
+    }
+  }
+  __syncthreads();   // sample arrays are dead from here: the two grid rows take their place
+  int g0 = umin % K;
+  if (g0 < 0) g0 += K;
+#pragma unroll
+  for (int i = 0; i < ADJ_MAXC; ++i) {
+    if (tid + i * nthr < K) {
+      int g = g0 + tid + i * nthr;
+      if (g >= K) g -= K;
+      grid[g] = acc0[i];
+      grid[K + g] = acc1[i];
+    }
+  }
+  __syncthreads();
+
+  fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(grid, 2, K, a.fK, a.twK, tid, nthr);
+  float2* __restrict__ d0 = X + ((int64_t)b * a.Nlat + pr.x) * Nz;
+  float2* __restrict__ d1 = X + ((int64_t)b * a.Nlat + pr.y) * Nz;
+  const bool two = pr.y != pr.x;
+  batched_for(Nz, tid, nthr, [&](int n) { return a.deap[n]; }, [&](int n, float d) {
+    int idx = n - nc;
+    if (idx < 0) idx += K;
+    d0[n] = cscale(grid[idx], d);
+    if (two) d1[n] = cscale(grid[K + idx], d);
+  });
+}
+
 // Threads per column: enough for the FFT stages, and wide enough that the
 // per-column work is short (the column count of a B-scan is only ~1000).
 int nufft_threads(const NufftArgs& a, int want) {
@@ -410,5 +662,86 @@ hipError_t launch_nufft_adj(const NufftArgs& a, const float2* Rh, float2* X, hip
     case 4: return one ? nufft_adj_t<4, true>(a, Rh, X, nt, s) : nufft_adj_t<4, false>(a, Rh, X, nt, s);
     case 6: return one ? nufft_adj_t<6, true>(a, Rh, X, nt, s) : nufft_adj_t<6, false>(a, Rh, X, nt, s);
     default: return one ? nufft_adj_t<8, true>(a, Rh, X, nt, s) : nufft_adj_t<8, false>(a, Rh, X, nt, s);
+  }
+}
+
+// ---- half-spectrum column pairs
+size_t nufft_pair_lds_bytes(const NufftArgs& a, bool adjoint) {
+  if (!adjoint) return (size_t)2 * (a.K + 2 * KPAD) * sizeof(float2);
+  const size_t samples = (size_t)a.Mk * (2 * sizeof(float2) + sizeof(float) + sizeof(short)) + (size_t)a.K * sizeof(short);
+  const size_t grid = (size_t)2 * a.K * sizeof(float2);
+  return samples > grid ? samples : grid;
+}
+
+namespace {
+
+// threads for two K-point rows: every stage's butterflies fit (at most two
+// per thread), and the adjoint's cells fit ADJ_MAXC per thread
+int pair_threads(const NufftArgs& a, bool adjoint) {
+  const int bf = 2 * (a.K / a.fK.min_radix);
+  const int mb = fft_maxb(a.fK);
+  int nt = adjoint ? 512 : 256;
+  while (nt < 1024 && (bf > mb * nt || (adjoint && (a.K + nt - 1) / nt > ADJ_MAXC))) nt <<= 1;
+  if (adjoint && nt < 1024 && fft_one(a.fK, 2, 2 * nt) && !fft_one(a.fK, 2, nt)) nt <<= 1;   // one butterfly per thread
+  return nt;
+}
+
+template <int J, bool ONE>
+hipError_t nufft_fwd_pair_t(const NufftArgs& a, const float2* X1, float2* Wh, int nthr, hipStream_t s) {
+  const size_t lds = nufft_pair_lds_bytes(a, false);
+  if (lds > 64 * 1024) {
+    static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_fwd_pair_kernel<J, ONE>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    if (set != hipSuccess) return set;
+  }
+  hipLaunchKernelGGL((nufft_fwd_pair_kernel<J, ONE>), dim3(a.n_pairs * (a.n_cols / a.Nlat)), dim3(nthr), lds, s, a, X1,
+                     Wh);
+  return hipGetLastError();
+}
+
+template <int J, bool ONE>
+hipError_t nufft_adj_pair_t(const NufftArgs& a, const float2* Rh, float2* X, int nthr, hipStream_t s) {
+  const size_t lds = nufft_pair_lds_bytes(a, true);
+  if (lds > 64 * 1024 - 1024) {
+    static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_adj_pair_kernel<J, ONE>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    if (set != hipSuccess) return set;
+  }
+  hipLaunchKernelGGL((nufft_adj_pair_kernel<J, ONE>), dim3(a.n_pairs * (a.n_cols / a.Nlat)), dim3(nthr), lds, s, a, Rh,
+                     X);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool nufft_pair_supported(const NufftArgs& a) {
+  constexpr size_t lds_max = 156 * 1024;
+  if (nufft_pair_lds_bytes(a, false) > lds_max || nufft_pair_lds_bytes(a, true) > lds_max) return false;
+  const int bf = 2 * (a.K / a.fK.min_radix);
+  const int mb = fft_maxb(a.fK);
+  for (bool adj : {false, true}) {
+    const int nt = pair_threads(a, adj);
+    if (bf > mb * nt || (adj && (a.K + nt - 1) / nt > ADJ_MAXC)) return false;
+  }
+  return true;
+}
+
+hipError_t launch_nufft_fwd_pair(const NufftArgs& a, const float2* X1, float2* Wh, hipStream_t s) {
+  const int nt = pair_threads(a, false);
+  const bool one = fft_one(a.fK, 2, nt);
+  switch (a.J) {
+    case 4: return one ? nufft_fwd_pair_t<4, true>(a, X1, Wh, nt, s) : nufft_fwd_pair_t<4, false>(a, X1, Wh, nt, s);
+    case 6: return one ? nufft_fwd_pair_t<6, true>(a, X1, Wh, nt, s) : nufft_fwd_pair_t<6, false>(a, X1, Wh, nt, s);
+    default: return one ? nufft_fwd_pair_t<8, true>(a, X1, Wh, nt, s) : nufft_fwd_pair_t<8, false>(a, X1, Wh, nt, s);
+  }
+}
+
+hipError_t launch_nufft_adj_pair(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s) {
+  const int nt = pair_threads(a, true);
+  const bool one = fft_one(a.fK, 2, nt);
+  switch (a.J) {
+    case 4: return one ? nufft_adj_pair_t<4, true>(a, Rh, X, nt, s) : nufft_adj_pair_t<4, false>(a, Rh, X, nt, s);
+    case 6: return one ? nufft_adj_pair_t<6, true>(a, Rh, X, nt, s) : nufft_adj_pair_t<6, false>(a, Rh, X, nt, s);
+    default: return one ? nufft_adj_pair_t<8, true>(a, Rh, X, nt, s) : nufft_adj_pair_t<8, false>(a, Rh, X, nt, s);
   }
 }
