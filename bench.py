@@ -131,8 +131,8 @@ def phi_sizes_bench() -> dict:
 # kernels of the single-kernel stages (a volume's lateral stages take two or
 # three launches of the lateral kernel), by the name rocprofv3 reports
 STAGE_KERNEL = {
-    "nufft_fwd": "nufft_fwd_kernel<6, false>",
-    "nufft_adj": "nufft_adj_kernel<6, true>",
+    "nufft_fwd": "nufft_fwd_pair_kernel<6, false>",
+    "nufft_adj": "nufft_adj_pair_kernel<6, true>",
     "prox": {"tv": "tv2d_tile_kernel<false>", "haar": "haar_kernel<3, 3", "l1": "prox_l1_kernel"},
 }
 BSCAN_STAGE_KERNEL = {

@@ -180,6 +180,7 @@ struct oct_plan {
   // (W(q) + conj W(-q)) / 2 for q_x <= n_x / 2 only; column pairs (q, -q)
   bool hs = false;
   int64_t Nxh = 0;               // n_x / 2 + 1
+  int64_t Nxs = 0;               // half-spectrum slot stride per y row (n_x; slots < Nxh used)
   int4* pairs = nullptr;
   int n_pairs = 0;
   FftDesc fN{};
@@ -345,8 +346,8 @@ LineGeom lines_y_half(const oct_plan* p, int rows) {
   LineGeom lg = lines_y(p, rows);
   lg.n_lines = (int)(p->B * p->Nxh);
   lg.ocnt = (int)p->Nxh;
-  lg.sa = p->Ny * p->Nxh * rows;
-  lg.es = p->Nxh * rows;
+  lg.sa = p->Ny * p->Nxs * rows;
+  lg.es = p->Nxs * rows;
   return lg;
 }
 
@@ -395,7 +396,7 @@ NufftArgs nufft_args(const oct_plan* p) {
   a.twK = p->twK;
   a.pairs = p->pairs;
   a.n_pairs = p->n_pairs;
-  a.n_half = (int)(p->Ny * p->Nxh);
+  a.n_half = (int)(p->Ny * p->Nxs);
   return a;
 }
 
@@ -477,7 +478,7 @@ oct_status run_meas_forward(oct_plan* p, float* y, hipStream_t s, bool half) {
     HIPCHK(launch_lateral(LAT_FFT, b, s));
   }
   LatArgs a = lat_args(p, lines_x(p, rows), false);
-  if (half) a.sa_half = p->Nxh * rows;
+  if (half) a.sa_half = p->Nxs * rows;
   a.src = p->W;
   a.dstf = y;
   a.inverse = 1;
@@ -490,7 +491,7 @@ oct_status run_meas_forward(oct_plan* p, float* y, hipStream_t s, bool half) {
 oct_status run_meas_adjoint(oct_plan* p, const float* r, hipStream_t s, bool half, bool use_mask = true) {
   const int rows = (int)p->Mk;
   LatArgs a = lat_args(p, lines_x(p, rows), false);
-  if (half) a.sa_half = p->Nxh * rows;
+  if (half) a.sa_half = p->Nxs * rows;
   if (!use_mask) a.mask = nullptr;
   a.srcf = r;
   a.dst = p->W;
@@ -574,7 +575,7 @@ oct_status run_normal(oct_plan* p, const float* y, double* partial, int* nparts,
     HIPCHK(launch_lateral(LAT_FFT, b, s));
   }
   LatArgs a = lat_args(p, lines_x(p, rows), false);
-  if (half) a.sa_half = p->Nxh * rows;
+  if (half) a.sa_half = p->Nxs * rows;
   a.src = p->W;
   a.dst = p->W;
   a.y = y;
@@ -891,6 +892,10 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   // (mod n_y); a pair writes the half-spectrum slot of q and, when -q has a
   // slot too (q_x = -q_x, q_y != -q_y), that one
   p->Nxh = p->Nx / 2 + 1;
+  // rows of the half spectrum keep the full n_x stride (W is full-size): with
+  // the packed n_x / 2 + 1 stride the volume's y passes and residual seam ran
+  // 20% slower per byte (1.37 vs 1.13 ms per seam at 2048 x 256 x 256)
+  p->Nxs = p->Nx;
   if (p->model == OCT_MODEL_DIRECT) {
     std::vector<int4> pr;
     for (int64_t iy = 0; iy < p->Ny; ++iy) {
@@ -901,8 +906,8 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
         int4 e;
         e.x = (int)(iy * p->Nx + ix);
         e.y = (int)(jy * p->Nx + jx);
-        e.z = (int)(iy * p->Nxh + ix);
-        e.w = (xself && jy != iy) ? (int)(jy * p->Nxh + ix) : -1;
+        e.z = (int)(iy * p->Nxs + ix);
+        e.w = (xself && jy != iy) ? (int)(jy * p->Nxs + ix) : -1;
         pr.push_back(e);
       }
     }
