@@ -372,8 +372,9 @@ def table1_bench(search_iters: int = 10, u_range=(-6.0, -0.5), coarse: int = 8) 
     sparse point scatterers (bead-like) and layered speckle (tissue-like), 1%
     noise; measurements are synthesised with the library's own forward
     operator.  The twelve lambda searches of a specimen run concurrently, one
-    plan and stream each."""
+    plan and stream each; each coarse scan is one batched solve."""
     import concurrent.futures as cf
+    import dataclasses
     import numpy as np
     import torch
     import paper_2108_01438_amd as P
@@ -443,11 +444,13 @@ def table1_bench(search_iters: int = 10, u_range=(-6.0, -0.5), coarse: int = 8) 
             mname, pen, mask, y_m, delta, lam_max = job
             st = torch.cuda.Stream()
             plan = P.Plan(geom, mask)
+            plan_b = P.Plan(dataclasses.replace(geom, batch=coarse), mask)   # the coarse scan as one solve
             with torch.cuda.stream(st):
                 r = tune_lambda(plan, y_m, ref, pen, lam_max, delta, iters=100, u_range=u_range,
-                                search_iters=search_iters, coarse=coarse, stream=st)
+                                search_iters=search_iters, coarse=coarse, stream=st, batched_plan=plan_b)
             st.synchronize()
             plan.close()
+            plan_b.close()
             return mname, pen, r
         torch.cuda.synchronize()
         t0 = time.perf_counter()

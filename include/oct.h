@@ -201,7 +201,12 @@ typedef struct {
   double bound;           /* modulus bound of the constraint set C of eq. (16)
                              (as in oct_prox; 0 = none)                           */
   const void* x0;         /* device image, start point; NULL = zero               */
+  const double* lambda_item; /* HOST [batch] or NULL: a regularisation weight per
+                             batch item (lambda is then unused); see below       */
 } oct_solve_params;
+
+/* Largest batch that oct_solve_params.lambda_item may describe. */
+#define OCT_MAX_LAMBDA_ITEMS 64
 
 typedef struct {
   double delta_used;      /* step size actually used                              */
@@ -211,6 +216,17 @@ typedef struct {
 } oct_solve_report;
 
 /* FISTA (Sec. 2.3, eq. (15)): x^1 = x0, z^0 = x^1, t^1 = 1;
+ * Per-item weights (lambda_item != NULL): item b solves its own problem with
+ * weight lambda_item[b] > 0 (e.g. the candidates of the lambda search of
+ * Sec. 3.2 on one measurement replicated over the batch).  Every penalty is
+ * positively homogeneous, R(c x) = c R(x) for c > 0, so the FISTA iterates of
+ * (y_b, lambda_b) are s_b times those of (y_b / s_b, lambda_0) with
+ * s_b = lambda_b / lambda_0 (the gradient step and momentum are linear, and
+ * prox_{tau R}(c v) = c prox_{(tau/c) R}(v)); the solve runs every item at
+ * lambda_0 = max_b lambda_b on measurements scaled by 1 / s_b (a plan buffer
+ * of n_meas floats, allocated on first use) and scales item b of z^K by s_b.
+ * Requires batch <= OCT_MAX_LAMBDA_ITEMS, no bound, no objective report and no
+ * x0 (OCT_E_UNSUPPORTED otherwise); OCT_E_INVALID for a weight <= 0 or NaN.
  * z^k = prox(x^k - delta Phi^H(Phi x^k - y)) (with OCT_SOLVE_PAPER_BACKWARD:
  * Phi*(Phi x^k - y), the operator of oct_adjoint_paper); t^{k+1} = (1 + sqrt(1 + 4 t_k^2))/2;
  * x^{k+1} = z^k + (t^k - 1)/t^{k+1} (z^k - z^{k-1}).  Writes z^K to x_out.

@@ -46,7 +46,8 @@ class _CSolveParams(ctypes.Structure):
     _fields_ = [("penalty", ctypes.c_int32), ("iters", ctypes.c_int32), ("tv_inner", ctypes.c_int32),
                 ("haar_levels", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("seed", ctypes.c_uint64), ("lambda_", ctypes.c_double),
-                ("delta", ctypes.c_double), ("bound", ctypes.c_double), ("x0", ctypes.c_void_p)]
+                ("delta", ctypes.c_double), ("bound", ctypes.c_double), ("x0", ctypes.c_void_p),
+                ("lambda_item", ctypes.POINTER(ctypes.c_double))]
 
 
 class _CSolveReport(ctypes.Structure):
@@ -324,22 +325,30 @@ class Plan:
                                   ctypes.c_void_p(_stream_ptr(stream))))
         return out.value
 
-    def mbir_solve(self, y, penalty, lam: float, iters: int, delta: float = 0.0, tv_inner: int = 10,
+    def mbir_solve(self, y, penalty, lam, iters: int, delta: float = 0.0, tv_inner: int = 10,
                    haar_levels: int = 3, power_iters: int = 50, seed: int = 0, x0=None, x_out=None,
                    objective: bool = False, paper_backward: bool = False, bound=None, stream=None):
         """FISTA; returns (z^K, info) with info = {delta, lipschitz, objective (np.ndarray or None)}.
         paper_backward=True takes each gradient with the backward operator of
         eq. (10)-(11) (adjoint_paper) instead of the exact adjoint; bound sets the
-        constraint set C = {|x_i| <= bound} of the prox (l1, TV; None: none)."""
+        constraint set C = {|x_i| <= bound} of the prox (l1, TV; None: none).
+        lam: one weight, or a sequence of one weight per batch item."""
         import torch
         g = self.geom
         pen = PENALTIES[penalty] if isinstance(penalty, str) else int(penalty)
         if x_out is None:
             x_out = torch.empty(g.img_shape, dtype=torch.complex64, device=y.device)
+        lam_item = None
+        if np.ndim(lam) > 0:
+            lam_item = np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+            if lam_item.shape != (g.batch,):
+                raise ValueError(f"per-item weights must have shape ({g.batch},)")
+            lam = 0.0
         prm = _CSolveParams(pen, int(iters), int(tv_inner), int(haar_levels), int(power_iters),
                             SOLVE_PAPER_BACKWARD if paper_backward else 0,
                             int(seed), float(lam), float(delta), 0.0 if bound is None else float(bound),
-                            None if x0 is None else _dev(x0, torch.complex64, g.img_shape, "x0").value)
+                            None if x0 is None else _dev(x0, torch.complex64, g.img_shape, "x0").value,
+                            None if lam_item is None else lam_item.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         obj = np.zeros(iters, dtype=np.float64) if objective else None
         rep = _CSolveReport(0.0, 0.0, obj.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if objective else None)
         _check(_lib.oct_mbir_solve(self._h, _dev(y, torch.float32, g.meas_shape, "y"), ctypes.byref(prm),

@@ -207,6 +207,7 @@ struct oct_plan {
   float* beamone = nullptr;      // [Nlat] ones
   float2* phase_nd = nullptr;    // [Mk] e^{-j 2 k_m z_f} (no dispersion phase)
   float* yfill = nullptr;        // [batch][lat][Mk] real spectra (filled / residual), allocated on first use
+  float* yitem = nullptr;        // [batch][lat][Mk] measurements scaled per item (per-item weights), first use
   // solver state, allocated on first use
   float2 *za = nullptr, *zb = nullptr;
   float2* xext = nullptr;        // the extrapolated point x of the current iteration (lat_fwd -> update)
@@ -754,6 +755,7 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
        (size_t)Nlat * (8 + 4) * 2 + (size_t)g->n_k * 8 + (size_t)Nlat * ((g->n_k + 31) / 32) * 4;
   b += (size_t)N * 8 + (size_t)M * 8;            // workspace X1, W
   b += (size_t)Nlat * 16;                        // column-pair table of the half-spectrum path
+  b += (size_t)M * 4;                            // measurements scaled per item (per-item weights)
   if (g->model == OCT_MODEL_LITERAL)             // K's samples and the literal chain's tables
     b += (size_t)N * 8 + (size_t)g->n_depth * 16 + (size_t)g->n_k * 16;
   b += (size_t)N * 8 * 3;                        // FISTA iterates and the extrapolated point
@@ -1119,8 +1121,34 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   if ((prm->penalty == OCT_PEN_HAAR || prm->penalty == OCT_PEN_DTCWT) && bf < INFINITY)
     return fail(OCT_E_UNSUPPORTED, "a modulus bound with the Haar or DT-CWT step has no closed form");
   const bool paper = (prm->flags & OCT_SOLVE_PAPER_BACKWARD) != 0;
+  // per-item weights: every item runs at lambda = max_b lambda_b on its
+  // measurement scaled by lambda / lambda_b, and its z^K is scaled back
+  const bool per_item = prm->lambda_item != nullptr;
+  double lambda = prm->lambda;
+  ItemScales y_scale{}, z_scale{};
+  if (per_item) {
+    if (p->B > OCT_MAX_LAMBDA_ITEMS) return fail(OCT_E_UNSUPPORTED, "per-item weights need batch <= 64");
+    if (bf < INFINITY) return fail(OCT_E_UNSUPPORTED, "per-item weights with a modulus bound");
+    if (rep && rep->objective) return fail(OCT_E_UNSUPPORTED, "per-item weights with an objective report");
+    if (prm->x0) return fail(OCT_E_UNSUPPORTED, "per-item weights with a start point");
+    lambda = 0.0;
+    for (int64_t b = 0; b < p->B; ++b) {
+      const double l = prm->lambda_item[b];
+      if (!(l > 0) || !std::isfinite(l)) return fail(OCT_E_INVALID, "per-item weights must be finite and > 0");
+      lambda = std::max(lambda, l);
+    }
+    for (int64_t b = 0; b < p->B; ++b) {
+      y_scale.s[b] = (float)(lambda / prm->lambda_item[b]);
+      z_scale.s[b] = (float)(prm->lambda_item[b] / lambda);
+    }
+  }
   hipStream_t s = S(stream);
   OCTCHK(ensure_solver_state(p, prm->penalty, prm->iters));
+  if (per_item) {
+    if (!p->yitem) OCTCHK(dev_alloc(p, &p->yitem, (size_t)p->n_meas()));
+    HIPCHK(launch_scale_items(y, p->yitem, p->Nlat * p->Mk, (int)p->B, y_scale, s));
+    y = p->yitem;
+  }
   double delta = prm->delta, Lest = 0.0;
   if (!(delta > 0)) {
     if (prm->power_iters < 1) return fail(OCT_E_INVALID, "power_iters must be >= 1 when delta <= 0");
@@ -1148,7 +1176,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
     HIPCHK(launch_zero(zo, n, s));
   }
   const bool want_obj = rep && rep->objective;
-  const float tau = (float)(prm->lambda * delta);
+  const float tau = (float)(lambda * delta);
   float2* pin = nullptr;
   float2* pout = p->p0;
   const bool fused_l1 = (prm->penalty == OCT_PEN_L1) && p->lat_dims == 1;
@@ -1219,11 +1247,12 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
         }
       }
     }
-    if (want_obj) HIPCHK(launch_objective(res_part, nres, pen_part, npen, prm->lambda, p->hist + k, s));
+    if (want_obj) HIPCHK(launch_objective(res_part, nres, pen_part, npen, lambda, p->hist + k, s));
     std::swap(zc, zo);
     mu_prev = (float)mu[k];
   }
-  HIPCHK(launch_copy(zc, (float2*)x_out, n, s));
+  if (per_item) HIPCHK(launch_scale_items(zc, (float2*)x_out, p->Nlat * p->Nz, (int)p->B, z_scale, s));
+  else HIPCHK(launch_copy(zc, (float2*)x_out, n, s));
   if (rep) {
     rep->delta_used = delta;
     rep->lipschitz_est = Lest;

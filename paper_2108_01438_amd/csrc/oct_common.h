@@ -167,6 +167,14 @@ hipError_t launch_scale_by_inv_sqrt(const float2* x, float2* y, int64_t n, const
                                     hipStream_t s);
 hipError_t launch_fill_counter_uniform(float2* x, int64_t n, uint64_t seed, hipStream_t s);
 hipError_t launch_copy(const float2* x, float2* y, int64_t n, hipStream_t s);
+// per-item scale factors passed by value (no device copy): at most OCT_MAX_LAMBDA_ITEMS items
+struct ItemScales {
+  float s[64];
+};
+hipError_t launch_scale_items(const float* x, float* y, int64_t per_item, int items, const ItemScales& sc,
+                              hipStream_t s);
+hipError_t launch_scale_items(const float2* x, float2* y, int64_t per_item, int items, const ItemScales& sc,
+                              hipStream_t s);
 hipError_t launch_zero(float2* x, int64_t n, hipStream_t s);
 hipError_t launch_objective(const double* res_partial, int nres, const double* pen_partial,
                             int npen, double lambda, double* out, hipStream_t s);

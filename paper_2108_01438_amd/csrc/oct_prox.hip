@@ -89,6 +89,16 @@ __global__ void copy_kernel(const float2* __restrict__ x, float2* y, int64_t n) 
     y[i] = x[i];
 }
 
+// y[b][i] = s_b x[b][i] for items of per_item elements (T = float or float2)
+template <typename T>
+__global__ void scale_items_kernel(const T* __restrict__ x, T* y, int64_t per_item, int64_t n, ItemScales sc) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float f = sc.s[i / per_item];
+    if constexpr (sizeof(T) == sizeof(float)) y[i] = x[i] * f;
+    else y[i] = cscale(x[i], f);
+  }
+}
+
 __global__ void zero_kernel(float2* y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = make_float2(0.f, 0.f);
@@ -611,6 +621,20 @@ hipError_t launch_fill_counter_uniform(float2* x, int64_t n, uint64_t seed, hipS
 
 hipError_t launch_copy(const float2* x, float2* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_items(const float* x, float* y, int64_t per_item, int items, const ItemScales& sc,
+                              hipStream_t s) {
+  const int64_t n = per_item * items;
+  hipLaunchKernelGGL(scale_items_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, per_item, n, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_items(const float2* x, float2* y, int64_t per_item, int items, const ItemScales& sc,
+                              hipStream_t s) {
+  const int64_t n = per_item * items;
+  hipLaunchKernelGGL(scale_items_kernel<float2>, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, per_item, n, sc);
   return hipGetLastError();
 }
 

@@ -137,4 +137,14 @@ def test_lambda_search_on_device():
     assert r["ncc"] == max(v for _, v in r["evaluations"])
     z, _ = plan.mbir_solve(ym, "l1", r["lam"], 30, delta=delta)
     assert abs(plan.ncc(z, ref) - r["ncc"]) <= 1e-12
+    # a coarse scan run one candidate at a time and as one batched solve
+    import dataclasses
+    flush("[tune] coarse scan: sequential vs batched")
+    rs = tune_lambda(plan, ym, ref, "l1", lam_max, delta, iters=30, u_range=(-4.0, -0.5), search_iters=2,
+                     coarse=8)
+    rb = tune_lambda(plan, ym, ref, "l1", lam_max, delta, iters=30, u_range=(-4.0, -0.5), search_iters=2,
+                     coarse=8, batched_plan=P.Plan(dataclasses.replace(pg, batch=8), mask))
+    for (ua, va), (ub, vb) in zip(rs["evaluations"][:8], rb["evaluations"][:8]):
+        assert ua == ub and abs(va - vb) <= 1e-5
+    assert rs["u"] == rb["u"]
     torch.cuda.synchronize()
