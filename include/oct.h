@@ -104,7 +104,9 @@ oct_status oct_plan_destroy(oct_plan_t plan);
 
 /* Upper bound of the device bytes a plan plus one oct_mbir_solve of the given
  * penalty hold (tables, workspace, solver state); used for admission control.
- * Host-only, returns 0 for an invalid geometry. */
+ * penalty < 0: the bound for a plan that runs every penalty and entry point
+ * over its life (all solver states and optional buffers, which a plan keeps
+ * once allocated).  Host-only, returns 0 for an invalid geometry. */
 size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty);
 
 /* y = Phi x = diag(s) Re{ diag(e^{j Omega}) D Q K x }  (eq. (7)), computed as

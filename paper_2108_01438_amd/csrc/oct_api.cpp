@@ -759,8 +759,10 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   if (g->model == OCT_MODEL_LITERAL)             // K's samples and the literal chain's tables
     b += (size_t)N * 8 + (size_t)g->n_depth * 16 + (size_t)g->n_k * 16;
   b += (size_t)N * 8 * 3;                        // FISTA iterates and the extrapolated point
-  if (penalty == OCT_PEN_TV) b += (size_t)N * 8 * (2 * nd + 1 + nd);
-  if (penalty == OCT_PEN_DTCWT) b += (size_t)N * 8 * (g->lateral_dims == 2 ? 24 : 8);
+  const bool all = penalty < 0;                  // every penalty's state and every optional buffer
+  if (penalty == OCT_PEN_TV || all) b += (size_t)N * 8 * (2 * nd + 1 + nd);
+  if (penalty == OCT_PEN_DTCWT || all) b += (size_t)N * 8 * (g->lateral_dims == 2 ? 24 : 8);
+  if (all) b += (size_t)M * 4;                   // filled spectra / real residual (interpolated ISAM, paper backward)
   b += 64 * 1024 * 8;                            // partials, scalars, history
   return b;
 }

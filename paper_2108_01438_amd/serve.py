@@ -161,6 +161,21 @@ class Server:
                 "mean_s": float(lat.mean())}
 
 
+def plan_footprint(P, geom) -> int:
+    """Device bytes a pooled plan may hold over its life: plans are pooled by
+    geometry and mask and keep every solver state they have allocated, so the
+    bound covers every penalty (TV duals and the DT-CWT workspace together)."""
+    return int(P.footprint_bytes(geom, -1))
+
+
+def request_footprint(P, req: Request) -> int:
+    """Admission size of a request: its plan's bound + the y and result buffers."""
+    g = req.geom
+    img = g.batch * g.n_y * g.n_x * g.n_depth * 8
+    meas = g.batch * g.n_y * g.n_x * g.n_k * 4
+    return plan_footprint(P, g) + img + meas
+
+
 class HipExecutor:
     """Runs requests with liboct: one plan per in-flight request (pooled per
     geometry and mask), one stream per slot, device buffers for y and the result."""
@@ -184,11 +199,7 @@ class HipExecutor:
         return (dataclasses.astuple(g), mk)
 
     def footprint(self, req: Request) -> int:
-        """Plan (sized for the largest solver state, TV) + y + result buffers."""
-        g = req.geom
-        img = g.batch * g.n_y * g.n_x * g.n_depth * 8
-        meas = g.batch * g.n_y * g.n_x * g.n_k * 4
-        return int(self.P.footprint_bytes(g, self.P.PENALTIES["tv"])) + img + meas
+        return request_footprint(self.P, req)
 
     def cached_bytes(self) -> int:
         return self._cached
@@ -203,7 +214,7 @@ class HipExecutor:
             self._cached -= self.plan_bytes[id(plan)]
             return plan
         plan = self.P.Plan(req.geom, req.mask)
-        self.plan_bytes[id(plan)] = int(self.P.footprint_bytes(req.geom, self.P.PENALTIES["tv"]))
+        self.plan_bytes[id(plan)] = plan_footprint(self.P, req.geom)
         return plan
 
     def evict_idle(self, need: int) -> int:
@@ -285,4 +296,5 @@ def run_sequential(executor, reqs):
     return outs, time.perf_counter() - t0
 
 
-__all__ = ["Request", "Server", "HipExecutor", "AdmissionError", "run_sequential"]
+__all__ = ["Request", "Server", "HipExecutor", "AdmissionError", "run_sequential", "plan_footprint",
+           "request_footprint"]

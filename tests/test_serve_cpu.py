@@ -168,3 +168,29 @@ def test_serving_mix_geometries_pass_plan_validation():
             except P.OctError as e:
                 assert e.status != 4, (spec["geom"], str(e))
     assert len(seen) > 100
+
+
+def test_admission_footprint_covers_every_penalty_state():
+    """A pooled plan keeps every solver state it allocates (plans are pooled
+    by geometry and mask, not penalty), so admission and pool accounting use a
+    bound that covers them all: at least the library's footprint for TV and
+    for the DT-CWT (whose volume workspace is the largest), for B-scans and
+    volumes, plus the request's own y and result buffers."""
+    import paper_2108_01438_amd as P
+    from paper_2108_01438_amd.serve import Request, plan_footprint, request_footprint
+    for geo in (P.Geometry(n_depth=1024, n_x=512, n_k=1024),
+                P.Geometry(n_depth=1024, n_x=64, n_y=64, n_k=1024, lateral_dims=2)):
+        img = geo.n_y * geo.n_x * geo.n_depth * 8
+        meas = geo.n_y * geo.n_x * geo.n_k * 4
+        tv = P.footprint_bytes(geo, P.PEN_TV)
+        dt = P.footprint_bytes(geo, P.PEN_DTCWT)
+        both = plan_footprint(P, geo)
+        assert both >= max(tv, dt)
+        # both states together: the DT-CWT workspace on top of the TV footprint
+        extra_dt = dt - P.footprint_bytes(geo, P.PEN_L1)
+        assert both >= tv + extra_dt
+        r = Request(geom=geo, y=np.zeros((1, geo.n_y, geo.n_x, geo.n_k), np.float32), penalty="dtcwt")
+        assert request_footprint(P, r) == both + img + meas
+    v = P.Geometry(n_depth=1024, n_x=64, n_y=64, n_k=1024, lateral_dims=2)
+    n = 64 * 64 * 1024
+    assert P.footprint_bytes(v, P.PEN_DTCWT) - P.footprint_bytes(v, P.PEN_L1) == 24 * 8 * n
