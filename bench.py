@@ -680,6 +680,9 @@ def main() -> int:
                     help="only compare the paper's literal K, Q, D chain with the direct model (M_k = 2 N_z)")
     ap.add_argument("--paper-backward", action="store_true",
                     help="only compare the paper's backward operator with the exact adjoint (cost and solutions)")
+    ap.add_argument("--profile-stages", action="store_true",
+                    help="only run every stage of the headline workload's FISTA iteration --stage-reps times on "
+                         "random data (for counter profiles)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (counter calibration)")
     args = ap.parse_args()
@@ -690,6 +693,9 @@ def main() -> int:
         with open(path, "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
+        return 0
+    if args.profile_stages:
+        print(json.dumps(profile_stages(args)), flush=True)
         return 0
     if args.copy_probe_mib > 0:
         import torch
@@ -738,6 +744,25 @@ def main() -> int:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
     return 0
+
+
+def profile_stages(args) -> dict:
+    """Every stage of one FISTA iteration of the headline workload, --stage-reps
+    times each, on random data (the launch shapes of the timed solve)."""
+    import torch
+    import paper_2108_01438_amd as P
+    import synth
+    torch.cuda.set_device(0)
+    name, pen = (WORKLOAD, "haar") if args.workload == "volume" else (BSCAN, "tv")
+    geom = P.Geometry.from_dict(synth.preset(name)["geom"])
+    plan = P.Plan(geom)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    y = torch.randn(geom.meas_shape, dtype=torch.float32, device="cuda", generator=gen)
+    sb = stage_bytes(geom, False, pen)
+    st = time_stages(plan, pen, y, sb, args.stage_reps)
+    plan.close()
+    return {"workload": name, "reps": args.stage_reps,
+            "stages_ms": {k: round(v["ms"], 5) for k, v in st.items()}}
 
 
 def time_stages(plan, penalty: str, y, sb: dict, reps: int) -> dict:

@@ -226,6 +226,7 @@ constexpr short EVANESCENT16 = -32768;
 // fractions, base cells) and, after the gather, the K-cell grid share one
 // region; each thread holds its cells in registers in between.
 constexpr int ADJ_MAXC = 8;   // grid cells per thread
+constexpr int ADJ_REG_SAMPLES = 2;   // samples per thread kept in registers by the pair adjoint's scatter path
 
 template <int J, bool ONE>
 __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs a, const float2* __restrict__ Rh,
@@ -451,60 +452,16 @@ __global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const
   }
 }
 
-template <int J, bool ONE>
-__global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_pair_kernel(NufftArgs a, const float2* __restrict__ Rh,
-                                                                           float2* __restrict__ X) {
-  extern __shared__ float4 smem4[];
-  __shared__ float kc[J * KBH];
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int K = a.K, Mk = a.Mk, Nz = a.Nz, nc = a.nc;
-  const int b = blockIdx.x / a.n_pairs;
-  const int4 pr = a.pairs[blockIdx.x - b * a.n_pairs];
-  float2* region = reinterpret_cast<float2*>(smem4);
-  float2* grid = region;                    // after the gather: two rows of K cells
-  float2* us0 = region;                     // before: filtered samples of column q
-  float2* us1 = us0 + Mk;                   // and of column -q
-  float* xm = reinterpret_cast<float*>(us1 + Mk);
-  short* bm = reinterpret_cast<short*>(xm + Mk);
-  short* first = bm + Mk;                   // [K] first contributing sample of each cell
-
-  __shared__ int s_mf;
-  if (tid == 0) s_mf = Mk;
-  for (int i = tid; i < J * KBH; i += nthr) kc[i] = a.kbc[i];
-  const double q2 = a.q2[pr.x];
-  const float bq = a.beam[pr.x];
-  const float2* __restrict__ rin = Rh + ((int64_t)b * a.n_half + pr.z) * Mk;
-  __syncthreads();
-  for (int m = tid; m < Mk; m += nthr) {
-    const KPR v{a.k2x4[m], a.phase[m], rin[m]};
-    const double arg = v.k2 - q2;
-    if (arg > 0.0 && (m == 0 || a.k2x4[m - 1] - q2 <= 0.0)) s_mf = m;
-    if (arg > 0.0) {
-      const double beta = beta_of(arg);
-      const double t = a.ct * beta;
-      const double fl = floor(t);
-      bm[m] = (short)(int)fl;
-      xm[m] = (float)(2.0 * (t - fl) - 1.0);
-      const float2 hc = cconj(filter_h(a, v.ph, bq, beta));
-      us0[m] = cmul(hc, v.r);
-      us1[m] = cmul(hc, cconj(v.r));
-    } else {
-      bm[m] = EVANESCENT16;
-      xm[m] = 0.f;
-      us0[m] = make_float2(0.f, 0.f);
-      us1[m] = make_float2(0.f, 0.f);
-    }
-  }
-  __syncthreads();
-
-  const int mf = s_mf;
-  int umin = 0, umax = -1;
-  if (mf < Mk) {
-    umin = bm[mf] - J / 2 + 1;
-    umax = bm[Mk - 1] + J / 2;
-  }
-  const int span = umax - umin + 1;
-  const int nph = span > K ? (span + K - 1) / K : 1;
+// The cell gather of the pair adjoint (the general path): first-contributor
+// table, per-cell sums over the samples in increasing m (both columns from one
+// weight evaluation), then the sums into the two grid rows.  The sample
+// arrays are read from LDS; the grid rows overwrite them at the end.
+template <int J>
+__device__ __forceinline__ void adj_pair_gather(const NufftArgs& a, const float* kc, double q2, const short* bm,
+                                                const float* xm, const float2* us0, const float2* us1, short* first,
+                                                float2* grid, int mf, int umin, int umax, int span, int nph,
+                                                int tid, int nthr) {
+  const int K = a.K, Mk = a.Mk;
   if (nph == 1) {
     for (int m = mf + tid; m < Mk; m += nthr) {
       const int ulo = (m == mf) ? umin : bm[m - 1] + J / 2 + 1;
@@ -580,6 +537,156 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_pair_kernel(Nufft
   }
   __syncthreads();
 
+}
+
+template <int J, bool ONE>
+__global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_pair_kernel(NufftArgs a, const float2* __restrict__ Rh,
+                                                                           float2* __restrict__ X) {
+  extern __shared__ float4 smem4[];
+  __shared__ float kc[J * KBH];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int K = a.K, Mk = a.Mk, Nz = a.Nz, nc = a.nc;
+  const int b = blockIdx.x / a.n_pairs;
+  const int4 pr = a.pairs[blockIdx.x - b * a.n_pairs];
+  float2* region = reinterpret_cast<float2*>(smem4);
+  float2* grid = region;                    // after the gather: two rows of K cells
+  float2* us0 = region;                     // before: filtered samples of column q
+  float2* us1 = us0 + Mk;                   // and of column -q
+  float* xm = reinterpret_cast<float*>(us1 + Mk);
+  short* bm = reinterpret_cast<short*>(xm + Mk);
+  short* first = bm + Mk;                   // [K] first contributing sample of each cell
+
+  __shared__ int s_mf, s_dup;
+  if (tid == 0) {
+    s_mf = Mk;
+    s_dup = 0;
+  }
+  for (int i = tid; i < J * KBH; i += nthr) kc[i] = a.kbc[i];
+  const double q2 = a.q2[pr.x];
+  const float bq = a.beam[pr.x];
+  const float2* __restrict__ rin = Rh + ((int64_t)b * a.n_half + pr.z) * Mk;
+  __syncthreads();
+  // Per-sample setup.  When every thread's samples fit ADJ_REG_SAMPLES, they
+  // stay in registers (only the base cells go to LDS, for the checks below);
+  // otherwise all sample arrays go to LDS for the cell gather.
+  const bool regs = Mk <= ADJ_REG_SAMPLES * nthr;
+  int cb[ADJ_REG_SAMPLES];
+  float xr[ADJ_REG_SAMPLES];
+  float2 u0r[ADJ_REG_SAMPLES], u1r[ADJ_REG_SAMPLES];
+  auto setup = [&](int m, int& c, float& x, float2& u0, float2& u1) __attribute__((always_inline)) {
+    const KPR v{a.k2x4[m], a.phase[m], rin[m]};
+    const double arg = v.k2 - q2;
+    if (arg > 0.0 && (m == 0 || a.k2x4[m - 1] - q2 <= 0.0)) s_mf = m;
+    if (arg > 0.0) {
+      const double beta = beta_of(arg);
+      const double t = a.ct * beta;
+      const double fl = floor(t);
+      c = (int)fl;
+      x = (float)(2.0 * (t - fl) - 1.0);
+      const float2 hc = cconj(filter_h(a, v.ph, bq, beta));
+      u0 = cmul(hc, v.r);
+      u1 = cmul(hc, cconj(v.r));
+    } else {
+      c = EVANESCENT;
+      x = 0.f;
+      u0 = make_float2(0.f, 0.f);
+      u1 = make_float2(0.f, 0.f);
+    }
+    bm[m] = c == EVANESCENT ? EVANESCENT16 : (short)c;   // t < 32000 (checked at plan creation)
+  };
+  if (regs) {
+#pragma unroll
+    for (int i = 0; i < ADJ_REG_SAMPLES; ++i) {
+      const int m = tid + i * nthr;
+      cb[i] = EVANESCENT;
+      xr[i] = 0.f;
+      u0r[i] = u1r[i] = make_float2(0.f, 0.f);
+      if (m < Mk) setup(m, cb[i], xr[i], u0r[i], u1r[i]);
+    }
+  } else {
+    for (int m = tid; m < Mk; m += nthr) {
+      int c;
+      float x;
+      float2 u0, u1;
+      setup(m, c, x, u0, u1);
+      xm[m] = x;
+      us0[m] = u0;
+      us1[m] = u1;
+    }
+  }
+  __syncthreads();
+
+  const int mf = s_mf;
+  int umin = 0, umax = -1;
+  if (mf < Mk) {
+    umin = bm[mf] - J / 2 + 1;
+    umax = bm[Mk - 1] + J / 2;
+  }
+  const int span = umax - umin + 1;
+  const int nph = span > K ? (span + K - 1) / K : 1;
+
+  // Scatter path: with distinct base cells (consecutive samples at least a
+  // cell apart: sigma >= 2, up to rounding, which the check below catches)
+  // and a span within K cells, tap j of every sample hits a different grid
+  // cell, so one LDS pass per tap adds w_j u into the cells with no
+  // conflicts.  Taps go from J - 1 down to 0, i.e. each cell receives its
+  // samples in increasing m: the order of the cell gather.
+  if (regs && nph == 1) {
+#pragma unroll
+    for (int i = 0; i < ADJ_REG_SAMPLES; ++i) {
+      const int m = tid + i * nthr;
+      if (m > mf && m < Mk && bm[m] <= bm[m - 1]) s_dup = 1;
+    }
+  }
+  __syncthreads();
+  if (regs && nph == 1 && !s_dup) {
+    for (int i = tid; i < 2 * K; i += nthr) grid[i] = make_float2(0.f, 0.f);   // over the base cells: read above
+    float w[ADJ_REG_SAMPLES][J];
+    int g0[ADJ_REG_SAMPLES];
+#pragma unroll
+    for (int i = 0; i < ADJ_REG_SAMPLES; ++i) {
+      const float x = xr[i], x2 = x * x;
+#pragma unroll
+      for (int jj = 0; jj < J / 2; ++jj) kb_pair(a.kbc + jj * 2 * KBH, x, x2, w[i][jj], w[i][J - 1 - jj]);
+      int g = (cb[i] - J / 2 + 1) % K;
+      g0[i] = g < 0 ? g + K : g;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = J - 1; j >= 0; --j) {
+#pragma unroll
+      for (int i = 0; i < ADJ_REG_SAMPLES; ++i) {
+        const int m = tid + i * nthr;
+        if (m >= mf && m < Mk) {
+          int g = g0[i] + j;
+          if (g >= K) g -= K;
+          float2 c0 = grid[g], c1 = grid[K + g];
+          c0.x = fmaf(w[i][j], u0r[i].x, c0.x);
+          c0.y = fmaf(w[i][j], u0r[i].y, c0.y);
+          c1.x = fmaf(w[i][j], u1r[i].x, c1.x);
+          c1.y = fmaf(w[i][j], u1r[i].y, c1.y);
+          grid[g] = c0;
+          grid[K + g] = c1;
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    if (regs) {   // the gather reads the samples from LDS
+#pragma unroll
+      for (int i = 0; i < ADJ_REG_SAMPLES; ++i) {
+        const int m = tid + i * nthr;
+        if (m < Mk) {
+          xm[m] = xr[i];
+          us0[m] = u0r[i];
+          us1[m] = u1r[i];
+        }
+      }
+      __syncthreads();
+    }
+    adj_pair_gather<J>(a, kc, q2, bm, xm, us0, us1, first, grid, mf, umin, umax, span, nph, tid, nthr);
+  }
+
   fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(grid, 2, K, a.fK, a.twK, tid, nthr);
   float2* __restrict__ d0 = X + ((int64_t)b * a.Nlat + pr.x) * Nz;
   float2* __restrict__ d1 = X + ((int64_t)b * a.Nlat + pr.y) * Nz;
@@ -591,6 +698,7 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_pair_kernel(Nufft
     if (two) d1[n] = cscale(grid[K + idx], d);
   });
 }
+
 
 // Threads per column: enough for the FFT stages, and wide enough that the
 // per-column work is short (the column count of a B-scan is only ~1000).
