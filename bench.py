@@ -290,76 +290,102 @@ def cpu_baseline(slab_y: int = 16) -> dict:
                       f"{res[nt]:.1f} s on {nt} threads, {res[1]:.1f} s on one; host: {model}"}
 
 
-def serving_bench(n_req: int, seed: int = 4) -> dict:
+def serving_bench(n_req: int, seed: int = 4, warmup: int = 20, rates=(0.5, 0.8, 1.0), slots: int = 8,
+                  budget_gib: int = 200) -> dict:
     """Serving mix (60% B-scans 1024-2048 px x 256-2000 A-scans, 30% volumes
     1024 x 64^2..128^2, 10% 512 x 64 B-scans; random penalty, 50-100
-    iterations): sequential solves vs the continuous-batching server, closed
-    loop and Poisson arrivals at 0.8x the sequential rate."""
+    iterations): `warmup` requests first, then `n_req` requests solved one at
+    a time (the sequential rate C), by the continuous-batching server with
+    every request queued at once (closed loop), and with Poisson arrivals at
+    each rate x C.  Every result of the mix is compared bitwise with its
+    sequential solve (SHA-1 of the bytes)."""
+    import hashlib
     import numpy as np
     import torch
     import paper_2108_01438_amd as P
     import synth
     from paper_2108_01438_amd.serve import HipExecutor, Request, Server, run_sequential
     rng = np.random.default_rng(seed)
-    mix = synth.serving_mix(rng, n_req)
-    reqs, Lcache = [], {}
-    for spec in mix:
+    mix = synth.serving_mix(rng, warmup + n_req)
+    reqs, Lcache, plans = [], {}, {}
+    t0 = time.perf_counter()
+    for i, spec in enumerate(mix):
         r = np.random.default_rng(spec["seed"])
         geo = dict(synth.OPTICS)
         geo.update(spec["geom"])
         g = P.Geometry.from_dict(geo)
-        plan = P.Plan(g)
+        key = tuple(sorted(spec["geom"].items()))
+        plan = plans.get(key)
+        if plan is None:
+            if len(plans) > 16:
+                for p_ in plans.values():
+                    p_.close()
+                plans.clear()
+            plan = plans[key] = P.Plan(g)
         x = synth.scatterers(r, g.img_shape, 20).astype(np.complex64)
         y = plan.forward(torch.from_numpy(x).cuda())
-        y = (y + 0.01 * float(y.abs().max().item()) * torch.randn_like(y)).contiguous()
+        noise = torch.from_numpy(synth.standard_normal(r, g.meas_shape).astype(np.float32)).cuda()
+        y = (y + 0.01 * float(y.abs().max().item()) * noise).contiguous()
         lam = spec["lam"] * float(plan.adjoint(y).abs().max().item())
-        key = tuple(sorted(spec["geom"].items()))
         if key not in Lcache:
             Lcache[key] = plan.lipschitz(50)
-        plan.close()
         reqs.append(Request(geom=g, y=y.cpu().numpy(), penalty=spec["pen"], lam=lam, iters=spec["iters"],
                             delta=1.0 / (1.05 * Lcache[key])))
-    print(f"[serving] {n_req} requests ready", file=sys.stderr, flush=True)
+        if (i + 1) % 100 == 0:
+            print(f"[serving] {i + 1} requests ready ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    for p_ in plans.values():
+        p_.close()
+    warm, meas = reqs[:warmup], reqs[warmup:]
+    digest = lambda a: hashlib.sha1(np.ascontiguousarray(a).view(np.uint8)).hexdigest()   # noqa: E731
+    budget = budget_gib << 30
+
     ex1 = HipExecutor(slots=1)
-    run_sequential(ex1, reqs[:2])               # plan and code warm-up
-    alone, t_seq = run_sequential(ex1, reqs)
+    run_sequential(ex1, warm)
+    t0 = time.perf_counter()
+    alone = []
+    for r in meas:
+        outs, _ = run_sequential(ex1, [r])
+        alone.append(digest(outs[0]))
+    t_seq = time.perf_counter() - t0
     ex1.shutdown()
     C = n_req / t_seq
     print(f"[serving] sequential {C:.2f} solves/s", file=sys.stderr, flush=True)
-    budget = 96 << 30
-    srv = Server(HipExecutor(slots=8), mem_budget=budget, slots=8)
-    t0 = time.perf_counter()
-    futs = [srv.submit(r) for r in reqs]
-    mix_out = [f.result(timeout=600) for f in futs]
-    t_closed = time.perf_counter() - t0
-    srv.close()
-    mism = sum(int(not np.array_equal(a.view(np.uint32), b.view(np.uint32))) for a, b in zip(alone, mix_out))
-    closed = srv.latency_stats()
-    print(f"[serving] closed loop {n_req / t_closed:.2f} solves/s", file=sys.stderr, flush=True)
-    rate = 0.8 * C
-    arr = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
-    srv = Server(HipExecutor(slots=8), mem_budget=budget, slots=8)
-    t0 = time.perf_counter()
-    futs = []
-    for r, ta in zip(reqs, arr):
-        dt = t0 + ta - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
-        futs.append(srv.submit(r))
-    for f in futs:
-        f.result(timeout=600)
-    t_pois = time.perf_counter() - t0
-    srv.close()
-    pst = srv.latency_stats()
-    return {"metric": "serving solves/s with p50/p99 latency (continuous batching vs sequential solves)",
-            "requests": n_req, "sequential_solves_per_s": round(C, 3),
-            "closed_loop_solves_per_s": round(n_req / t_closed, 3),
-            "closed_loop_gain": round((n_req / t_closed) / C, 3),
-            "closed_loop_p50_ms": round(closed["p50_s"] * 1e3, 2), "closed_loop_p99_ms": round(closed["p99_s"] * 1e3, 2),
-            "poisson_rate_solves_per_s": round(rate, 3), "poisson_solves_per_s": round(n_req / t_pois, 3),
-            "poisson_p50_ms": round(pst["p50_s"] * 1e3, 2), "poisson_p99_ms": round(pst["p99_s"] * 1e3, 2),
-            "sequential_mean_ms": round(t_seq / n_req * 1e3, 2),
-            "alone_vs_mix_bitwise_mismatches": mism, "slots": 8, "mem_budget_GiB": budget >> 30}
+
+    def serve(arrivals):
+        srv = Server(HipExecutor(slots=slots), mem_budget=budget, slots=slots)
+        for f in [srv.submit(r) for r in warm]:
+            f.result(timeout=600)
+        srv.completed.clear()
+        t_start = time.perf_counter()
+        futs = []
+        for r, ta in zip(meas, arrivals):
+            dt = t_start + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            futs.append(srv.submit(r))
+        outs = [digest(f.result(timeout=900)) for f in futs]
+        t_all = time.perf_counter() - t_start
+        srv.close()
+        st = srv.latency_stats()
+        mism = sum(int(a != b) for a, b in zip(alone, outs))
+        return {"solves_per_s": round(n_req / t_all, 3), "p50_ms": round(st["p50_s"] * 1e3, 2),
+                "p99_ms": round(st["p99_s"] * 1e3, 2), "mean_ms": round(st["mean_s"] * 1e3, 2),
+                "alone_vs_mix_mismatches": mism}
+
+    out = {"metric": "serving solves/s with p50/p99 latency (continuous batching vs sequential solves)",
+           "warmup_requests": warmup, "requests": n_req, "slots": slots, "mem_budget_GiB": budget_gib,
+           "sequential_solves_per_s": round(C, 3), "sequential_mean_ms": round(t_seq / n_req * 1e3, 2)}
+    cl = serve([0.0] * n_req)
+    out["closed_loop"] = cl
+    out["closed_loop_gain"] = round(cl["solves_per_s"] / C, 3)
+    print(f"[serving] closed loop {cl}", file=sys.stderr, flush=True)
+    for rate in rates:
+        arr = np.cumsum(rng.exponential(1.0 / (rate * C), size=n_req))
+        res = serve(list(arr))
+        res["offered_solves_per_s"] = round(rate * C, 3)
+        out[f"poisson_{rate:g}C"] = res
+        print(f"[serving] poisson {rate:g} C: {res}", file=sys.stderr, flush=True)
+    return out
 
 
 def table1_bench(search_iters: int = 10, u_range=(-6.0, -0.5), coarse: int = 8) -> dict:
@@ -667,7 +693,9 @@ def main() -> int:
                     help="only write profiles/traffic_<workload>.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
                          "runs of this bench and of --copy-probe-mib 512")
     ap.add_argument("--serving", type=int, default=0,
-                    help="only run the serving benchmark with this many requests")
+                    help="only run the serving benchmark with this many measured requests")
+    ap.add_argument("--serving-warmup", type=int, default=20, help="warm-up requests of the serving benchmark")
+    ap.add_argument("--serving-slots", type=int, default=8, help="concurrent solves of the serving benchmark")
     ap.add_argument("--table1", action="store_true",
                     help="only run the synthetic analogue of Table 1 (NCC of direct, interpolated and MBIR images)")
     ap.add_argument("--phi-sizes", action="store_true",
@@ -725,7 +753,8 @@ def main() -> int:
     if args.serving > 0:
         import torch
         torch.cuda.set_device(0)
-        print(json.dumps(serving_bench(args.serving)), flush=True)
+        print(json.dumps(serving_bench(args.serving, warmup=args.serving_warmup, slots=args.serving_slots)),
+              flush=True)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -102,6 +102,14 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
 /* Free a plan and everything it owns.  Synchronises the device first. */
 oct_status oct_plan_destroy(oct_plan_t plan);
 
+/* Free a plan without synchronising the device: for pools of plans (the
+ * serving loop) that know the plan's work is complete, e.g. from an event
+ * recorded after its last call; freeing a plan with work still pending on
+ * some stream is undefined.  Plan memory comes from the device's
+ * stream-ordered memory pool, whose freed blocks serve the next plans (the
+ * library raises the pool's release threshold, so the process keeps them). */
+oct_status oct_plan_release(oct_plan_t plan);
+
 /* Upper bound of the device bytes a plan plus one oct_mbir_solve of the given
  * penalty hold (tables, workspace, solver state); used for admission control.
  * penalty < 0: the bound for a plan that runs every penalty and entry point

@@ -66,6 +66,7 @@ def _load():
     sig = {
         "oct_plan_create": ([ctypes.POINTER(_CGeometry), P, ctypes.POINTER(P)], ctypes.c_int),
         "oct_plan_destroy": ([P], ctypes.c_int),
+        "oct_plan_release": ([P], ctypes.c_int),
         "oct_plan_footprint_bytes": ([ctypes.POINTER(_CGeometry), ctypes.c_int32], ctypes.c_size_t),
         "oct_forward": ([P, P, P, P], ctypes.c_int),
         "oct_adjoint": ([P, P, P, P], ctypes.c_int),
@@ -215,6 +216,13 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             _lib.oct_plan_destroy(self._h)
+            self._h = None
+
+    def release(self):
+        """Free the plan without synchronising the device (oct_plan_release):
+        only when every call using it has completed."""
+        if getattr(self, "_h", None):
+            _lib.oct_plan_release(self._h)
             self._h = None
 
     def __del__(self):

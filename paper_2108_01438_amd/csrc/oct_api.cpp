@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -223,12 +224,31 @@ struct oct_plan {
 
 namespace {
 
+// Plan memory comes from the device's stream-ordered pool on the null stream
+// (allocated ready for use: the null stream is synchronised), so that a plan
+// can be freed without synchronising the device (oct_plan_release).  The
+// pool keeps freed blocks for the next plans (release threshold raised once
+// per device).
+void keep_pool_memory(int device) {
+  static std::mutex mu;
+  static bool done[64] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0 || device >= 64 || done[device]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  done[device] = true;
+}
+
 template <typename T>
 oct_status dev_alloc(oct_plan* p, T** out, size_t count) {
   void* ptr = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
-  if (e != hipSuccess) return fail(OCT_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  hipError_t e = hipMallocAsync(&ptr, count * sizeof(T), nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return fail(OCT_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
   p->allocs.push_back(ptr);
   *out = reinterpret_cast<T*>(ptr);
   return OCT_OK;
@@ -628,6 +648,7 @@ int partial_need(oct_plan* p) {
 }
 
 oct_status ensure_solver_state(oct_plan* p, int pen, int iters) {
+  const size_t n0 = p->allocs.size();
   if (!p->za) {
     OCTCHK(dev_alloc(p, &p->za, p->n_img()));
     OCTCHK(dev_alloc(p, &p->zb, p->n_img()));
@@ -655,6 +676,8 @@ oct_status ensure_solver_state(oct_plan* p, int pen, int iters) {
     OCTCHK(dev_alloc(p, &p->hist, (size_t)iters));
     p->hist_cap = iters;
   }
+  // first use: the null-stream clears above finish before the caller's stream runs
+  if (p->allocs.size() != n0) HIPCHK(hipStreamSynchronize(nullptr));
   return OCT_OK;
 }
 
@@ -776,6 +799,7 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   if (!p) return fail(OCT_E_NOMEM, "host allocation failed");
   p->g = *g;
   HIPCHK(hipGetDevice(&p->device));
+  keep_pool_memory(p->device);
   p->lat_dims = g->lateral_dims;
   p->Nz = g->n_depth;
   p->Nx = g->n_x;
@@ -922,7 +946,8 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   if ((st = dev_alloc(p, &p->X1, p->n_img())) != OCT_OK) return cleanup(st);
   if ((st = dev_alloc(p, &p->W, p->n_meas())) != OCT_OK) return cleanup(st);
   if (hipMemset(p->X1, 0, sizeof(float2) * p->n_img()) != hipSuccess ||
-      hipMemset(p->W, 0, sizeof(float2) * p->n_meas()) != hipSuccess)
+      hipMemset(p->W, 0, sizeof(float2) * p->n_meas()) != hipSuccess ||
+      hipStreamSynchronize(nullptr) != hipSuccess)
     return cleanup(fail(OCT_E_DEVICE, "hipMemset of the workspace failed"));
   p->partial_cap = partial_need(p);
   if ((st = dev_alloc(p, &p->partial, (size_t)p->partial_cap * 2)) != OCT_OK) return cleanup(st);
@@ -935,7 +960,19 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
 oct_status oct_plan_destroy(oct_plan_t p) {
   if (!p) return OCT_OK;
   hipDeviceSynchronize();
-  for (void* a : p->allocs) hipFree(a);
+  for (void* a : p->allocs) hipFreeAsync(a, nullptr);
+  hipStreamSynchronize(nullptr);
+  delete p;
+  return OCT_OK;
+}
+
+oct_status oct_plan_release(oct_plan_t p) {
+  if (!p) return OCT_OK;
+  int cur = 0;
+  hipGetDevice(&cur);
+  if (cur != p->device) hipSetDevice(p->device);
+  for (void* a : p->allocs) hipFreeAsync(a, nullptr);   // ordered on the null stream, no device-wide wait
+  if (cur != p->device) hipSetDevice(cur);
   delete p;
   return OCT_OK;
 }

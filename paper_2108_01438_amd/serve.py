@@ -228,7 +228,7 @@ class HipExecutor:
             b = self.plan_bytes.pop(id(plan), 0)
             self._cached -= b
             freed += b
-            plan.close()
+            plan.release()   # idle: its last solve's event has completed; no device-wide wait
         return freed
 
     def start(self, req: Request):
@@ -279,7 +279,7 @@ class HipExecutor:
     def shutdown(self):
         for lst in self.idle.values():
             for p in lst:
-                p.close()
+                p.release()
         self.idle.clear()
         self._cached = 0
 

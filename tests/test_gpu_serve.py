@@ -49,7 +49,12 @@ def test_mix_equals_alone_and_oracle():
     flush("[serve] alone")
     alone, _ = run_sequential(HipExecutor(slots=1), reqs)
     flush("[serve] mix")
-    srv = Server(HipExecutor(slots=4), mem_budget=2 << 30, slots=4)
+    # a budget of ~2.5 of the largest requests: idle pooled plans are released
+    # (without a device-wide wait) while other requests run
+    from paper_2108_01438_amd.serve import request_footprint
+    import paper_2108_01438_amd as P
+    budget = int(2.5 * max(request_footprint(P, r) for r in reqs))
+    srv = Server(HipExecutor(slots=4), mem_budget=budget, slots=4)
     futs = [srv.submit(r) for r in reqs]
     mix = [f.result(timeout=60) for f in futs]
     srv.close()
@@ -62,3 +67,24 @@ def test_mix_equals_alone_and_oracle():
     og = O.Geometry(**{k: getattr(r.geom, k) for k in r.geom.__dataclass_fields__})
     zo, _ = O.fista(r.y.astype(np.float64), og, r.mask, O.PEN_TV, r.lam, r.delta, r.iters, tv_inner=10)
     assert rel(mix[1], zo) <= 1e-4
+
+
+def test_released_plan_memory_is_reused_correctly():
+    """oct_plan_release frees an idle plan without a device-wide wait; its
+    memory serves the next plan, whose results are those of a fresh plan."""
+    import torch
+    import paper_2108_01438_amd as P
+    g = P.Geometry(n_depth=256, n_x=64, n_k=256)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.randn(g.img_shape, dtype=torch.complex64, device="cuda", generator=gen)
+    a = P.Plan(g)
+    ya = a.forward(x)
+    torch.cuda.synchronize()
+    a.release()
+    for _ in range(3):
+        b = P.Plan(g)
+        yb = b.forward(x)
+        z, _ = b.mbir_solve(yb, "tv", 0.1, 5, delta=1e-4)
+        torch.cuda.synchronize()
+        assert torch.equal(ya, yb)
+        b.release()
