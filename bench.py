@@ -254,10 +254,10 @@ def volume_specimen(synth, shape, pr):
     return x.astype(np.complex64)
 
 
-def cpu_baseline(slab_y: int = 16) -> dict:
+def cpu_baseline(slab_y: int = 32) -> dict:
     """The FP64 oracle, as it stands, on one FISTA-Haar iteration of a slab of
     the volume workload (all 2048 depth samples and 256 A-scans along x, slab_y
-    of the 256 along y, i.e. 1/16 of the volume), on one thread and on every
+    of the 256 along y, i.e. 1/8 of the volume), on one thread and on every
     host core; the rate is scaled to the whole volume (time x 256 / slab_y)."""
     import numpy as np
     import oracle as O
