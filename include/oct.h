@@ -213,6 +213,12 @@ typedef struct {
   const void* x0;         /* device image, start point; NULL = zero               */
   const double* lambda_item; /* HOST [batch] or NULL: a regularisation weight per
                              batch item (lambda is then unused); see below       */
+  const void* z_prev0;    /* device image or NULL: z^{k0-1} of a resumed solve
+                             (NULL: x0)                                            */
+  void* z_prev_out;       /* device image or NULL: receives z^{K-1} (with x_out's
+                             z^K, the state a later solve resumes from)            */
+  int32_t k0;             /* iterations already done (>= 0): the momenta continue
+                             from t_{k0+1}; k0 > 0 needs x0 = z^{k0}               */
 } oct_solve_params;
 
 /* Largest batch that oct_solve_params.lambda_item may describe. */
@@ -226,6 +232,11 @@ typedef struct {
 } oct_solve_report;
 
 /* FISTA (Sec. 2.3, eq. (15)): x^1 = x0, z^0 = x^1, t^1 = 1;
+ * Resume: a solve of K iterations with x0 = z^k0, z_prev0 = z^{k0-1} and k0
+ * continues a solve that has run k0 iterations; the two together equal one
+ * solve of k0 + K iterations bitwise (for TV the dual warm start continues
+ * from the plan's own last solve: resume on the plan that ran the first part,
+ * with nothing else solved on it in between).
  * Per-item weights (lambda_item != NULL): item b solves its own problem with
  * weight lambda_item[b] > 0 (e.g. the candidates of the lambda search of
  * Sec. 3.2 on one measurement replicated over the batch).  Every penalty is

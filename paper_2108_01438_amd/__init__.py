@@ -47,7 +47,8 @@ class _CSolveParams(ctypes.Structure):
                 ("haar_levels", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("seed", ctypes.c_uint64), ("lambda_", ctypes.c_double),
                 ("delta", ctypes.c_double), ("bound", ctypes.c_double), ("x0", ctypes.c_void_p),
-                ("lambda_item", ctypes.POINTER(ctypes.c_double))]
+                ("lambda_item", ctypes.POINTER(ctypes.c_double)), ("z_prev0", ctypes.c_void_p),
+                ("z_prev_out", ctypes.c_void_p), ("k0", ctypes.c_int32)]
 
 
 class _CSolveReport(ctypes.Structure):
@@ -335,12 +336,15 @@ class Plan:
 
     def mbir_solve(self, y, penalty, lam, iters: int, delta: float = 0.0, tv_inner: int = 10,
                    haar_levels: int = 3, power_iters: int = 50, seed: int = 0, x0=None, x_out=None,
-                   objective: bool = False, paper_backward: bool = False, bound=None, stream=None):
+                   objective: bool = False, paper_backward: bool = False, bound=None, stream=None,
+                   z_prev0=None, k0: int = 0, z_prev_out=None):
         """FISTA; returns (z^K, info) with info = {delta, lipschitz, objective (np.ndarray or None)}.
         paper_backward=True takes each gradient with the backward operator of
         eq. (10)-(11) (adjoint_paper) instead of the exact adjoint; bound sets the
         constraint set C = {|x_i| <= bound} of the prox (l1, TV; None: none).
-        lam: one weight, or a sequence of one weight per batch item."""
+        lam: one weight, or a sequence of one weight per batch item.
+        Resume: x0 = z^k0, z_prev0 = z^{k0-1}, k0 = iterations already done
+        (z_prev_out receives z^{K-1} of this solve)."""
         import torch
         g = self.geom
         pen = PENALTIES[penalty] if isinstance(penalty, str) else int(penalty)
@@ -356,7 +360,11 @@ class Plan:
                             SOLVE_PAPER_BACKWARD if paper_backward else 0,
                             int(seed), float(lam), float(delta), 0.0 if bound is None else float(bound),
                             None if x0 is None else _dev(x0, torch.complex64, g.img_shape, "x0").value,
-                            None if lam_item is None else lam_item.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                            None if lam_item is None else lam_item.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            None if z_prev0 is None else _dev(z_prev0, torch.complex64, g.img_shape, "z_prev0").value,
+                            None if z_prev_out is None else _dev(z_prev_out, torch.complex64, g.img_shape,
+                                                                 "z_prev_out").value,
+                            int(k0))
         obj = np.zeros(iters, dtype=np.float64) if objective else None
         rep = _CSolveReport(0.0, 0.0, obj.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if objective else None)
         _check(_lib.oct_mbir_solve(self._h, _dev(y, torch.float32, g.meas_shape, "y"), ctypes.byref(prm),

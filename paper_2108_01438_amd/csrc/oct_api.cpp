@@ -175,6 +175,7 @@ struct oct_plan {
   FftDesc fK{}, fX{}, fY{}, fM{};
   float2 *twK = nullptr, *twX = nullptr, *twY = nullptr;
   float2* twM = nullptr;         // spectral-axis transform (analytic signal; literal chain's D)
+  float2* tv_last = nullptr;     // the TV dual the last solve ended with (p0 or p1), for a resumed solve
   // literal K, Q, D chain (model 1): even-pixel NUFFT tables, the N-point transform, e^{j Omega}
   int model = OCT_MODEL_DIRECT;
   // half-spectrum path (direct model): the forward NUFFT keeps W_h(q) =
@@ -1148,6 +1149,9 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
                           oct_solve_report* rep, void* stream) {
   if (!p || !y || !prm || !x_out) return fail(OCT_E_INVALID, "null argument");
   if (prm->iters < 1) return fail(OCT_E_INVALID, "iters must be >= 1");
+  if (prm->k0 < 0 || prm->k0 > (1 << 24)) return fail(OCT_E_INVALID, "k0 must be in 0..2^24");
+  if (prm->k0 > 0 && !prm->x0) return fail(OCT_E_INVALID, "a resumed solve (k0 > 0) needs x0 = z^k0");
+  if (prm->z_prev0 && !prm->x0) return fail(OCT_E_INVALID, "z_prev0 needs x0");
   if (prm->penalty < 0 || prm->penalty > 3) return fail(OCT_E_INVALID, "unknown penalty");
   if (prm->penalty == OCT_PEN_DTCWT) OCTCHK(check_dtcwt(p, prm->haar_levels));
   if (!(prm->lambda >= 0)) return fail(OCT_E_INVALID, "lambda must be >= 0");
@@ -1169,7 +1173,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
     if (p->B > OCT_MAX_LAMBDA_ITEMS) return fail(OCT_E_UNSUPPORTED, "per-item weights need batch <= 64");
     if (bf < INFINITY) return fail(OCT_E_UNSUPPORTED, "per-item weights with a modulus bound");
     if (rep && rep->objective) return fail(OCT_E_UNSUPPORTED, "per-item weights with an objective report");
-    if (prm->x0) return fail(OCT_E_UNSUPPORTED, "per-item weights with a start point");
+    if (prm->x0 || prm->z_prev_out) return fail(OCT_E_UNSUPPORTED, "per-item weights with a start point or z_prev_out");
     lambda = 0.0;
     for (int64_t b = 0; b < p->B; ++b) {
       const double l = prm->lambda_item[b];
@@ -1196,10 +1200,13 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   }
   const int64_t n = p->n_img();
   // FISTA momenta mu_k = (t_k - 1) / t_{k+1}, t_1 = 1 (FP64)
-  std::vector<double> mu(prm->iters);
+  // FISTA momenta mu_k = (t_k - 1) / t_{k+1}, t_1 = 1 (FP64), continued from
+  // iteration k0 when the solve resumes
+  const int k0 = prm->k0;
+  std::vector<double> mu((size_t)k0 + prm->iters);
   {
     double t = 1.0;
-    for (int k = 0; k < prm->iters; ++k) {
+    for (size_t k = 0; k < mu.size(); ++k) {
       const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
       mu[k] = (t - 1.0) / tn;
       t = tn;
@@ -1209,7 +1216,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   float2* zo = p->zb;   // z^{k-2}
   if (prm->x0) {
     HIPCHK(launch_copy((const float2*)prm->x0, zc, n, s));
-    HIPCHK(launch_copy((const float2*)prm->x0, zo, n, s));
+    HIPCHK(launch_copy((const float2*)(prm->z_prev0 ? prm->z_prev0 : prm->x0), zo, n, s));
   } else {
     HIPCHK(launch_zero(zc, n, s));
     HIPCHK(launch_zero(zo, n, s));
@@ -1218,6 +1225,10 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   const float tau = (float)(lambda * delta);
   float2* pin = nullptr;
   float2* pout = p->p0;
+  if (k0 > 0 && prm->penalty == OCT_PEN_TV && p->tv_last) {   // the dual where the last solve ended
+    pin = p->tv_last;
+    pout = (pin == p->p0) ? p->p1 : p->p0;
+  }
   const bool fused_l1 = (prm->penalty == OCT_PEN_L1) && p->lat_dims == 1;
   if (paper) {
     // set up before any work: fails when n_k does not suit the analytic-signal transform
@@ -1226,8 +1237,8 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   }
   double* res_part = p->partial;
   double* pen_part = p->partial + p->partial_cap;
-  float mu_prev = 0.f;
-  if (fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, 0.f, s));
+  float mu_prev = k0 > 0 ? (float)mu[k0 - 1] : 0.f;
+  if (fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s));
   for (int k = 0; k < prm->iters; ++k) {
     if (!fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s, p->xext));
     OCTCHK(run_cols_fwd(p, s, p->hs && !paper));
@@ -1244,7 +1255,7 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
       a.z = zc;
       a.zo = zo;
       a.mu = mu_prev;
-      a.mu_next = (float)mu[k];
+      a.mu_next = (float)mu[k0 + k];
       a.delta = (float)delta;
       a.tau = tau;
       a.bound = bf;
@@ -1288,10 +1299,12 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
     }
     if (want_obj) HIPCHK(launch_objective(res_part, nres, pen_part, npen, lambda, p->hist + k, s));
     std::swap(zc, zo);
-    mu_prev = (float)mu[k];
+    mu_prev = (float)mu[k0 + k];
   }
+  if (prm->penalty == OCT_PEN_TV) p->tv_last = pin;
   if (per_item) HIPCHK(launch_scale_items(zc, (float2*)x_out, p->Nlat * p->Nz, (int)p->B, z_scale, s));
   else HIPCHK(launch_copy(zc, (float2*)x_out, n, s));
+  if (prm->z_prev_out) HIPCHK(launch_copy(zo, (float2*)prm->z_prev_out, n, s));   // z^{K-1}
   if (rep) {
     rep->delta_used = delta;
     rep->lipschitz_est = Lest;

@@ -187,7 +187,13 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
       [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; },
       [&](int idx, Z2 v) {
         const int l = idx >> lt, t = idx & (T - 1);
-        const float2 x = make_float2(v.a.x + a.mu * (v.a.x - v.b.x), v.a.y + a.mu * (v.a.y - v.b.y));
+        float2 x;
+        {
+          // x = z + mu (z - z_prev) rounded step by step, as the fused l1 update
+          // forms it: a resumed solve then matches an uninterrupted one bitwise
+#pragma clang fp contract(off)
+          x = make_float2(v.a.x + a.mu * (v.a.x - v.b.x), v.a.y + a.mu * (v.a.y - v.b.y));
+        }
         lds[t * rs + l] = t < nr ? x : make_float2(0.f, 0.f);
         if (a.xout && t < nr) a.xout[base + (int64_t)l * lg.es + t] = x;
       });
@@ -377,10 +383,16 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
           const float vi = z.y + a.mu * (z.y - zo.y) - a.delta * g.y;
           const float mag = sqrtf(vr * vr + vi * vi);
           const float sc = mag > a.tau ? fminf(1.f - a.tau / mag, a.bound / mag) : 0.f;
-          const float2 zn = make_float2(vr * sc, vi * sc);
+          float2 zn;
+          {
+            // z^k and the next x from the rounded z^k (no fused multiply-adds across
+            // the rounding): the same bits a resumed solve forms from stored z^k
+#pragma clang fp contract(off)
+            zn = make_float2(vr * sc, vi * sc);
+            xn = make_float2(zn.x + a.mu_next * (zn.x - z.x), zn.y + a.mu_next * (zn.y - z.y));
+          }
           acc += (double)sqrtf(zn.x * zn.x + zn.y * zn.y);
           a.zo[off] = zn;
-          xn = make_float2(zn.x + a.mu_next * (zn.x - z.x), zn.y + a.mu_next * (zn.y - z.y));
         }
         lds[t * rs + l] = xn;
       });

@@ -168,6 +168,35 @@ def test_fista_warm_start_resume():
     assert rel(to_host(z), zo) <= SOLVE_TOL
 
 
+@pytest.mark.parametrize("pen,kw,masked", [
+    ("l1", dict(n_depth=128, n_x=48, n_k=128), False),                 # fused lateral l1 path
+    ("tv", dict(n_depth=128, n_x=48, n_k=128), True),                  # tiled TV, dual carried over
+    ("haar", dict(n_depth=64, n_x=16, n_y=16, lateral_dims=2, n_k=64), False),
+])
+def test_fista_exact_resume(pen, kw, masked):
+    """Resume from the state (z^k, z^{k-1}, k): 20 iterations, then 20 more
+    from x0 = z^20, z_prev0 = z^19, k0 = 20, equal one solve of 40 bitwise."""
+    import torch
+    import paper_2108_01438_amd as P
+    flush(f"[fista] exact resume, {pen}")
+    og, pg = both_geoms(**kw)
+    rng = np.random.default_rng(14)
+    mask = synth.mask_random_exact(rng, (og.n_y if og.lateral_dims == 2 else 1, og.n_x), og.n_k, og.n_k // 2) \
+        if masked else None
+    _, y = _problem(og, rng, 12, mask)
+    plan = P.Plan(pg, mask)
+    yd = to_dev(y.astype(np.float32))
+    lam = (0.005 if pen == "tv" else 0.01) * O.lambda_max(y, og, mask)
+    delta = O.step_size(O.lipschitz(og, mask, iters=20))
+    z40, _ = plan.mbir_solve(yd, pen, lam, 40, delta=delta)
+    zp = torch.empty_like(z40)
+    z20, _ = plan.mbir_solve(yd, pen, lam, 20, delta=delta, z_prev_out=zp)
+    z40r, _ = plan.mbir_solve(yd, pen, lam, 20, delta=delta, x0=z20, z_prev0=zp, k0=20)
+    assert torch.equal(z40r, z40)
+    z19, _ = plan.mbir_solve(yd, pen, lam, 19, delta=delta)
+    assert torch.equal(zp, z19)
+
+
 def test_solve_replays_bitwise_from_a_graph():
     """A whole solve (TV, batch of two) captured in a graph replays bitwise
     equal to the eager solve, with the caller's own work (zeroing the output)
