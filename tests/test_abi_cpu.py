@@ -90,3 +90,44 @@ def test_dtcwt_filters_designed_by_the_library_match_the_oracle():
         np.testing.assert_allclose(got, ref[which], atol=1e-7)
     with pytest.raises(P.OctError):
         P.dtcwt_filter(4)
+
+
+def _shift_orthonormal(h, tol):
+    for k in range(0, len(h) // 2):
+        s = float(np.dot(h[: len(h) - 2 * k], h[2 * k:]))
+        assert abs(s - (1.0 if k == 0 else 0.0)) <= tol, (k, s)
+
+
+def _highpass_moments(h, K, tol):
+    n = np.arange(len(h))
+    for p in range(K):
+        assert abs(float(np.sum((-1.0) ** n * n ** p * h))) <= tol * max(1, len(h) ** p), p
+
+
+def test_dtcwt_filters_of_the_library_satisfy_their_design_properties():
+    """The DT-CWT filters the library designs on the host, checked against the
+    mathematics of the design rather than against the oracle's own design:
+    lowpass sum sqrt(2), orthonormal to even shifts, K = 3 vanishing moments;
+    the first level is the published 6-tap Daubechies filter (tree b one sample
+    later); the later-level pair has equal magnitude responses and tree b lags
+    tree a by half a sample at low frequencies (Selesnick's common-factor
+    design with a maximally flat delay)."""
+    import paper_2108_01438_amd as P
+    a1, b1, a2, b2 = (P.dtcwt_filter(w) for w in range(4))
+    for h in (a1, b1, a2, b2):
+        assert abs(h.sum() - np.sqrt(2.0)) <= 1e-6
+        _shift_orthonormal(h, 1e-6)
+        _highpass_moments(h, 3, 1e-5)
+    d6 = np.array([0.3326705529500825, 0.8068915093110924, 0.4598775021184914,
+                   -0.1350110200102546, -0.0854412738820267, 0.0352262918857095])   # Daubechies 1988
+    core = a1[np.abs(a1) > 1e-9]
+    assert min(np.max(np.abs(core - d6)), np.max(np.abs(core[::-1] - d6))) <= 2e-6
+    assert np.allclose(b1[1:], a1[:-1], atol=0) and b1[0] == 0.0
+    w = np.linspace(0.0, np.pi, 257)
+    E = np.exp(-1j * np.outer(w, np.arange(len(a2))))
+    Ha, Hb = E @ a2, E @ b2
+    assert np.max(np.abs(np.abs(Ha) - np.abs(Hb))) <= 1e-6
+    low = w <= np.pi / 2
+    dphi = np.unwrap(np.angle(Hb[low])) - np.unwrap(np.angle(Ha[low]))
+    dphi -= dphi[0]
+    assert np.max(np.abs(dphi + 0.5 * w[low])) <= 0.02 or np.max(np.abs(dphi - 0.5 * w[low])) <= 0.02
