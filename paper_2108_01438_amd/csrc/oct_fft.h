@@ -83,13 +83,17 @@ template <bool INV> struct Dft<4, INV> {
 
 template <bool INV> struct Dft<8, INV> {
   static __device__ __forceinline__ void run(float2* a) {
-    const float h = 0.70710678118654752440f;
     float2 b[4], c[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       b[k] = cadd(a[k], a[k + 4]);
       c[k] = csub(a[k], a[k + 4]);
     }
+    finish(b, c, a);
+  }
+  // the rest of the DFT from b_k = a_k + a_{k+4} and c_k = a_k - a_{k+4}
+  static __device__ __forceinline__ void finish(float2* b, float2* c, float2* a) {
+    const float h = 0.70710678118654752440f;
     // c_k *= w8^k, w8 = e^{-+ i pi / 4}
     {
       float2 t = c[1];
@@ -384,14 +388,21 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, int nrows, int rowstri
   __syncthreads();
 }
 
+// stages S..E-1 of the compile-time plan of length N
+template <int N, int S, int E, int MAXB, bool INV>
+__device__ __forceinline__ void fft_ct_stage_range(float2* buf, int nrows, int rowstride, const FftDesc& d,
+                                                   const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr CtPlan P = ct_plan(N);
+  if constexpr (S < E) {
+    fft_stage_ct<P.r[S], N, ct_ns_before(P, S), MAXB, INV>(buf, nrows, rowstride, tw + d.tw_off[S], tid, nthr);
+    fft_ct_stage_range<N, S + 1, E, MAXB, INV>(buf, nrows, rowstride, d, tw, tid, nthr);
+  }
+}
+
 template <int N, int S, int MAXB, bool INV>
 __device__ __forceinline__ void fft_ct_stages(float2* buf, int nrows, int rowstride, const FftDesc& d,
                                               const float2* __restrict__ tw, int tid, int nthr) {
-  constexpr CtPlan P = ct_plan(N);
-  if constexpr (S < P.ns) {
-    fft_stage_ct<P.r[S], N, ct_ns_before(P, S), MAXB, INV>(buf, nrows, rowstride, tw + d.tw_off[S], tid, nthr);
-    fft_ct_stages<N, S + 1, MAXB, INV>(buf, nrows, rowstride, d, tw, tid, nthr);
-  }
+  fft_ct_stage_range<N, S, ct_plan(N).ns, MAXB, INV>(buf, nrows, rowstride, d, tw, tid, nthr);
 }
 
 // fft_rows with a compile-time path for each length in SIZES (the generic

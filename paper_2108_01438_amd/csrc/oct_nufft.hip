@@ -136,6 +136,167 @@ __device__ __forceinline__ float2 filter_h(const NufftArgs& a, float2 ph, float 
   return h;
 }
 
+// ---------------------------------------------------------------------------
+// Half-band edge stages (oversampling 2: K = 2 Nz, n_c = Nz / 2).  The
+// centred, zero-padded depth column occupies grid cells [0, K/4) (depth
+// n = n_c .. Nz-1) and [3K/4, K) (n = 0 .. n_c-1).  The first Stockham stage
+// of a K-point transform with radix 8 reads butterfly j's inputs from cells
+// j + r K/8: only r = 0, 1, 6, 7 are nonzero, at depths j + K/4, j + 3K/8, j
+// and j + K/8.  The forward grid transform therefore takes its first stage
+// straight from global memory, deapodised, with no zero fill and no LDS
+// round trip; symmetrically the adjoint's last stage (radix R = 8 or 4,
+// outputs k + r K/R) keeps only the outputs r < R/4 and r >= 3R/4, the cells
+// that hold depths, and stores them deapodised to global memory.
+// ---------------------------------------------------------------------------
+template <int N>
+struct HalfBand {
+  static constexpr CtPlan P = ct_plan(N);
+  static constexpr int RL = P.r[P.ns - 1];
+  static constexpr bool ok = P.ns >= 3 && P.r[0] == 8 && (RL == 8 || RL == 4) && N / RL != 8;
+};
+
+// nonzero first-stage inputs a_0, a_1, a_6, a_7 of a radix-8 butterfly
+// (a_2..a_5 = 0): b_k = a_k + a_{k+4} and c_k = a_k - a_{k+4} need no adds
+template <bool INV>
+__device__ __forceinline__ void dft8_edges(float2 a0, float2 a1, float2 a6, float2 a7, float2* out) {
+  float2 b[4] = {a0, a1, a6, a7};
+  float2 c[4] = {a0, a1, make_float2(-a6.x, -a6.y), make_float2(-a7.x, -a7.y)};
+  Dft<8, INV>::finish(b, c, out);
+}
+
+// Forward K-point transforms of nrows (1 or 2) deapodised, centred depth
+// columns src0 (row 0) and src1 (row 1) into LDS rows buf + row rowstride.
+template <int N, int MAXB>
+__device__ __forceinline__ void fwd_grid_fft_half(float2* buf, int nrows, int rowstride,
+                                                  const float2* __restrict__ src0, const float2* __restrict__ src1,
+                                                  const float* __restrict__ deap, const FftDesc& d,
+                                                  const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr int nb = N / 8;
+  const int total = nrows * nb;
+  for (int i0 = tid; i0 < total; i0 += MAXB * nthr) {
+    float2 x[MAXB][4];
+    float dd[MAXB][4];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int item = min(i0 + b * nthr, total - 1);
+      const int row = item >= nb ? 1 : 0;
+      const int j = item - row * nb;
+      const float2* __restrict__ sp = row ? src1 : src0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        x[b][q] = sp[j + q * nb];
+        dd[b][q] = deap[j + q * nb];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int item = i0 + b * nthr;
+      if (item < total) {
+        const int row = item >= nb ? 1 : 0;
+        const int j = item - row * nb;
+        float2 v[8];
+        // depths j, j + nb, j + 2nb, j + 3nb sit at r = 6, 7, 0, 1
+        dft8_edges<false>(cscale(x[b][2], dd[b][2]), cscale(x[b][3], dd[b][3]), cscale(x[b][0], dd[b][0]),
+                          cscale(x[b][1], dd[b][1]), v);
+        float2* dst = buf + row * rowstride;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) dst[fft_swz(j * 8 + r)] = v[r];   // the layout a first radix-8 stage leaves
+      }
+    }
+  }
+  __syncthreads();
+  fft_ct_stage_range<N, 1, HalfBand<N>::P.ns, MAXB, false>(buf, nrows, rowstride, d, tw, tid, nthr);
+}
+
+// Inverse K-point transforms of the LDS rows, stored deapodised as depth
+// columns dst0 (row 0) and dst1 (row 1; nullptr: not stored).
+template <int N, int MAXB>
+__device__ __forceinline__ void adj_grid_ifft_half(float2* buf, int nrows, int rowstride, float2* __restrict__ dst0,
+                                                   float2* __restrict__ dst1, const float* __restrict__ deap, int nc,
+                                                   const FftDesc& d, const float2* __restrict__ tw, int tid,
+                                                   int nthr) {
+  using HB = HalfBand<N>;
+  constexpr int S = HB::P.ns - 1;
+  constexpr int R = HB::RL;
+  constexpr int nb = N / R;   // butterflies per row = the stride of the outputs
+  constexpr int NQ = fft_tw_pad(R) / 2;
+  constexpr int RO = R / 4;   // outputs r < RO and r >= R - RO hold depths
+  fft_ct_stage_range<N, 0, S, MAXB, true>(buf, nrows, rowstride, d, tw, tid, nthr);
+  const float4* __restrict__ tws = reinterpret_cast<const float4*>(tw + d.tw_off[S]);
+  const int total = nrows * nb;
+  for (int i0 = tid; i0 < total; i0 += MAXB * nthr) {
+    float2 v[MAXB][R];
+    float4 wq[MAXB][NQ];
+    float dd[MAXB][2 * RO];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int item = min(i0 + b * nthr, total - 1);
+      const int row = item >= nb ? 1 : 0;
+      const int k = item - row * nb;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) wq[b][q] = tws[k * NQ + q];
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        dd[b][r] = deap[k + r * nb + nc];
+        dd[b][RO + r] = deap[k + r * nb];
+      }
+      const float2* src = buf + row * rowstride + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = src[r * nb];
+    }
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int item = i0 + b * nthr;
+      if (item < total) {
+        const int row = item >= nb ? 1 : 0;
+        const int k = item - row * nb;
+        float2* __restrict__ dst = row ? dst1 : dst0;
+        if (dst) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const float4 q = wq[b][(r - 1) >> 1];
+            const float2 w = ((r - 1) & 1) ? make_float2(q.z, -q.w) : make_float2(q.x, -q.y);
+            v[b][r] = cmul(v[b][r], w);
+          }
+          Dft<R, true>::run(v[b]);
+          // cell k + r nb: depth k + r nb + n_c for r < RO, k + (r - R + RO) nb for r >= R - RO
+#pragma unroll
+          for (int r = 0; r < RO; ++r) {
+            dst[k + r * nb + nc] = cscale(v[b][r], dd[b][r]);
+            dst[k + r * nb] = cscale(v[b][R - RO + r], dd[b][RO + r]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// the half-band forward transform for a compile-time K in SIZES, if there is one
+template <int MAXB, int... SIZES>
+__device__ __forceinline__ bool fwd_grid_fft_half_sized(float2* buf, int nrows, int rowstride, const float2* src0,
+                                                        const float2* src1, const float* deap, const FftDesc& d,
+                                                        const float2* tw, int tid, int nthr) {
+  bool done = false;
+  ((!done && d.n == SIZES && HalfBand<SIZES>::ok
+        ? (fwd_grid_fft_half<SIZES, MAXB>(buf, nrows, rowstride, src0, src1, deap, d, tw, tid, nthr), done = true)
+        : false),
+   ...);
+  return done;
+}
+
+template <int MAXB, int... SIZES>
+__device__ __forceinline__ bool adj_grid_ifft_half_sized(float2* buf, int nrows, int rowstride, float2* dst0,
+                                                         float2* dst1, const float* deap, int nc, const FftDesc& d,
+                                                         const float2* tw, int tid, int nthr) {
+  bool done = false;
+  ((!done && d.n == SIZES && HalfBand<SIZES>::ok
+        ? (adj_grid_ifft_half<SIZES, MAXB>(buf, nrows, rowstride, dst0, dst1, deap, nc, d, tw, tid, nthr),
+           done = true)
+        : false),
+   ...);
+  return done;
+}
+
 // per-element loads gathered for batched_for (grid loads and stores; the
 // sample loops are not batched: their bodies are long, other waves cover the
 // table loads, and batching them would cost registers)
@@ -168,16 +329,21 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
   const float2* __restrict__ src = X1 + (int64_t)col * Nz;
   const float2* __restrict__ twl = a.twK;
 
-  // n' = n - n_c placed at n' mod K; cells [Nz - nc, K - nc) stay zero.
-  for (int i = tid; i < K - Nz; i += nthr) grid[Nz - nc + i] = make_float2(0.f, 0.f);
-  batched_for(Nz, tid, nthr, [&](int n) { return VD{src[n], a.deap[n]}; },
-              [&](int n, VD v) {
-                int idx = n - nc;
-                if (idx < 0) idx += K;
-                grid[idx] = cscale(v.v, v.d);
-              });
-  __syncthreads();
-  fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(grid, 1, K, a.fK, twl, tid, nthr);
+  const bool half = K == 2 * Nz && 2 * nc == Nz &&
+                    fwd_grid_fft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(grid, 1, K, src, src, a.deap, a.fK,
+                                                                                twl, tid, nthr);
+  if (!half) {
+    // n' = n - n_c placed at n' mod K; cells [Nz - nc, K - nc) stay zero.
+    for (int i = tid; i < K - Nz; i += nthr) grid[Nz - nc + i] = make_float2(0.f, 0.f);
+    batched_for(Nz, tid, nthr, [&](int n) { return VD{src[n], a.deap[n]}; },
+                [&](int n, VD v) {
+                  int idx = n - nc;
+                  if (idx < 0) idx += K;
+                  grid[idx] = cscale(v.v, v.d);
+                });
+    __syncthreads();
+    fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(grid, 1, K, a.fK, twl, tid, nthr);
+  }
   if (tid < 2 * KPAD) {   // cells -KPAD..-1 and K..K+KPAD-1 (K >= 2J >= KPAD)
     const int c = tid < KPAD ? tid - KPAD : K + tid - KPAD;
     grid[c] = grid[tid < KPAD ? c + K : c - K];
@@ -355,8 +521,12 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
   }
   __syncthreads();
 
-  fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(grid, 1, K, a.fK, twl, tid, nthr);
   float2* __restrict__ dst = X + (int64_t)col * Nz;
+  if (K == 2 * Nz && 2 * nc == Nz &&
+      adj_grid_ifft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(grid, 1, K, dst, nullptr, a.deap, nc, a.fK, twl,
+                                                                   tid, nthr))
+    return;
+  fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(grid, 1, K, a.fK, twl, tid, nthr);
   batched_for(Nz, tid, nthr, [&](int n) { return a.deap[n]; }, [&](int n, float d) {
     int idx = n - nc;
     if (idx < 0) idx += K;
@@ -389,20 +559,25 @@ __global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const
   const float2* __restrict__ s0 = X1 + ((int64_t)b * a.Nlat + pr.x) * Nz;
   const float2* __restrict__ s1 = X1 + ((int64_t)b * a.Nlat + pr.y) * Nz;
 
-  // n' = n - n_c placed at n' mod K; cells [Nz - nc, K - nc) stay zero
-  for (int i = tid; i < K - Nz; i += nthr) {
-    g0[Nz - nc + i] = make_float2(0.f, 0.f);
-    g1[Nz - nc + i] = make_float2(0.f, 0.f);
+  const bool half = K == 2 * Nz && 2 * nc == Nz &&
+                    fwd_grid_fft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(g0, 2, rs, s0, s1, a.deap, a.fK,
+                                                                                a.twK, tid, nthr);
+  if (!half) {
+    // n' = n - n_c placed at n' mod K; cells [Nz - nc, K - nc) stay zero
+    for (int i = tid; i < K - Nz; i += nthr) {
+      g0[Nz - nc + i] = make_float2(0.f, 0.f);
+      g1[Nz - nc + i] = make_float2(0.f, 0.f);
+    }
+    batched_for(Nz, tid, nthr, [&](int n) { return VD2{s0[n], s1[n], a.deap[n]}; },
+                [&](int n, VD2 v) {
+                  int idx = n - nc;
+                  if (idx < 0) idx += K;
+                  g0[idx] = cscale(v.a, v.d);
+                  g1[idx] = cscale(v.b, v.d);
+                });
+    __syncthreads();
+    fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(g0, 2, rs, a.fK, a.twK, tid, nthr);
   }
-  batched_for(Nz, tid, nthr, [&](int n) { return VD2{s0[n], s1[n], a.deap[n]}; },
-              [&](int n, VD2 v) {
-                int idx = n - nc;
-                if (idx < 0) idx += K;
-                g0[idx] = cscale(v.a, v.d);
-                g1[idx] = cscale(v.b, v.d);
-              });
-  __syncthreads();
-  fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(g0, 2, rs, a.fK, a.twK, tid, nthr);
   if (tid < 4 * KPAD) {   // wrapped copies, cells -KPAD..-1 and K..K+KPAD-1 of both rows
     float2* g = tid < 2 * KPAD ? g0 : g1;
     const int t = tid & (2 * KPAD - 1);
@@ -687,10 +862,14 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_pair_kernel(Nufft
     adj_pair_gather<J>(a, kc, q2, bm, xm, us0, us1, first, grid, mf, umin, umax, span, nph, tid, nthr);
   }
 
-  fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(grid, 2, K, a.fK, a.twK, tid, nthr);
   float2* __restrict__ d0 = X + ((int64_t)b * a.Nlat + pr.x) * Nz;
   float2* __restrict__ d1 = X + ((int64_t)b * a.Nlat + pr.y) * Nz;
   const bool two = pr.y != pr.x;
+  if (K == 2 * Nz && 2 * nc == Nz &&
+      adj_grid_ifft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(grid, 2, K, d0, two ? d1 : nullptr, a.deap, nc,
+                                                                   a.fK, a.twK, tid, nthr))
+    return;
+  fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(grid, 2, K, a.fK, a.twK, tid, nthr);
   batched_for(Nz, tid, nthr, [&](int n) { return a.deap[n]; }, [&](int n, float d) {
     int idx = n - nc;
     if (idx < 0) idx += K;
