@@ -178,9 +178,13 @@ def request_footprint(P, req: Request) -> int:
 
 class HipExecutor:
     """Runs requests with liboct: one plan per in-flight request (pooled per
-    geometry and mask), one stream per slot, device buffers for y and the result."""
+    geometry and mask), one stream and one launching thread per slot, device
+    buffers for y and the result.  A solve issues a thousand or more kernel
+    launches; they go out from the slot's own thread (ctypes releases the GIL
+    during the call), so the scheduler thread never waits on a launch queue."""
 
     def __init__(self, slots: int = 8):
+        import concurrent.futures as cf
         import torch
         import paper_2108_01438_amd as P
         self.P = P
@@ -191,6 +195,8 @@ class HipExecutor:
         self.lipschitz = {}                      # key -> L (power iteration, cached)
         self.plan_bytes = {}
         self._cached = 0                         # bytes held by idle plans
+        self._lock = threading.Lock()            # pool, streams and caches
+        self._workers = cf.ThreadPoolExecutor(max_workers=slots, thread_name_prefix="oct-slot")
 
     @staticmethod
     def key(req: Request):
@@ -202,49 +208,59 @@ class HipExecutor:
         return request_footprint(self.P, req)
 
     def cached_bytes(self) -> int:
-        return self._cached
+        with self._lock:
+            return self._cached
 
     def _plan(self, req: Request):
         k = self.key(req)
-        lst = self.idle.get(k)
-        if lst:
-            plan = lst.pop()
-            if not lst:
-                del self.idle[k]
-            self._cached -= self.plan_bytes[id(plan)]
-            return plan
-        plan = self.P.Plan(req.geom, req.mask)
-        self.plan_bytes[id(plan)] = plan_footprint(self.P, req.geom)
+        with self._lock:
+            lst = self.idle.get(k)
+            if lst:
+                plan = lst.pop()
+                if not lst:
+                    del self.idle[k]
+                self._cached -= self.plan_bytes[id(plan)]
+                return plan
+        plan = self.P.Plan(req.geom, req.mask)   # outside the lock: host tables and uploads
+        with self._lock:
+            self.plan_bytes[id(plan)] = plan_footprint(self.P, req.geom)
         return plan
 
     def evict_idle(self, need: int) -> int:
         """Free idle plans, least recently used first, until `need` bytes are free."""
         freed = 0
-        while freed < need and self.idle:
-            k, lst = next(iter(self.idle.items()))
-            plan = lst.pop()
-            if not lst:
-                del self.idle[k]
-            b = self.plan_bytes.pop(id(plan), 0)
-            self._cached -= b
+        while freed < need:
+            with self._lock:
+                if not self.idle:
+                    break
+                k, lst = next(iter(self.idle.items()))
+                plan = lst.pop()
+                if not lst:
+                    del self.idle[k]
+                b = self.plan_bytes.pop(id(plan), 0)
+                self._cached -= b
             freed += b
             plan.release()   # idle: its last solve's event has completed; no device-wide wait
         return freed
 
-    def start(self, req: Request):
+    def _run(self, req: Request, si: int):
+        """The slot thread: plan, upload, solve, download, completion event."""
         torch = self.torch
-        plan = self._plan(req)
         k = self.key(req)
-        si = self.free_streams.pop()
         s = self.streams[si]
+        plan = self._plan(req)
         try:
             if req.delta > 0:
                 delta = req.delta
             else:
-                if k not in self.lipschitz:
+                with self._lock:
+                    L = self.lipschitz.get(k)
+                if L is None:
                     with torch.cuda.stream(s):
-                        self.lipschitz[k] = plan.lipschitz(50, stream=s)
-                delta = 1.0 / (1.05 * self.lipschitz[k])
+                        L = plan.lipschitz(50, stream=s)
+                    with self._lock:
+                        self.lipschitz[k] = L
+                delta = 1.0 / (1.05 * L)
             with torch.cuda.stream(s):
                 y = torch.from_numpy(np.ascontiguousarray(req.y, dtype=np.float32)).pin_memory().to(
                     "cuda", non_blocking=True)
@@ -255,33 +271,49 @@ class HipExecutor:
                 ev = torch.cuda.Event()
                 ev.record(s)
         except Exception:
-            self.free_streams.append(si)
             self._release(k, plan)
             raise
-        return {"ev": ev, "host": host, "keep": (y, z), "plan": plan, "key": k, "stream": si}
+        return {"ev": ev, "host": host, "keep": (y, z), "plan": plan, "key": k}
+
+    def start(self, req: Request):
+        with self._lock:
+            si = self.free_streams.pop()
+        return {"fut": self._workers.submit(self._run, req, si), "stream": si}
 
     def _release(self, k, plan):
-        self.idle.setdefault(k, []).append(plan)
-        self.idle.move_to_end(k)
-        self._cached += self.plan_bytes[id(plan)]
+        with self._lock:
+            self.idle.setdefault(k, []).append(plan)
+            self.idle.move_to_end(k)
+            self._cached += self.plan_bytes[id(plan)]
 
     def done(self, h) -> bool:
-        return h["ev"].query()
+        f = h["fut"]
+        if not f.done():
+            return False
+        if f.exception() is not None:
+            return True
+        return f.result()["ev"].query()
 
     def result(self, h):
-        h["ev"].synchronize()
-        out = h["host"].numpy().copy()
-        self.free_streams.append(h["stream"])
-        self._release(h["key"], h["plan"])
-        h["keep"] = None
+        try:
+            r = h["fut"].result()
+        finally:
+            with self._lock:
+                self.free_streams.append(h["stream"])
+        r["ev"].synchronize()
+        out = r["host"].numpy().copy()
+        self._release(r["key"], r["plan"])
+        r["keep"] = None
         return out
 
     def shutdown(self):
-        for lst in self.idle.values():
-            for p in lst:
-                p.release()
-        self.idle.clear()
-        self._cached = 0
+        self._workers.shutdown(wait=True)
+        with self._lock:
+            plans = [p for lst in self.idle.values() for p in lst]
+            self.idle.clear()
+            self._cached = 0
+        for p in plans:
+            p.release()
 
 
 def run_sequential(executor, reqs):
