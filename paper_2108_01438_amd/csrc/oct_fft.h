@@ -43,6 +43,14 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) {
 // second stage, which reads through the same map, sees the same data.
 __device__ __forceinline__ int fft_swz(int i) { return i ^ ((i >> 3) & 7); }
 
+// The same for the second radix-8 stage (sub-transform size 8) when a stage
+// follows it: butterfly j writes output r to 64 (j div 8) + (j mod 8) + 8 r,
+// so for one r the 64 lanes of a wave cover only eight bank pairs.  Flipping
+// bit 3 of the index with bit 6 gives each group of 16 lanes 16 distinct bank
+// pairs; the map permutes inside aligned groups of 16 and is its own inverse,
+// and the next stage reads through it.
+__device__ __forceinline__ int fft_swz2(int i) { return i ^ ((i >> 3) & 8); }
+
 // Element loop with batched loads: every thread first issues the loads of U
 // elements (indices clamped to a valid element, so each load is in bounds
 // and none waits on another), then consumes them in order.  A plain loop
@@ -324,7 +332,7 @@ constexpr int ct_ns_before(const CtPlan& p, int s) {
   return v;
 }
 
-template <int R, int N, int NS, int MAXB, bool INV>
+template <int R, int N, int NS, int MAXB, bool INV, bool SWZ2_IN = false, bool SWZ2_OUT = false>
 __device__ __forceinline__ void fft_stage_ct(float2* buf, int nrows, int rowstride,
                                              const float2* __restrict__ tw, int tid, int nthr) {
   constexpr int NQ = fft_tw_pad(R) / 2;
@@ -350,6 +358,10 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, int nrows, int rowstri
         const float2* src = buf + base[b];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[b][r] = src[fft_swz(j + r * nb)];
+      } else if (SWZ2_IN) {   // after a swizzled second stage
+        const float2* src = buf + base[b];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b][r] = src[fft_swz2(j + r * nb)];
       } else {
         const float2* src = buf + base[b] + j;
 #pragma unroll
@@ -378,6 +390,11 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, int nrows, int rowstri
         float2* dst = buf + base[b];
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[fft_swz(j * R + r)] = v[b][r];
+      } else if (SWZ2_OUT) {
+        float2* dst = buf + base[b];
+        const int o = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[fft_swz2(o + r * NS)] = v[b][r];
       } else {
         float2* dst = buf + base[b] + (j - k) * R + k;
 #pragma unroll
@@ -388,13 +405,23 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, int nrows, int rowstri
   __syncthreads();
 }
 
+// Stage S of the plan of length N writes through fft_swz2 when it is a
+// radix-8 stage of sub-transform size 8 and another stage follows; stage S
+// reads through it when stage S - 1 did.
+template <int N, int S>
+constexpr bool ct_swz2_out() {
+  constexpr CtPlan P = ct_plan(N);
+  return S >= 0 && S + 1 < P.ns && P.r[S] == 8 && ct_ns_before(P, S) == 8;
+}
+
 // stages S..E-1 of the compile-time plan of length N
 template <int N, int S, int E, int MAXB, bool INV>
 __device__ __forceinline__ void fft_ct_stage_range(float2* buf, int nrows, int rowstride, const FftDesc& d,
                                                    const float2* __restrict__ tw, int tid, int nthr) {
   constexpr CtPlan P = ct_plan(N);
   if constexpr (S < E) {
-    fft_stage_ct<P.r[S], N, ct_ns_before(P, S), MAXB, INV>(buf, nrows, rowstride, tw + d.tw_off[S], tid, nthr);
+    fft_stage_ct<P.r[S], N, ct_ns_before(P, S), MAXB, INV, ct_swz2_out<N, S - 1>(), ct_swz2_out<N, S>()>(
+        buf, nrows, rowstride, tw + d.tw_off[S], tid, nthr);
     fft_ct_stage_range<N, S + 1, E, MAXB, INV>(buf, nrows, rowstride, d, tw, tid, nthr);
   }
 }

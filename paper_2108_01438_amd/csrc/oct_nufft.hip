@@ -217,6 +217,7 @@ __device__ __forceinline__ void adj_grid_ifft_half(float2* buf, int nrows, int r
                                                    int nthr) {
   using HB = HalfBand<N>;
   constexpr int S = HB::P.ns - 1;
+  static_assert(!ct_swz2_out<N, S - 1>(), "the last stage reads the natural layout");
   constexpr int R = HB::RL;
   constexpr int nb = N / R;   // butterflies per row = the stride of the outputs
   constexpr int NQ = fft_tw_pad(R) / 2;
