@@ -13,6 +13,8 @@
 //     the next iteration's forward lateral transform.
 #include "oct_fft.h"
 
+#include <type_traits>
+
 namespace {
 
 __device__ __forceinline__ bool mask_bit(const uint32_t* __restrict__ mask, int words, int lat, int m) {
@@ -74,14 +76,36 @@ struct FM {
 };
 struct YM {
   float ya, yb;
-  uint32_t ma, mb;
+  uint32_t m;   // the mask word of both rows
 };
 
 // float2 slots of the tile in LDS, rounded up to keep the twiddle rows that
 // follow it 16-byte aligned
 __host__ __device__ inline int lat_tile_f2(int T, int rs) { return (T * rs + 1) & ~1; }
 
-template <int MODE, bool ONE>
+// Offset of a tile element from the tile's origin.  OFF32 (the tile spans
+// less than 4 GiB): a 32-bit byte offset of the float2 element (a float
+// array takes half of it), made opaque at each access so that the access
+// takes the uniform origin from scalar registers plus this one 32-bit
+// register; otherwise a 64-bit element offset.
+template <bool OFF32> struct LatOff;
+template <> struct LatOff<true> {
+  using type = uint32_t;
+  __device__ static type of(int64_t elems) { return (uint32_t)(elems * 8); }
+  template <typename T> __device__ static T* at(T* origin, type o) {
+    uint32_t b = sizeof(T) == sizeof(float2) ? o : (o >> 1);
+    asm volatile("" : "+v"(b));
+    using C = std::conditional_t<std::is_const<T>::value, const char, char>;
+    return reinterpret_cast<T*>(reinterpret_cast<C*>(origin) + b);
+  }
+};
+template <> struct LatOff<false> {
+  using type = int64_t;
+  __device__ static type of(int64_t elems) { return elems; }
+  template <typename T> __device__ static T* at(T* origin, type o) { return origin + o; }
+};
+
+template <int MODE, bool ONE, bool OFF32>
 __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   extern __shared__ float2 lds[];
   __shared__ double red[16];
@@ -122,15 +146,74 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   const bool pair = REAL_PAIRS && T >= 2;
   const int H = T >> 1;
   const int nrow_t = pair ? H : T;   // rows that go through the transforms
-  // global offset of tile element idx (row t = idx mod T, lateral l = idx / T); rows past the
-  // image (ragged last tile) are clamped to a valid row and masked by the caller
-  auto goff = [&](int idx) -> int64_t {
-    const int l = idx >> lt, t = min(idx & (T - 1), nr - 1);
-    return base + (int64_t)l * lg.es + t;
+  // Element mapping.  nthr is a multiple of T, so thread tid owns one tile
+  // row, t_own = tid mod T, and the laterals l = l_own + u LS (u = 0, 1, ...):
+  // its row, clamped row and LDS row are fixed, and the offset of its next
+  // element is the last one plus a uniform step.  Rows past the image
+  // (ragged last tile) load a clamped valid row and store nothing.  The
+  // real-pair loops run over rows p < H the same way (p_own = tid mod H).
+  const int t_own = tid & (T - 1);
+  const int l_own = tid >> lt;
+  const int LS = nthr >> lt;
+  const int t_cl = min(t_own, nr - 1);
+  const bool t_ok = t_own < nr;
+  const int log2H = lt > 0 ? lt - 1 : 0;
+  const int p_own = tid & (H > 0 ? H - 1 : 0);
+  const int l_ownH = tid >> log2H;
+  const int LSH = nthr >> log2H;
+  // per-array tile origins (uniform: scalar registers)
+  auto org = [](auto* p, int64_t b) { return p ? p + b : p; };
+  const float2* __restrict__ src_o = org(a.src, base);
+  const float2* __restrict__ srch_o = org(a.src, hbase);
+  const float* __restrict__ srcf_o = org(a.srcf, base);
+  const float2* __restrict__ z_o = org(a.z, base);
+  const float2* __restrict__ zo_o = org(a.zo, base);
+  float2* __restrict__ zow_o = org(a.zo, base);
+  float2* __restrict__ xout_o = org(a.xout, base);
+  float2* __restrict__ dst_o = org(a.dst, base);
+  float2* __restrict__ dsth_o = org(a.dst, hbase);
+  float* __restrict__ dstf_o = org(a.dstf, base);
+  const float* __restrict__ y_o = org(a.y, base);
+  // mask words of this tile's rows (T <= 32 rows from a multiple of T: one word)
+  const uint32_t* __restrict__ mrow = a.mask ? a.mask + (int64_t)latb * a.mask_words + (r0 >> 5) : nullptr;
+  auto mword = [&](int mo) -> uint32_t { return mrow ? mrow[mo] : ~0u; };
+  auto mbit = [&](uint32_t m, int t) -> bool { return (m >> ((r0 + t) & 31)) & 1u; };
+  using Off = typename LatOff<OFF32>::type;
+
+  // use(l, o, v) for the thread's laterals l = l_start + u lstep < Lend, with
+  // o the offset of element (l, row) from the tile origin and
+  // v = load(l, o, mo), mo = l mask_words; U loads in flight before the first use
+  auto row_for = [&](int l_start, int lstep, int Lend, int row, auto load, auto use) __attribute__((always_inline)) {
+    constexpr int U = 8;
+    const Off os = LatOff<OFF32>::of((int64_t)lstep * lg.es);
+    const int ms = lstep * a.mask_words;
+    Off o = LatOff<OFF32>::of((int64_t)l_start * lg.es + row);
+    int mo = l_start * a.mask_words;
+    for (int lb = l_start; lb < Lend; lb += U * lstep, o += U * os, mo += U * ms) {
+      using R = decltype(load(0, o, 0));
+      R r[U];
+      if (lb + (U - 1) * lstep < Lend) {   // the whole chunk (the usual case: no per-element branches)
+#pragma unroll
+        for (int u = 0; u < U; ++u) r[u] = load(lb + u * lstep, o + u * os, mo + u * ms);
+#pragma unroll
+        for (int u = 0; u < U; ++u) use(lb + u * lstep, o + u * os, r[u]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (lb + u * lstep < Lend) r[u] = load(lb + u * lstep, o + u * os, mo + u * ms);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (lb + u * lstep < Lend) use(lb + u * lstep, o + u * os, r[u]);
+      }
+    }
   };
-  auto mword = [&](int l, int row) -> uint32_t {
-    return a.mask ? a.mask[(int64_t)(latb + l) * a.mask_words + (row >> 5)] : ~0u;
+  // the thread's laterals without loads: f(l, o)
+  auto lat_each = [&](int l_start, int lstep, int Lend, int row, auto f) __attribute__((always_inline)) {
+    const Off os = LatOff<OFF32>::of((int64_t)lstep * lg.es);
+    Off o = LatOff<OFF32>::of((int64_t)l_start * lg.es + row);
+    for (int l = l_start; l < Lend; l += lstep, o += os) f(l, o);
   };
+  auto at = [&](auto* origin, Off o) __attribute__((always_inline)) { return LatOff<OFF32>::at(origin, o); };
 
   // Loads consumed after the transform (the extrapolated point, or the
   // iterate pair z, z_prev it comes from, of the gradient step; the data and
@@ -141,31 +224,30 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   constexpr bool LATE_Z = MODE == LAT_UPDATE || MODE == LAT_UPDATE_L1;
   constexpr bool LATE_Y = MODE == LAT_NORMAL;
   constexpr int PF = 8;
-  const int log2H = lt - 1;
-  auto load_z = [&](int idx) {
-    const int64_t o = goff(idx);
-    return Z2{a.z[o], a.zo ? a.zo[o] : make_float2(0.f, 0.f)};
-  };
-  auto load_y = [&](int idx) {
-    const int l = idx >> log2H, p = idx & (H - 1);
-    const int pa = min(p, nr - 1), pb = min(p + H, nr - 1);
-    const int64_t oa = base + (int64_t)l * lg.es + pa, ob = base + (int64_t)l * lg.es + pb;
-    return YM{a.y ? a.y[oa] : 0.f, a.y ? a.y[ob] : 0.f, mword(l, r0 + pa), mword(l, r0 + pb)};
+  auto load_z = [&](int, Off o, int) { return Z2{*at(z_o, o), a.zo ? *at(zo_o, o) : make_float2(0.f, 0.f)}; };
+  // rows p and p + H share their mask word; o is the offset of (l, row pa)
+  const int pa = min(p_own, nr - 1), pb = min(p_own + H, nr - 1);
+  const Off pbo = LatOff<OFF32>::of(pb - pa);
+  auto load_y = [&](int, Off o, int mo) {
+    return YM{a.y ? *at(y_o, o) : 0.f, a.y ? *at(y_o, o + pbo) : 0.f, mword(mo)};
   };
   using Late = std::conditional_t<LATE_Y, YM, Z2>;
   const int n_late = LATE_Y ? (n >> 1) : n;
   const bool early = (LATE_Z || (LATE_Y && pair)) && n_late <= PF * nthr;
+  const int late_l0 = LATE_Y ? l_ownH : l_own, late_ls = LATE_Y ? LSH : LS, late_row = LATE_Y ? pa : t_cl;
   Late pf[PF];
-  // run use(idx, value) over the late elements, prefetched or loaded now
+  // run use(l, o, value) over the late elements, prefetched or loaded now
   auto late_for = [&](auto load, auto use) __attribute__((always_inline)) {
     if (early) {
+      const Off os = LatOff<OFF32>::of((int64_t)late_ls * lg.es);
+      const Off o0 = LatOff<OFF32>::of((int64_t)late_l0 * lg.es + late_row);
 #pragma unroll
-      for (int i = 0; i < PF; ++i) {
-        const int idx = tid + i * nthr;
-        if (idx < n_late) use(idx, pf[i]);
+      for (int u = 0; u < PF; ++u) {
+        const int l = late_l0 + u * late_ls;
+        if (l < L) use(l, o0 + u * os, pf[u]);
       }
     } else {
-      batched_for(n_late, tid, nthr, load, use);
+      row_for(late_l0, late_ls, L, late_row, load, use);
     }
   };
 
@@ -173,20 +255,17 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   if (MODE == LAT_ADJ_MEAS) {
     // real rows; paired: row t -> component t >= H of row t mod H
     float* ldsf = reinterpret_cast<float*>(lds);
-    batched_for(n, tid, nthr,
-      [&](int idx) { const int l = idx >> lt, t = min(idx & (T - 1), nr - 1);
-                     return FM{a.srcf[goff(idx)], mword(l, r0 + t)}; },
-      [&](int idx, FM v) {
-        const int l = idx >> lt, t = idx & (T - 1);
-        const float r = (t < nr && ((v.m >> ((r0 + t) & 31)) & 1u)) ? v.f : 0.f;
-        if (pair) ldsf[2 * ((t < H ? t : t - H) * rs + l) + (t < H ? 0 : 1)] = r;
-        else lds[t * rs + l] = make_float2(r, 0.f);
+    row_for(l_own, LS, L, t_cl,
+      [&](int, Off o, int mo) { return FM{*at(srcf_o, o), mword(mo)}; },
+      [&](int l, Off, FM v) {
+        const float r = (t_ok && mbit(v.m, t_own)) ? v.f : 0.f;
+        if (pair) ldsf[2 * ((t_own < H ? t_own : t_own - H) * rs + l) + (t_own < H ? 0 : 1)] = r;
+        else lds[t_own * rs + l] = make_float2(r, 0.f);
       });
   } else if (MODE == LAT_FFT && a.z != nullptr) {
-    batched_for(n, tid, nthr,
-      [&](int idx) { const int64_t o = goff(idx); return Z2{a.z[o], a.zo[o]}; },
-      [&](int idx, Z2 v) {
-        const int l = idx >> lt, t = idx & (T - 1);
+    row_for(l_own, LS, L, t_cl,
+      [&](int, Off o, int) { return Z2{*at(z_o, o), *at(zo_o, o)}; },
+      [&](int l, Off o, Z2 v) {
         float2 x;
         {
           // x = z + mu (z - z_prev) rounded step by step, as the fused l1 update
@@ -194,59 +273,55 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
 #pragma clang fp contract(off)
           x = make_float2(v.a.x + a.mu * (v.a.x - v.b.x), v.a.y + a.mu * (v.a.y - v.b.y));
         }
-        lds[t * rs + l] = t < nr ? x : make_float2(0.f, 0.f);
-        if (a.xout && t < nr) a.xout[base + (int64_t)l * lg.es + t] = x;
+        lds[t_own * rs + l] = t_ok ? x : make_float2(0.f, 0.f);
+        if (a.xout && t_ok) *at(xout_o, o) = x;
       });
   } else if ((MODE == LAT_FWD_MEAS || MODE == LAT_NORMAL) && half) {
     // half rows of Hermitian spectra, extended: row[L - l] = conj(row[l]); at
     // l = 0 (and L/2) only the real part belongs to the Hermitian row.
     // Paired: row p <- row_p + j row_{p+H}, so that one inverse transform
     // gives the real rows p and p + H (in .x and .y).
-    auto hoff = [&](int l, int t) -> int64_t { return hbase + (int64_t)l * lg.es + min(t, nr - 1); };
     if (pair) {
-      const int log2H = lt - 1;
-      batched_for(Lh * H, tid, nthr,
-        [&](int idx) { const int l = idx >> log2H, p = idx & (H - 1);
-                       return Z2{a.src[hoff(l, p)], a.src[hoff(l, p + H)]}; },
-        [&](int idx, Z2 v) {
-          const int l = idx >> log2H, p = idx & (H - 1);
-          float2 va = p < nr ? v.a : make_float2(0.f, 0.f), vb = p + H < nr ? v.b : make_float2(0.f, 0.f);
+      row_for(l_ownH, LSH, Lh, pa,
+        [&](int, Off o, int) { return Z2{*at(srch_o, o), *at(srch_o, o + pbo)}; },
+        [&](int l, Off, Z2 v) {
+          float2 va = p_own < nr ? v.a : make_float2(0.f, 0.f), vb = p_own + H < nr ? v.b : make_float2(0.f, 0.f);
           const bool self = l == 0 || 2 * l == L;
           if (self) { va.y = 0.f; vb.y = 0.f; }
-          float2* ra = lds + p * rs;
+          float2* ra = lds + p_own * rs;
           ra[l] = make_float2(va.x - vb.y, va.y + vb.x);
           if (!self) ra[L - l] = make_float2(va.x + vb.y, vb.x - va.y);
         });
     } else {
-      batched_for(Lh * T, tid, nthr,
-        [&](int idx) { return a.src[hoff(idx >> lt, idx & (T - 1))]; },
-        [&](int idx, float2 v) {
-          const int l = idx >> lt, t = idx & (T - 1);
-          if (t >= nr) v = make_float2(0.f, 0.f);
+      row_for(l_own, LS, Lh, t_cl,
+        [&](int, Off o, int) { return *at(srch_o, o); },
+        [&](int l, Off, float2 v) {
+          if (!t_ok) v = make_float2(0.f, 0.f);
           const bool self = l == 0 || 2 * l == L;
           if (self) v.y = 0.f;
-          lds[t * rs + l] = v;
-          if (!self) lds[t * rs + L - l] = cconj(v);
+          lds[t_own * rs + l] = v;
+          if (!self) lds[t_own * rs + L - l] = cconj(v);
         });
     }
   } else {
-    batched_for(n, tid, nthr,
-      [&](int idx) { return a.src[goff(idx)]; },
-      [&](int idx, float2 v) {
-        const int l = idx >> lt, t = idx & (T - 1);
-        lds[t * rs + l] = t < nr ? v : make_float2(0.f, 0.f);
-      });
+    row_for(l_own, LS, L, t_cl,
+      [&](int, Off o, int) { return *at(src_o, o); },
+      [&](int l, Off, float2 v) { lds[t_own * rs + l] = t_ok ? v : make_float2(0.f, 0.f); });
   }
   // retire the tile's loads (including the clamped ones nobody reads), so
   // that no register the transform reuses waits on the late loads
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
   if (early) {
+    const Off os = LatOff<OFF32>::of((int64_t)late_ls * lg.es);
+    const Off o0 = LatOff<OFF32>::of((int64_t)late_l0 * lg.es + late_row);
+    const int ms = late_ls * a.mask_words;
 #pragma unroll
-    for (int i = 0; i < PF; ++i) {
-      const int idx = tid + i * nthr;
-      if (idx < n_late) {
-        if constexpr (LATE_Y) pf[i] = load_y(idx);
-        else pf[i] = load_z(idx);
+    for (int u = 0; u < PF; ++u) {
+      const int l = late_l0 + u * late_ls;
+      if (l < L) {
+        const int mo = late_l0 * a.mask_words + u * ms;
+        if constexpr (LATE_Y) pf[u] = load_y(l, o0 + u * os, mo);
+        else pf[u] = load_z(l, o0 + u * os, mo);
       }
     }
   }
@@ -260,37 +335,34 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   else fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, nrow_t, rs, a.fd, twl, tid, nthr);
 
   if (MODE == LAT_FFT || MODE == LAT_ADJ_MEAS) {
-    const int nout = (MODE == LAT_ADJ_MEAS && half) ? Lh * T : n;   // spectra of real rows: l <= L/2 suffices
-    for (int idx = tid; idx < nout; idx += nthr) {
-      const int l = idx >> lt, t = idx & (T - 1);
-      if (t < nr) {
-        const float2 v = (MODE == LAT_ADJ_MEAS && pair) ? unpack_real_pair(lds, rs, L, H, t, l) : lds[t * rs + l];
-        a.dst[hbase + (int64_t)l * lg.es + t] = cscale(v, a.scale);
-      }
-    }
+    const int Lout = (MODE == LAT_ADJ_MEAS && half) ? Lh : L;   // spectra of real rows: l <= L/2 suffices
+    if (t_ok)
+      lat_each(l_own, LS, Lout, t_own, [&](int l, Off o) {
+        const float2 v = (MODE == LAT_ADJ_MEAS && pair) ? unpack_real_pair(lds, rs, L, H, t_own, l)
+                                                         : lds[t_own * rs + l];
+        *at(dsth_o, o) = cscale(v, a.scale);
+      });
     return;
   }
   if (MODE == LAT_FWD_MEAS) {
-    batched_for(n, tid, nthr,
-      [&](int idx) { const int l = idx >> lt, t = min(idx & (T - 1), nr - 1); return mword(l, r0 + t); },
-      [&](int idx, uint32_t m) {
-        const int l = idx >> lt, t = idx & (T - 1);
-        if (t < nr) {
-          const float re = !pair ? lds[t * rs + l].x : (t < H ? lds[t * rs + l].x : lds[(t - H) * rs + l].y);
-          const float yv = ((m >> ((r0 + t) & 31)) & 1u) ? re * a.scale : 0.f;
-          a.dstf[base + (int64_t)l * lg.es + t] = yv;
+    row_for(l_own, LS, L, t_cl,
+      [&](int, Off, int mo) { return mword(mo); },
+      [&](int l, Off o, uint32_t m) {
+        if (t_ok) {
+          const float re = !pair ? lds[t_own * rs + l].x
+                                 : (t_own < H ? lds[t_own * rs + l].x : lds[(t_own - H) * rs + l].y);
+          *at(dstf_o, o) = mbit(m, t_own) ? re * a.scale : 0.f;
         }
       });
     return;
   }
   if constexpr (MODE == LAT_UPDATE) {
     late_for(load_z,
-      [&](int idx, Z2 v) {
-        const int l = idx >> lt, t = idx & (T - 1);
-        if (t < nr) {
-          const float2 g = cscale(lds[t * rs + l], a.scale);
+      [&](int l, Off o, Z2 v) {
+        if (t_ok) {
+          const float2 gr = cscale(lds[t_own * rs + l], a.scale);
           const float xr = v.a.x + a.mu * (v.a.x - v.b.x), xi = v.a.y + a.mu * (v.a.y - v.b.y);
-          a.dst[base + (int64_t)l * lg.es + t] = make_float2(xr - a.delta * g.x, xi - a.delta * g.y);
+          *at(dst_o, o) = make_float2(xr - a.delta * gr.x, xi - a.delta * gr.y);
         }
       });
     return;
@@ -298,17 +370,16 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   if (MODE == LAT_RESID) {
     // residual rows only (pairs: rows p and p + H from the real and imaginary parts of row p)
     double acc = 0.0;
-    batched_for(n, tid, nthr,
-      [&](int idx) { const int l = idx >> lt, t = min(idx & (T - 1), nr - 1);
-                     return FM{a.y ? a.y[goff(idx)] : 0.f, mword(l, r0 + t)}; },
-      [&](int idx, FM v) {
-        const int l = idx >> lt, t = idx & (T - 1);
-        if (t < nr) {
-          const float re = !pair ? lds[t * rs + l].x : (t < H ? lds[t * rs + l].x : lds[(t - H) * rs + l].y);
+    row_for(l_own, LS, L, t_cl,
+      [&](int, Off o, int mo) { return FM{a.y ? *at(y_o, o) : 0.f, mword(mo)}; },
+      [&](int l, Off o, FM v) {
+        if (t_ok) {
+          const float re = !pair ? lds[t_own * rs + l].x
+                                 : (t_own < H ? lds[t_own * rs + l].x : lds[(t_own - H) * rs + l].y);
           float r = 0.f;
-          if ((v.m >> ((r0 + t) & 31)) & 1u) r = re * a.scale - v.f;
+          if (mbit(v.m, t_own)) r = re * a.scale - v.f;
           acc += (double)r * (double)r;
-          a.dstf[base + (int64_t)l * lg.es + t] = r;
+          *at(dstf_o, o) = r;
         }
       });
     if (a.partial) {
@@ -320,25 +391,25 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   if constexpr (MODE == LAT_NORMAL) if (pair) {
     // residual of rows p and p + H from the real and imaginary parts of row p
     double acc = 0.0;
+    const bool pa_ok = p_own < nr, pb_ok = p_own + H < nr;
     late_for(load_y,
-      [&](int idx, YM v) {
-        const int l = idx >> log2H, p = idx & (H - 1);
-        const float2 vv = lds[p * rs + l];
+      [&](int l, Off, YM v) {
+        const float2 vv = lds[p_own * rs + l];
         float ra = 0.f, rb = 0.f;
-        if (p < nr && ((v.ma >> ((r0 + p) & 31)) & 1u)) ra = vv.x * a.scale - v.ya;
-        if (p + H < nr && ((v.mb >> ((r0 + p + H) & 31)) & 1u)) rb = vv.y * a.scale - v.yb;
+        if (pa_ok && mbit(v.m, p_own)) ra = vv.x * a.scale - v.ya;
+        if (pb_ok && mbit(v.m, p_own + H)) rb = vv.y * a.scale - v.yb;
         if (a.partial) {
           acc += (double)ra * (double)ra;
           acc += (double)rb * (double)rb;
         }
-        lds[p * rs + l] = make_float2(ra, rb);
+        lds[p_own * rs + l] = make_float2(ra, rb);
       });
     __syncthreads();
     fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, H, rs, a.fd, twl, tid, nthr);
-    for (int idx = tid; idx < (half ? Lh * T : n); idx += nthr) {
-      const int l = idx >> lt, t = idx & (T - 1);
-      if (t < nr) a.dst[hbase + (int64_t)l * lg.es + t] = cscale(unpack_real_pair(lds, rs, L, H, t, l), a.scale2);
-    }
+    if (t_ok)
+      lat_each(l_own, LS, half ? Lh : L, t_own, [&](int l, Off o) {
+        *at(dsth_o, o) = cscale(unpack_real_pair(lds, rs, L, H, t_own, l), a.scale2);
+      });
     if (a.partial) {   // the residual norm only when the caller asks for it
       const double s = block_sum_d(acc, red);
       if (tid == 0) a.partial[bid] = s;
@@ -347,22 +418,20 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   }
   if (MODE == LAT_NORMAL) {
     double acc = 0.0;
-    batched_for(n, tid, nthr,
-      [&](int idx) { const int l = idx >> lt, t = min(idx & (T - 1), nr - 1);
-                     return FM{a.y ? a.y[goff(idx)] : 0.f, mword(l, r0 + t)}; },
-      [&](int idx, FM v) {
-        const int l = idx >> lt, t = idx & (T - 1);
+    row_for(l_own, LS, L, t_cl,
+      [&](int, Off o, int mo) { return FM{a.y ? *at(y_o, o) : 0.f, mword(mo)}; },
+      [&](int l, Off, FM v) {
         float r = 0.f;
-        if (t < nr && ((v.m >> ((r0 + t) & 31)) & 1u)) r = lds[t * rs + l].x * a.scale - v.f;
+        if (t_ok && mbit(v.m, t_own)) r = lds[t_own * rs + l].x * a.scale - v.f;
         acc += (double)r * (double)r;
-        lds[t * rs + l] = make_float2(r, 0.f);
+        lds[t_own * rs + l] = make_float2(r, 0.f);
       });
     __syncthreads();
     fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, T, rs, a.fd, twl, tid, nthr);
-    for (int idx = tid; idx < (half ? Lh * T : n); idx += nthr) {
-      const int l = idx >> lt, t = idx & (T - 1);
-      if (t < nr) a.dst[hbase + (int64_t)l * lg.es + t] = cscale(lds[t * rs + l], a.scale2);
-    }
+    if (t_ok)
+      lat_each(l_own, LS, half ? Lh : L, t_own, [&](int l, Off o) {
+        *at(dsth_o, o) = cscale(lds[t_own * rs + l], a.scale2);
+      });
     if (a.partial) {
       const double s = block_sum_d(acc, red);
       if (tid == 0) a.partial[bid] = s;
@@ -372,15 +441,13 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   if constexpr (MODE == LAT_UPDATE_L1) {
     double acc = 0.0;
     late_for(load_z,
-      [&](int idx, Z2 v) {
-        const int l = idx >> lt, t = idx & (T - 1);
+      [&](int l, Off o, Z2 v) {
         float2 xn = make_float2(0.f, 0.f);
-        if (t < nr) {
-          const int64_t off = base + (int64_t)l * lg.es + t;
-          const float2 g = cscale(lds[t * rs + l], a.scale);
+        if (t_ok) {
+          const float2 gr = cscale(lds[t_own * rs + l], a.scale);
           const float2 z = v.a, zo = v.b;
-          const float vr = z.x + a.mu * (z.x - zo.x) - a.delta * g.x;
-          const float vi = z.y + a.mu * (z.y - zo.y) - a.delta * g.y;
+          const float vr = z.x + a.mu * (z.x - zo.x) - a.delta * gr.x;
+          const float vi = z.y + a.mu * (z.y - zo.y) - a.delta * gr.y;
           const float mag = sqrtf(vr * vr + vi * vi);
           const float sc = mag > a.tau ? fminf(1.f - a.tau / mag, a.bound / mag) : 0.f;
           float2 zn;
@@ -392,16 +459,14 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
             xn = make_float2(zn.x + a.mu_next * (zn.x - z.x), zn.y + a.mu_next * (zn.y - z.y));
           }
           acc += (double)sqrtf(zn.x * zn.x + zn.y * zn.y);
-          a.zo[off] = zn;
+          *at(zow_o, o) = zn;
         }
-        lds[t * rs + l] = xn;
+        lds[t_own * rs + l] = xn;
       });
     __syncthreads();
     fft_rows_sized<ONE, false, OCT_CT_LAT_SIZES>(lds, T, rs, a.fd, twl, tid, nthr);
-    for (int idx = tid; idx < n; idx += nthr) {
-      const int l = idx >> lt, t = idx & (T - 1);
-      if (t < nr) a.dst[base + (int64_t)l * lg.es + t] = lds[t * rs + l];
-    }
+    if (t_ok)
+      lat_each(l_own, LS, L, t_own, [&](int l, Off o) { *at(dst_o, o) = lds[t_own * rs + l]; });
     if (a.partial) {
       const double s = block_sum_d(acc, red);
       if (tid == 0) a.partial[bid] = s;
@@ -434,29 +499,30 @@ int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* row
   return 0;
 }
 
-template <int MODE, bool ONE>
+template <int MODE, bool ONE, bool OFF32>
 hipError_t launch_lateral_m(const LatArgs& a, int nthr, hipStream_t s) {
   const size_t lds = ((size_t)lat_tile_f2(a.T, a.rowstride) + (size_t)a.fd.tw_total) * sizeof(float2);
   if (lds > 64 * 1024) {
     // once per instantiation (thread-safe initialisation of a local static)
-    static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void*>(&lat_kernel<MODE, ONE>),
+    static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void*>(&lat_kernel<MODE, ONE, OFF32>),
                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
     if (set != hipSuccess) return set;
   }
-  hipLaunchKernelGGL((lat_kernel<MODE, ONE>), dim3((a.lg.n_lines * a.n_tiles + 7) & ~7), dim3(nthr), lds, s, a);
+  hipLaunchKernelGGL((lat_kernel<MODE, ONE, OFF32>), dim3((a.lg.n_lines * a.n_tiles + 7) & ~7), dim3(nthr), lds, s,
+                     a);
   return hipGetLastError();
 }
 
-template <bool ONE>
+template <bool ONE, bool OFF32>
 hipError_t launch_lateral_t(LatMode mode, const LatArgs& a, int nthr, hipStream_t s) {
   switch (mode) {
-    case LAT_FFT: return launch_lateral_m<LAT_FFT, ONE>(a, nthr, s);
-    case LAT_FWD_MEAS: return launch_lateral_m<LAT_FWD_MEAS, ONE>(a, nthr, s);
-    case LAT_ADJ_MEAS: return launch_lateral_m<LAT_ADJ_MEAS, ONE>(a, nthr, s);
-    case LAT_NORMAL: return launch_lateral_m<LAT_NORMAL, ONE>(a, nthr, s);
-    case LAT_UPDATE: return launch_lateral_m<LAT_UPDATE, ONE>(a, nthr, s);
-    case LAT_UPDATE_L1: return launch_lateral_m<LAT_UPDATE_L1, ONE>(a, nthr, s);
-    case LAT_RESID: return launch_lateral_m<LAT_RESID, ONE>(a, nthr, s);
+    case LAT_FFT: return launch_lateral_m<LAT_FFT, ONE, OFF32>(a, nthr, s);
+    case LAT_FWD_MEAS: return launch_lateral_m<LAT_FWD_MEAS, ONE, OFF32>(a, nthr, s);
+    case LAT_ADJ_MEAS: return launch_lateral_m<LAT_ADJ_MEAS, ONE, OFF32>(a, nthr, s);
+    case LAT_NORMAL: return launch_lateral_m<LAT_NORMAL, ONE, OFF32>(a, nthr, s);
+    case LAT_UPDATE: return launch_lateral_m<LAT_UPDATE, ONE, OFF32>(a, nthr, s);
+    case LAT_UPDATE_L1: return launch_lateral_m<LAT_UPDATE_L1, ONE, OFF32>(a, nthr, s);
+    case LAT_RESID: return launch_lateral_m<LAT_RESID, ONE, OFF32>(a, nthr, s);
   }
   return hipErrorInvalidValue;
 }
@@ -467,6 +533,12 @@ hipError_t launch_lateral(LatMode mode, const LatArgs& a, hipStream_t s) {
   int nthr = 256;
   while (nthr < 1024 && bf > (int64_t)mb * nthr) nthr <<= 1;
   if (bf > (int64_t)mb * nthr) return hipErrorInvalidConfiguration;
-  return fft_one(a.fd, a.T, nthr) ? launch_lateral_t<true>(mode, a, nthr, s)
-                                  : launch_lateral_t<false>(mode, a, nthr, s);
+  // a thread owns one tile row: the threads must be a multiple of the rows
+  if (nthr % a.T != 0) return hipErrorInvalidConfiguration;
+  // 32-bit byte offsets inside a tile when its span (lateral stride times the
+  // laterals, plus the rows) stays below 4 GiB
+  const bool off32 = ((int64_t)(a.lg.L - 1) * a.lg.es + a.T) * (int64_t)sizeof(float2) < ((int64_t)1 << 32);
+  if (fft_one(a.fd, a.T, nthr))
+    return off32 ? launch_lateral_t<true, true>(mode, a, nthr, s) : launch_lateral_t<true, false>(mode, a, nthr, s);
+  return off32 ? launch_lateral_t<false, true>(mode, a, nthr, s) : launch_lateral_t<false, false>(mode, a, nthr, s);
 }
