@@ -735,8 +735,9 @@ oct_status run_prox(oct_plan* p, int pen, float tau, float bound, int tv_inner, 
   } else if (pen == OCT_PEN_HAAR) {
     if (bound < INFINITY) return fail(OCT_E_UNSUPPORTED, "a modulus bound with the Haar prox has no closed form");
     OCTCHK(check_haar(p, haar_levels));
-    HIPCHK(launch_prox_haar(pg, haar_levels, v, z, tau, p->partial, s));
-    *np = haar_partials(pg, haar_levels);
+    // |detail| partials only when the value is wanted (the kernel skips them otherwise)
+    HIPCHK(launch_prox_haar(pg, haar_levels, v, z, tau, want_value ? p->partial : nullptr, s));
+    *np = want_value ? haar_partials(pg, haar_levels) : 0;
   } else if (pen == OCT_PEN_TV) {
     if (tv_inner < 1 || tv_inner > 1000) return fail(OCT_E_INVALID, "tv_inner must be 1..1000");
     std::vector<float> mom = fgp_momenta(tv_inner);

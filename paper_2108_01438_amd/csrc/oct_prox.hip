@@ -159,15 +159,19 @@ __device__ __forceinline__ void haar_inv_group(float2* v) {
   }
 }
 
+// soft threshold; with PART the modulus of the result joins the l1 partial sum
+template <bool PART>
 __device__ __forceinline__ float2 soft(float2 a, float tau, double& acc) {
   const float mag = sqrtf(a.x * a.x + a.y * a.y);
   const float sc = mag > tau ? 1.f - tau / mag : 0.f;
   const float2 r = make_float2(a.x * sc, a.y * sc);
-  acc += (double)sqrtf(r.x * r.x + r.y * r.y);
+  if (PART) acc += (double)sqrtf(r.x * r.x + r.y * r.y);
   return r;
 }
 
-template <int D, int LV, int NBN>
+// PART: also the per-block FP64 sums of |detail coefficients| (the penalty
+// value), only when the caller asks for them
+template <int D, int LV, int NBN, bool PART>
 __global__ void __launch_bounds__(1024) haar_kernel(ProxGeom g, const float2* __restrict__ vin, float2* zout,
                                                     float tau, double* partial) {
   constexpr int NV = 1 << D;
@@ -190,6 +194,13 @@ __global__ void __launch_bounds__(1024) haar_kernel(ProxGeom g, const float2* __
   const int iy = t % ty; t /= ty;
   const int b = t;
   const int z0 = iz * NBN * BS, x0 = ix * BS, y0 = iy * BS;
+  // a 2x2(x2) group at depth 2a, x 2bb, y 2c of the tile: its first element's
+  // offset; the others lie 1 (depth), sx (x) and sy (y) further
+  const int64_t sx = Nz, sy = (int64_t)Nx * Nz;
+  auto group_off = [&](int a, int bb, int c) -> int64_t {
+    return (((int64_t)b * Ny + y0 + 2 * c) * Nx + x0 + 2 * bb) * Nz + z0 + 2 * a;
+  };
+  auto elem_off = [&](int i) -> int64_t { return (i & 1) + ((i >> 1) & 1) * sx + ((i >> 2) & 1) * sy; };
 
   float2 det[LV][NV];
   double acc = 0.0;
@@ -199,16 +210,12 @@ __global__ void __launch_bounds__(1024) haar_kernel(ProxGeom g, const float2* __
       const int a = tid % GA0, bb = (tid / GA0) % GB0, c = tid / (GA0 * GB0);
       float2 v[NV];
       const bool ok = z0 + 2 * a < Nz;
+      const float2* __restrict__ src = vin + group_off(a, bb, c);
 #pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        const int zz = z0 + 2 * a + (i & 1);
-        const int xx = x0 + 2 * bb + ((i >> 1) & 1);
-        const int yy = (D == 3) ? y0 + 2 * c + ((i >> 2) & 1) : 0;
-        v[i] = ok ? vin[(((int64_t)b * Ny + yy) * Nx + xx) * Nz + zz] : make_float2(0.f, 0.f);
-      }
+      for (int i = 0; i < NV; ++i) v[i] = ok ? src[elem_off(i)] : make_float2(0.f, 0.f);
       haar_fwd_group<D>(v);
 #pragma unroll
-      for (int i = 1; i < NV; ++i) det[0][i] = soft(v[i], tau, acc);
+      for (int i = 1; i < NV; ++i) det[0][i] = soft<PART>(v[i], tau, acc);
       ll[0][tid] = v[0];
     }
   }
@@ -229,7 +236,7 @@ __global__ void __launch_bounds__(1024) haar_kernel(ProxGeom g, const float2* __
       }
       haar_fwd_group<D>(v);
 #pragma unroll
-      for (int i = 1; i < NV; ++i) det[l][i] = soft(v[i], tau, acc);
+      for (int i = 1; i < NV; ++i) det[l][i] = soft<PART>(v[i], tau, acc);
       det[l][0] = v[0];   // coarsest low band kept (only used at l = LV-1)
       ll[dstb][tid] = v[0];
     }
@@ -267,17 +274,15 @@ __global__ void __launch_bounds__(1024) haar_kernel(ProxGeom g, const float2* __
     for (int i = 1; i < NV; ++i) v[i] = det[0][i];
     haar_inv_group<D>(v);
     if (z0 + 2 * a < Nz) {
+      float2* __restrict__ dst = zout + group_off(a, bb, c);
 #pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        const int zz = z0 + 2 * a + (i & 1);
-        const int xx = x0 + 2 * bb + ((i >> 1) & 1);
-        const int yy = (D == 3) ? y0 + 2 * c + ((i >> 2) & 1) : 0;
-        zout[(((int64_t)b * Ny + yy) * Nx + xx) * Nz + zz] = v[i];
-      }
+      for (int i = 0; i < NV; ++i) dst[elem_off(i)] = v[i];
     }
   }
-  const double s = block_sum(acc, sh);
-  if (tid == 0 && partial) partial[blockIdx.x] = s;
+  if (PART) {
+    const double s = block_sum(acc, sh);
+    if (tid == 0) partial[blockIdx.x] = s;
+  }
 }
 
 template <int D, int LV> struct HaarCfg;
@@ -304,7 +309,11 @@ hipError_t haar_launch(const ProxGeom& g, const float2* v, float2* z, float tau,
   constexpr int NBN = HaarCfg<D, LV>::NBN;
   const int nt = haar_threads<D, LV>();
   const int nb = haar_blocks<D, LV>(g);
-  hipLaunchKernelGGL((haar_kernel<D, LV, NBN>), dim3(nb), dim3(nt < 64 ? 64 : nt), 0, s, g, v, z, tau, partial);
+  if (partial)
+    hipLaunchKernelGGL((haar_kernel<D, LV, NBN, true>), dim3(nb), dim3(nt < 64 ? 64 : nt), 0, s, g, v, z, tau, partial);
+  else
+    hipLaunchKernelGGL((haar_kernel<D, LV, NBN, false>), dim3(nb), dim3(nt < 64 ? 64 : nt), 0, s, g, v, z, tau,
+                       partial);
   return hipGetLastError();
 }
 
