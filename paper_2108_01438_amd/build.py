@@ -50,6 +50,44 @@ def build_library(verbose: bool = True) -> str:
     return LIB
 
 
+# Host sanitizer build: the library's sources and tests/sanitize/host_sanitize_driver.cpp
+# linked into one executable whose HOST code carries AddressSanitizer and
+# UndefinedBehaviorSanitizer (each -fsanitize= follows -Xarch_host: the device
+# code is built as usual).  tests/test_gpu_host_sanitizers.py runs it.
+SAN_DIR = os.path.join(BUILD_DIR, "sanitize")
+SAN_DRIVER = os.path.join(ROOT, "tests", "sanitize", "host_sanitize_driver.cpp")
+SAN_EXE = os.path.join(ROOT, "tests", "sanitize", "host_sanitize_driver")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer", "-g1"]
+
+
+def _compile_san(path: str) -> str:
+    obj = os.path.join(SAN_DIR, os.path.basename(path) + ".o")
+    cmd = [HIPCC] + FLAGS + SAN_FLAGS + ["-x", "hip", "-c", path, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {path}:\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build_sanitize_driver(verbose: bool = True) -> str:
+    os.makedirs(SAN_DIR, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES] + [SAN_DRIVER]
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        objs = list(ex.map(_compile_san, srcs))
+    tmp = SAN_EXE + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950"] + SAN_FLAGS + ["-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SAN_EXE)
+    if verbose:
+        print(f"built {SAN_EXE}")
+    return SAN_EXE
+
+
 if __name__ == "__main__":
     build_library()
+    if "--sanitize" in sys.argv:
+        build_sanitize_driver()
     sys.exit(0)

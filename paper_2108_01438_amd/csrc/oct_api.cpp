@@ -797,10 +797,12 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   *out = nullptr;
   OCTCHK(validate(g));
   OCTCHK(unsupported_sizes(g));
+  int device = 0;
+  HIPCHK(hipGetDevice(&device));   // before the plan exists: nothing to free on failure
   oct_plan* p = new (std::nothrow) oct_plan();
   if (!p) return fail(OCT_E_NOMEM, "host allocation failed");
   p->g = *g;
-  HIPCHK(hipGetDevice(&p->device));
+  p->device = device;
   keep_pool_memory(p->device);
   p->lat_dims = g->lateral_dims;
   p->Nz = g->n_depth;
