@@ -768,6 +768,13 @@ extern "C" {
 
 const char* oct_last_error(void) { return g_err.c_str(); }
 
+// Slot stride of the half spectrum's y rows (see plan creation) and the
+// elements of W: the full spectrum, or the padded half spectrum if larger.
+static int64_t w_slot_stride(const oct_geometry& g) { return g.n_y > 1 ? g.n_x + 1 : g.n_x; }
+static int64_t w_elems(const oct_geometry& g) {
+  return g.batch * std::max(g.n_y * g.n_x, g.n_y * w_slot_stride(g)) * g.n_k;
+}
+
 size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   if (validate(g) != OCT_OK) return 0;
   const int64_t Nlat = g->n_x * g->n_y;
@@ -778,7 +785,7 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   size_t b = 0;
   b += (size_t)(K + g->n_x + g->n_y) * 8 + (size_t)g->n_depth * 4 + (size_t)g->n_k * (8 + 8) +
        (size_t)Nlat * (8 + 4) * 2 + (size_t)g->n_k * 8 + (size_t)Nlat * ((g->n_k + 31) / 32) * 4;
-  b += (size_t)N * 8 + (size_t)M * 8;            // workspace X1, W
+  b += (size_t)N * 8 + (size_t)w_elems(*g) * 8;  // workspace X1, W
   b += (size_t)Nlat * 16;                        // column-pair table of the half-spectrum path
   b += (size_t)M * 4;                            // measurements scaled per item (per-item weights)
   if (g->model == OCT_MODEL_LITERAL)             // K's samples and the literal chain's tables
@@ -926,8 +933,11 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   p->Nxh = p->Nx / 2 + 1;
   // rows of the half spectrum keep the full n_x stride (W is full-size): with
   // the packed n_x / 2 + 1 stride the volume's y passes and residual seam ran
-  // 20% slower per byte (1.37 vs 1.13 ms per seam at 2048 x 256 x 256)
-  p->Nxs = p->Nx;
+  // 20% slower per byte (1.37 vs 1.13 ms per seam at 2048 x 256 x 256).  A
+  // volume pads it by one slot: with a power-of-two n_x the y stride n_x n_k
+  // is a power of two, and the half-spectrum y passes ran 8% slower for it
+  // (seam 1.065 vs 0.976 ms at 2048 x 256 x 256).
+  p->Nxs = w_slot_stride(p->g);
   if (p->model == OCT_MODEL_DIRECT) {
     std::vector<int4> pr;
     for (int64_t iy = 0; iy < p->Ny; ++iy) {
@@ -948,9 +958,9 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
     p->hs = nufft_pair_supported(nufft_args(p));
   }
   if ((st = dev_alloc(p, &p->X1, p->n_img())) != OCT_OK) return cleanup(st);
-  if ((st = dev_alloc(p, &p->W, p->n_meas())) != OCT_OK) return cleanup(st);
+  if ((st = dev_alloc(p, &p->W, w_elems(p->g))) != OCT_OK) return cleanup(st);
   if (hipMemset(p->X1, 0, sizeof(float2) * p->n_img()) != hipSuccess ||
-      hipMemset(p->W, 0, sizeof(float2) * p->n_meas()) != hipSuccess ||
+      hipMemset(p->W, 0, sizeof(float2) * w_elems(p->g)) != hipSuccess ||
       hipStreamSynchronize(nullptr) != hipSuccess)
     return cleanup(fail(OCT_E_DEVICE, "hipMemset of the workspace failed"));
   p->partial_cap = partial_need(p);
