@@ -183,6 +183,7 @@ struct oct_plan {
   bool hs = false;
   int64_t Nxh = 0;               // n_x / 2 + 1
   int64_t Nxs = 0;               // half-spectrum slot stride per y row (n_x; slots < Nxh used)
+  int64_t X1s = 0;               // column stride of X1's y rows (n_x, or n_x + 1 for a volume)
   int4* pairs = nullptr;
   int n_pairs = 0;
   FftDesc fN{};
@@ -364,6 +365,14 @@ LineGeom lines_y(const oct_plan* p, int rows) {
 }
 
 // y lines of a half-spectrum array [batch][n_y][n_x/2 + 1][rows]
+// y lines of X1 (y rows X1s columns apart)
+LineGeom lines_y_x1(const oct_plan* p, int rows) {
+  LineGeom lg = lines_y(p, rows);
+  lg.sa = p->Ny * p->X1s * rows;
+  lg.es = p->X1s * rows;
+  return lg;
+}
+
 LineGeom lines_y_half(const oct_plan* p, int rows) {
   LineGeom lg = lines_y(p, rows);
   lg.n_lines = (int)(p->B * p->Nxh);
@@ -403,6 +412,8 @@ NufftArgs nufft_args(const oct_plan* p) {
   a.J = p->J;
   a.Nlat = (int)p->Nlat;
   a.n_cols = (int)(p->B * p->Nlat);
+  a.Nx = (int)p->Nx;
+  a.xs = (int)p->X1s;
   a.ct = p->ct;
   a.invK = 1.0 / (double)p->K;
   a.df = p->df;
@@ -478,9 +489,10 @@ oct_status run_lat_forward(oct_plan* p, const float2* x, const float2* z, const 
   a.mu = mu;
   a.xout = xout;
   a.dst = p->X1;
+  a.sa_out = p->X1s * p->Nz;   // X1's x lines (image rows: lg.sa)
   HIPCHK(launch_lateral(LAT_FFT, a, s));
   if (p->lat_dims == 2) {
-    LatArgs b = lat_args(p, lines_y(p, (int)p->Nz), true);
+    LatArgs b = lat_args(p, lines_y_x1(p, (int)p->Nz), true);
     b.src = p->X1;
     b.dst = p->X1;
     HIPCHK(launch_lateral(LAT_FFT, b, s));
@@ -620,7 +632,7 @@ oct_status run_normal(oct_plan* p, const float* y, double* partial, int* nparts,
 // X1 (adjoint NUFFT output) -> g = F_lat^H X1 written to out
 oct_status run_lat_adjoint(oct_plan* p, float2* out, hipStream_t s) {
   if (p->lat_dims == 2) {
-    LatArgs b = lat_args(p, lines_y(p, (int)p->Nz), true);
+    LatArgs b = lat_args(p, lines_y_x1(p, (int)p->Nz), true);
     b.src = p->X1;
     b.dst = p->X1;
     b.inverse = 1;
@@ -628,6 +640,7 @@ oct_status run_lat_adjoint(oct_plan* p, float2* out, hipStream_t s) {
   }
   LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
   a.src = p->X1;
+  a.sa_in = p->X1s * p->Nz;   // X1's x lines
   a.dst = out;
   a.inverse = 1;
   HIPCHK(launch_lateral(LAT_FFT, a, s));
@@ -768,12 +781,14 @@ extern "C" {
 
 const char* oct_last_error(void) { return g_err.c_str(); }
 
-// Slot stride of the half spectrum's y rows (see plan creation) and the
-// elements of W: the full spectrum, or the padded half spectrum if larger.
+// Column stride of the y rows of the spectral buffers (see plan creation):
+// a volume pads them by one column; the elements of W (the full spectrum, or
+// the padded half spectrum if larger) and of X1.
 static int64_t w_slot_stride(const oct_geometry& g) { return g.n_y > 1 ? g.n_x + 1 : g.n_x; }
 static int64_t w_elems(const oct_geometry& g) {
   return g.batch * std::max(g.n_y * g.n_x, g.n_y * w_slot_stride(g)) * g.n_k;
 }
+static int64_t x1_elems(const oct_geometry& g) { return g.batch * g.n_y * w_slot_stride(g) * g.n_depth; }
 
 size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   if (validate(g) != OCT_OK) return 0;
@@ -785,7 +800,7 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   size_t b = 0;
   b += (size_t)(K + g->n_x + g->n_y) * 8 + (size_t)g->n_depth * 4 + (size_t)g->n_k * (8 + 8) +
        (size_t)Nlat * (8 + 4) * 2 + (size_t)g->n_k * 8 + (size_t)Nlat * ((g->n_k + 31) / 32) * 4;
-  b += (size_t)N * 8 + (size_t)w_elems(*g) * 8;  // workspace X1, W
+  b += (size_t)x1_elems(*g) * 8 + (size_t)w_elems(*g) * 8;  // workspace X1, W
   b += (size_t)Nlat * 16;                        // column-pair table of the half-spectrum path
   b += (size_t)M * 4;                            // measurements scaled per item (per-item weights)
   if (g->model == OCT_MODEL_LITERAL)             // K's samples and the literal chain's tables
@@ -938,6 +953,8 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
   // is a power of two, and the half-spectrum y passes ran 8% slower for it
   // (seam 1.065 vs 0.976 ms at 2048 x 256 x 256).
   p->Nxs = w_slot_stride(p->g);
+  // X1 pads its y rows the same way (its y passes have the same stride problem)
+  p->X1s = w_slot_stride(p->g);
   if (p->model == OCT_MODEL_DIRECT) {
     std::vector<int4> pr;
     for (int64_t iy = 0; iy < p->Ny; ++iy) {
@@ -957,9 +974,9 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
     if ((st = upload(p, &p->pairs, pr)) != OCT_OK) return cleanup(st);
     p->hs = nufft_pair_supported(nufft_args(p));
   }
-  if ((st = dev_alloc(p, &p->X1, p->n_img())) != OCT_OK) return cleanup(st);
+  if ((st = dev_alloc(p, &p->X1, x1_elems(p->g))) != OCT_OK) return cleanup(st);
   if ((st = dev_alloc(p, &p->W, w_elems(p->g))) != OCT_OK) return cleanup(st);
-  if (hipMemset(p->X1, 0, sizeof(float2) * p->n_img()) != hipSuccess ||
+  if (hipMemset(p->X1, 0, sizeof(float2) * x1_elems(p->g)) != hipSuccess ||
       hipMemset(p->W, 0, sizeof(float2) * w_elems(p->g)) != hipSuccess ||
       hipStreamSynchronize(nullptr) != hipSuccess)
     return cleanup(fail(OCT_E_DEVICE, "hipMemset of the workspace failed"));
@@ -1030,6 +1047,7 @@ oct_status oct_direct(oct_plan_t p, int32_t kind, const float* y, void* x, void*
       a.q2 = p->q2zero;
       a.beam = p->beamone;
       a.phase = (kind == OCT_DIRECT_AXIAL) ? p->phase_nd : p->phase;
+      a.xs = (int)p->Nx;   // the caller's image: dense rows
       HIPCHK(launch_nufft_adj(a, p->W, (float2*)x, s));
       return OCT_OK;
     }
@@ -1277,15 +1295,18 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
       HIPCHK(launch_lateral(LAT_UPDATE_L1, a, s));
     } else {
       if (p->lat_dims == 2) {
-        LatArgs b = lat_args(p, lines_y(p, (int)p->Nz), true);
+        LatArgs b = lat_args(p, lines_y_x1(p, (int)p->Nz), true);
         b.src = p->X1;
         b.dst = p->X1;
         b.inverse = 1;
         HIPCHK(launch_lateral(LAT_FFT, b, s));
       }
+      // v = x - delta grad overwrites x in place (same layout, each element
+      // read then written by one thread); X1's rows may be padded, the image's not
       LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
       a.src = p->X1;
-      a.dst = p->X1;
+      a.sa_in = p->X1s * p->Nz;
+      a.dst = p->xext;
       a.inverse = 1;
       a.z = p->xext;   // x as the forward pass formed it
       a.delta = (float)delta;
@@ -1293,14 +1314,14 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
       // z^k -> zo (z^{k-2} is no longer needed)
       if (prm->penalty == OCT_PEN_TV && !(tau > 0)) {
         // no TV term (its partials are zero): z = P_C(v)
-        if (bf < INFINITY) HIPCHK(launch_prox_l1(p->X1, zo, n, 0.f, bf, nullptr, 1024, s));
-        else HIPCHK(launch_copy(p->X1, zo, n, s));
+        if (bf < INFINITY) HIPCHK(launch_prox_l1(p->xext, zo, n, 0.f, bf, nullptr, 1024, s));
+        else HIPCHK(launch_copy(p->xext, zo, n, s));
         HIPCHK(launch_zero(reinterpret_cast<float2*>(pen_part), 1, s));
         npen = 1;
       } else {
         double* save = p->partial;
         p->partial = pen_part;
-        oct_status st = run_prox(p, prm->penalty, tau, bf, prm->tv_inner, prm->haar_levels, p->X1, zo, pin, pout,
+        oct_status st = run_prox(p, prm->penalty, tau, bf, prm->tv_inner, prm->haar_levels, p->xext, zo, pin, pout,
                                  &npen, s, want_obj);
         p->partial = save;
         OCTCHK(st);
@@ -1350,7 +1371,7 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
       return OCT_OK;
     case OCT_STAGE_LAT_UPDATE: {
       if (p->lat_dims == 2) {
-        LatArgs b = lat_args(p, lines_y(p, (int)p->Nz), true);
+        LatArgs b = lat_args(p, lines_y_x1(p, (int)p->Nz), true);
         b.src = p->X1;
         b.dst = p->X1;
         b.inverse = 1;
@@ -1358,7 +1379,8 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
       }
       LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
       a.src = p->X1;
-      a.dst = p->X1;
+      a.sa_in = p->X1s * p->Nz;
+      a.dst = p->xext;
       a.inverse = 1;
       a.z = p->xext;
       a.delta = 1e-3f;
@@ -1367,7 +1389,7 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
     }
     case OCT_STAGE_PROX: {
       int np = 0;
-      return run_prox(p, pen, 1e-3f, INFINITY, 10, 3, p->X1, p->zb, pen == OCT_PEN_TV ? p->p0 : nullptr,
+      return run_prox(p, pen, 1e-3f, INFINITY, 10, 3, p->xext, p->zb, pen == OCT_PEN_TV ? p->p0 : nullptr,
                       pen == OCT_PEN_TV ? p->p1 : nullptr, &np, s);
     }
     default:

@@ -111,6 +111,10 @@ struct LatArgs {
   // with line stride sa_half (0: full rows, line stride lg.sa).  The rows are
   // spectra of real rows, so l > L/2 holds conj(row[L - l]).
   int64_t sa_half;
+  // x lines only: line strides of the source and destination operands when
+  // they differ from lg.sa (0: lg.sa) -- a volume's spectral buffer pads
+  // its y rows while the images it is transformed from and to do not
+  int64_t sa_in, sa_out;
   const float2* z;       // current iterate z^{k-1} (UPDATE: the extrapolated x itself when zo is NULL)
   float2* zo;            // previous iterate z^{k-2}; receives z^k in UPDATE_L1
   float2* xout;          // FFT with z: also stores x = z + mu (z - zo) here (nullable)
@@ -125,6 +129,10 @@ struct LatArgs {
 struct NufftArgs {
   int Nz, Mk, K, nc, J, Nlat;
   int n_cols;
+  // image-side columns: lateral index y n_x + x of batch item b lives at
+  // ((b n_y + y) xs + x) Nz (xs = n_x: dense; n_x + 1: a volume's padded
+  // spectral buffer)
+  int Nx, xs;
   double ct;             // K dz / (2 pi): oversampled-grid coordinate per unit beta
   double invK;           // 1 / K
   double df;             // z_f - n_c dz (focus offset); 0 skips its phase

@@ -126,6 +126,10 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   // spectral operand in half-spectrum storage (x lines only: ocnt = 1, sb = 0)
   const bool half = a.sa_half != 0;
   const int Lh = L / 2 + 1;
+  // x lines whose source or destination has its own line stride (a volume's
+  // padded spectral buffer on one side, an image on the other)
+  const int64_t base_in = (lg.ocnt == 1 && a.sa_in) ? (int64_t)line * a.sa_in + r0 : base;
+  const int64_t base_out = (lg.ocnt == 1 && a.sa_out) ? (int64_t)line * a.sa_out + r0 : base;
   const int64_t hbase = half ? (int64_t)line * a.sa_half + r0 : base;
   const int latb = (line % lg.lat_lines) * L;
   const int n = L * T;
@@ -163,15 +167,15 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
   const int LSH = nthr >> log2H;
   // per-array tile origins (uniform: scalar registers)
   auto org = [](auto* p, int64_t b) { return p ? p + b : p; };
-  const float2* __restrict__ src_o = org(a.src, base);
-  const float2* __restrict__ srch_o = org(a.src, hbase);
+  const float2* __restrict__ src_o = org(a.src, base_in);
+  const float2* __restrict__ srch_o = org(a.src, half ? hbase : base_in);
   const float* __restrict__ srcf_o = org(a.srcf, base);
   const float2* __restrict__ z_o = org(a.z, base);
   const float2* __restrict__ zo_o = org(a.zo, base);
   float2* __restrict__ zow_o = org(a.zo, base);
   float2* __restrict__ xout_o = org(a.xout, base);
-  float2* __restrict__ dst_o = org(a.dst, base);
-  float2* __restrict__ dsth_o = org(a.dst, hbase);
+  float2* __restrict__ dst_o = org(a.dst, base_out);
+  float2* __restrict__ dsth_o = org(a.dst, half ? hbase : base_out);
   float* __restrict__ dstf_o = org(a.dstf, base);
   const float* __restrict__ y_o = org(a.y, base);
   // mask words of this tile's rows (T <= 32 rows from a multiple of T: one word)

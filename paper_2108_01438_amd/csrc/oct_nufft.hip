@@ -298,6 +298,12 @@ __device__ __forceinline__ bool adj_grid_ifft_half_sized(float2* buf, int nrows,
   return done;
 }
 
+// element offset of image-side column `lat` (lateral index y n_x + x) of batch item b
+__device__ __forceinline__ int64_t xcol(const NufftArgs& a, int b, int lat) {
+  const int y = lat / a.Nx, x = lat - y * a.Nx;
+  return ((int64_t)(b * (a.Nlat / a.Nx) + y) * a.xs + x) * a.Nz;
+}
+
 // per-element loads gathered for batched_for (grid loads and stores; the
 // sample loops are not batched: their bodies are long, other waves cover the
 // table loads, and batching them would cost registers)
@@ -327,7 +333,7 @@ __global__ void __launch_bounds__(1024) nufft_fwd_kernel(NufftArgs a, const floa
   const int col = blockIdx.x;
   const int lat = col % a.Nlat;
   const int K = a.K, Nz = a.Nz, nc = a.nc;
-  const float2* __restrict__ src = X1 + (int64_t)col * Nz;
+  const float2* __restrict__ src = X1 + xcol(a, col / a.Nlat, lat);
   const float2* __restrict__ twl = a.twK;
 
   const bool half = K == 2 * Nz && 2 * nc == Nz &&
@@ -522,7 +528,7 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
   }
   __syncthreads();
 
-  float2* __restrict__ dst = X + (int64_t)col * Nz;
+  float2* __restrict__ dst = X + xcol(a, col / a.Nlat, lat);
   if (K == 2 * Nz && 2 * nc == Nz &&
       adj_grid_ifft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(grid, 1, K, dst, nullptr, a.deap, nc, a.fK, twl,
                                                                    tid, nthr))
@@ -557,8 +563,8 @@ __global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int b = blockIdx.x / a.n_pairs;
   const int4 pr = a.pairs[blockIdx.x - b * a.n_pairs];
-  const float2* __restrict__ s0 = X1 + ((int64_t)b * a.Nlat + pr.x) * Nz;
-  const float2* __restrict__ s1 = X1 + ((int64_t)b * a.Nlat + pr.y) * Nz;
+  const float2* __restrict__ s0 = X1 + xcol(a, b, pr.x);
+  const float2* __restrict__ s1 = X1 + xcol(a, b, pr.y);
 
   const bool half = K == 2 * Nz && 2 * nc == Nz &&
                     fwd_grid_fft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(g0, 2, rs, s0, s1, a.deap, a.fK,
@@ -863,8 +869,8 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_pair_kernel(Nufft
     adj_pair_gather<J>(a, kc, q2, bm, xm, us0, us1, first, grid, mf, umin, umax, span, nph, tid, nthr);
   }
 
-  float2* __restrict__ d0 = X + ((int64_t)b * a.Nlat + pr.x) * Nz;
-  float2* __restrict__ d1 = X + ((int64_t)b * a.Nlat + pr.y) * Nz;
+  float2* __restrict__ d0 = X + xcol(a, b, pr.x);
+  float2* __restrict__ d1 = X + xcol(a, b, pr.y);
   const bool two = pr.y != pr.x;
   if (K == 2 * Nz && 2 * nc == Nz &&
       adj_grid_ifft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(grid, 2, K, d0, two ? d1 : nullptr, a.deap, nc,
