@@ -136,9 +136,9 @@ STAGE_KERNEL = {
     "prox": {"tv": "tv2d_tile_kernel<false>", "haar": "haar_kernel<3, 3", "l1": "prox_l1_kernel"},
 }
 BSCAN_STAGE_KERNEL = {
-    "lat_fwd": "lat_kernel<0, false>",
-    "normal": "lat_kernel<3, false>",
-    "lat_update": "lat_kernel<4, false>",
+    "lat_fwd": "lat_kernel<0, false, ",
+    "normal": "lat_kernel<3, false, ",
+    "lat_update": "lat_kernel<4, false, ",
 }
 STAGE_SOURCE = {
     "lat_fwd": "oct_lateral.hip", "normal": "oct_lateral.hip", "lat_update": "oct_lateral.hip",
