@@ -1102,7 +1102,8 @@ oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, dou
   OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
   OCTCHK(run_cols_fwd(p, s, p->hs));
   int np = 0;
-  OCTCHK(run_normal(p, y, p->partial, &np, s, p->hs));
+  // residual partials only when the caller asks for 1/2 ||r||^2
+  OCTCHK(run_normal(p, y, half_resid_sq ? p->partial : nullptr, &np, s, p->hs));
   if (half_resid_sq) HIPCHK(launch_reduce_sum(p->partial, np, half_resid_sq, 0.5, 0, s));
   OCTCHK(run_cols_adj(p, s, p->hs));
   OCTCHK(run_lat_adjoint(p, (float2*)gout, s));
