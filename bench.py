@@ -35,6 +35,7 @@ METRIC = "Φ+Φᴴ applications/s & HBM GB/s; MBIR iters/s; serving p50/p99 late
 HBM_PEAK_GBPS = 8000.0
 WORKLOAD = "volume_2048x256x256_haar"
 BSCAN = "bscan_2048x1000_tv"
+SMALL = "bscan_512x64_l1"
 
 
 def stage_bytes(g, masked: bool, penalty: str) -> dict:
@@ -687,7 +688,7 @@ def main() -> int:
     ap.add_argument("--stage-reps", type=int, default=10)
     ap.add_argument("--workload", choices=("volume", "bscan"), default="volume",
                     help="headline workload: the 2048 x 256 x 256 Haar volume (default) or the 2048 x 1000 TV B-scan")
-    ap.add_argument("--no-bscan", action="store_true", help="skip the B-scan summary of the volume line")
+    ap.add_argument("--no-bscan", action="store_true", help="skip the B-scan summaries (full-size TV, small l1) of the volume line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="only write profiles/traffic_<workload>.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
@@ -698,6 +699,8 @@ def main() -> int:
     ap.add_argument("--serving-slots", type=int, default=8, help="concurrent solves of the serving benchmark")
     ap.add_argument("--table1", action="store_true",
                     help="only run the synthetic analogue of Table 1 (NCC of direct, interpolated and MBIR images)")
+    ap.add_argument("--small", action="store_true",
+                    help="only the small B-scan's solve latency (launched and graph-replayed)")
     ap.add_argument("--phi-sizes", action="store_true",
                     help="only time Phi + Phi^H at the batch and volume sizes")
     ap.add_argument("--bound", type=float, default=0.0,
@@ -737,6 +740,11 @@ def main() -> int:
         return 0
     if args.table1:
         print(json.dumps(table1_bench()), flush=True)
+        return 0
+    if args.small:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(small_line()), flush=True)
         return 0
     if args.phi_sizes:
         print(json.dumps(phi_sizes_bench()), flush=True)
@@ -928,7 +936,79 @@ def volume_line(args) -> dict:
     }
     if not args.no_bscan:
         out[BSCAN] = bscan_line(args, extra=True)
+        out[SMALL] = small_line()
     return out
+
+
+def small_line(reps: int = 20) -> dict:
+    """The small B-scan (512 x 64, 20 scatterers, 1% noise, l1 lambda = 0.01
+    lambda_max, 50 iterations) is launch-bound: the latency of a whole solve,
+    launched op by op and replayed from a captured HIP graph of the same calls
+    (the replay's result is compared bitwise with the launched solve), and
+    Phi + Phi^H applications per second at this size."""
+    import numpy as np
+    import torch
+    import paper_2108_01438_amd as P
+    import synth
+    pr = synth.preset(SMALL)
+    geom = P.Geometry.from_dict(pr["geom"])
+    rng = np.random.default_rng(0)
+    x_true = synth.scatterers(rng, geom.img_shape, pr["scatterers"])
+    plan = P.Plan(geom)
+    y = plan.forward(torch.from_numpy(x_true.astype(np.complex64)).cuda())
+    noise = torch.from_numpy(rng.standard_normal(tuple(y.shape)).astype(np.float32)).cuda()
+    y = (y + pr["noise"] * float(y.abs().max().item()) * noise).contiguous()
+    lam = pr["lam"] * float(plan.adjoint(y).abs().max().item())
+    delta = 1.0 / (1.05 * plan.lipschitz(50, seed=0))
+    iters = pr["iters"]
+    z = torch.empty(geom.img_shape, dtype=torch.complex64, device="cuda")
+
+    def solve():
+        plan.mbir_solve(y, "l1", lam, iters, delta=delta, x_out=z)
+
+    def latency(fn) -> float:
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) * 1e3
+
+    for _ in range(3):
+        solve()
+    torch.cuda.synchronize()
+    ref = z.clone()
+    ms_eager = latency(solve)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        solve()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        solve()
+    z.zero_()
+    graph.replay()
+    torch.cuda.synchronize()
+    equal = bool(torch.equal(z, ref))
+    ms_graph = latency(graph.replay)
+    ms_grad = time_grad(plan, ref, y, 200)
+    gb = grad_bytes(geom, False)
+    del graph
+    plan.close()
+    return {
+        "workload": "B-scan 512 spectral px x 64 A-scans, 20 scatterers, l1 lambda=0.01 lambda_max, "
+                    "50 iterations per solve",
+        "solve_ms_launched": round(ms_eager, 4), "solve_ms_graph": round(ms_graph, 4),
+        "graph_replay_bitwise_equal": equal,
+        "iters_per_s_launched": round(iters * 1000.0 / ms_eager, 1),
+        "iters_per_s_graph": round(iters * 1000.0 / ms_graph, 1),
+        "phi_phih_ms": round(ms_grad, 5), "phi_phih_per_s": round(1000.0 / ms_grad, 1),
+        "phi_phih_GBps": round(gb / (ms_grad * 1e-3) / 1e9, 1),
+    }
 
 
 def bscan_line(args, extra: bool = False) -> dict:

@@ -197,13 +197,14 @@ def test_fista_exact_resume(pen, kw, masked):
     assert torch.equal(zp, z19)
 
 
-def test_solve_replays_bitwise_from_a_graph():
-    """A whole solve (TV, batch of two) captured in a graph replays bitwise
-    equal to the eager solve, with the caller's own work (zeroing the output)
-    and synchronisation between the replays."""
+@pytest.mark.parametrize("pen", ["tv", "l1", "haar"])
+def test_solve_replays_bitwise_from_a_graph(pen):
+    """A whole solve (batch of two) captured in a graph replays bitwise equal
+    to the eager solve, with the caller's own work (zeroing the output) and
+    synchronisation between the replays."""
     import torch
     import paper_2108_01438_amd as P
-    flush("[fista] graph capture")
+    flush(f"[fista] graph capture, {pen}")
     og, pg = both_geoms(n_depth=128, n_x=48, n_k=128, batch=2)
     rng = np.random.default_rng(12)
     mask = synth.mask_random_exact(rng, (1, og.n_x), og.n_k, og.n_k // 2)
@@ -215,15 +216,15 @@ def test_solve_replays_bitwise_from_a_graph():
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        plan.mbir_solve(yd, "tv", lam, 8, delta=delta, tv_inner=10, x_out=z)   # allocates the solver state
+        plan.mbir_solve(yd, pen, lam, 8, delta=delta, tv_inner=10, x_out=z)   # allocates the solver state
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
-    plan.mbir_solve(yd, "tv", lam, 8, delta=delta, tv_inner=10, x_out=z)
+    plan.mbir_solve(yd, pen, lam, 8, delta=delta, tv_inner=10, x_out=z)
     torch.cuda.synchronize()
     ref = to_host(z).copy()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        plan.mbir_solve(yd, "tv", lam, 8, delta=delta, tv_inner=10, x_out=z)
+        plan.mbir_solve(yd, pen, lam, 8, delta=delta, tv_inner=10, x_out=z)
     for _ in range(3):
         z.zero_()
         torch.cuda.synchronize()
