@@ -187,7 +187,9 @@ oct_status oct_dtcwt_filter(int32_t which, float* h0, int32_t* n);
  * from the top 53 bits), then iters steps of x <- w / ||w||, w = Phi^H Phi x.
  * flags = OCT_SOLVE_PAPER_BACKWARD iterates Phi* Phi instead (Phi* of
  * oct_adjoint_paper; not self-adjoint, ||w|| then tends to its spectral
- * radius); 0 otherwise.  Writes the last ||w|| to *L_out (host).  Synchronous. */
+ * radius); 0 otherwise.  Writes the last ||w|| to *L_out (host).  A w of
+ * zero norm stays zero (Phi = 0 on the plan's mask: nothing observed), so
+ * *L_out is then exactly 0.  Synchronous. */
 oct_status oct_lipschitz(oct_plan_t plan, int32_t iters, uint64_t seed, int32_t flags,
                          double* L_out, void* stream);
 
@@ -207,7 +209,8 @@ typedef struct {
   uint64_t seed;          /* power-iteration start vector seed                    */
   double lambda;          /* regularisation weight (absolute)                     */
   double delta;           /* step size; <= 0 selects 1 / (1.05 L_power), L_power
-                             from oct_lipschitz with these flags                  */
+                             from oct_lipschitz with these flags (L_power = 0:
+                             constant data term, every step admissible: 1)      */
   double bound;           /* modulus bound of the constraint set C of eq. (16)
                              (as in oct_prox; 0 = none)                           */
   const void* x0;         /* device image, start point; NULL = zero               */

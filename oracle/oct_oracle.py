@@ -987,14 +987,19 @@ def lipschitz(g: Geometry, mask=None, iters: int = 50, seed: int = 0, start=None
         else:
             w = adjoint(forward(x, g, mask), g, mask)
         L = float(np.linalg.norm(w))
+        if L == 0.0:
+            # the operator annihilated a random start: Phi = 0 on this mask (no
+            # observed sample), so the norm is 0 and every later iterate is 0
+            return 0.0
         x = w / L
     return L
 
 
 def step_size(L: float) -> float:
     """delta = 1 / (1.05 L): 'appropriately small' (Sec. 2.3) with a margin for
-    the power iteration's underestimate of L."""
-    return 1.0 / (1.05 * L)
+    the power iteration's underestimate of L.  L = 0 (nothing observed) makes
+    the data term constant, so every delta > 0 is admissible: delta = 1."""
+    return 1.0 / (1.05 * L) if L > 0.0 else 1.0
 
 
 # ----------------------------------------------------------------------------

@@ -1228,7 +1228,8 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   if (!(delta > 0)) {
     if (prm->power_iters < 1) return fail(OCT_E_INVALID, "power_iters must be >= 1 when delta <= 0");
     OCTCHK(oct_lipschitz(p, prm->power_iters, prm->seed, prm->flags, &Lest, stream));
-    delta = 1.0 / (1.05 * Lest);
+    // L = 0: nothing observed, the data term is constant and any step is admissible
+    delta = Lest > 0.0 ? 1.0 / (1.05 * Lest) : 1.0;
   }
   const int64_t n = p->n_img();
   // FISTA momenta mu_k = (t_k - 1) / t_{k+1}, t_1 = 1 (FP64)

@@ -63,7 +63,9 @@ __global__ void norm2_kernel(const float2* __restrict__ x, int64_t n, double* pa
 }
 
 __global__ void scale_inv_sqrt_kernel(const float2* __restrict__ x, float2* y, int64_t n, const double* sumsq) {
-  const float sc = (float)(1.0 / sqrt(sumsq[0]));
+  // a zero vector stays zero (the power iteration on Phi = 0 gives L = 0)
+  const double ss = sumsq[0];
+  const float sc = ss > 0.0 ? (float)(1.0 / sqrt(ss)) : 0.f;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = cscale(x[i], sc);
 }

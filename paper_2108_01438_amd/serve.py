@@ -260,7 +260,7 @@ class HipExecutor:
                         L = plan.lipschitz(50, stream=s)
                     with self._lock:
                         self.lipschitz[k] = L
-                delta = 1.0 / (1.05 * L)
+                delta = 1.0 / (1.05 * L) if L > 0 else 1.0   # L = 0: nothing observed, any step
             with torch.cuda.stream(s):
                 y = torch.from_numpy(np.ascontiguousarray(req.y, dtype=np.float32)).pin_memory().to(
                     "cuda", non_blocking=True)

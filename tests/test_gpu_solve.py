@@ -197,6 +197,24 @@ def test_fista_exact_resume(pen, kw, masked):
     assert torch.equal(zp, z19)
 
 
+@pytest.mark.parametrize("pen", ["l1", "tv", "haar"])
+def test_nothing_observed_gives_zero_lipschitz_and_zero_solution(pen):
+    """An all-zero mask makes Phi = 0: the power iteration gives exactly L = 0
+    (as the oracle does), the solve takes the step delta = 1 (every step is
+    admissible for a constant data term) and returns exactly zero."""
+    import paper_2108_01438_amd as P
+    flush(f"[fista] nothing observed, {pen}")
+    og, pg = both_geoms(n_depth=64, n_x=16, n_k=64)
+    mask = np.zeros((1, og.n_x, og.n_k), dtype=np.uint8)
+    plan = P.Plan(pg, mask)
+    assert plan.lipschitz(10) == 0.0 == O.lipschitz(og, mask, iters=10)
+    y = np.random.default_rng(43).standard_normal(O.meas_shape(og)).astype(np.float32)
+    z, info = plan.mbir_solve(to_dev(y), pen, 0.1, 5, haar_levels=2)
+    assert info["lipschitz"] == 0.0 and info["delta"] == 1.0 == O.step_size(0.0)
+    assert np.all(to_host(z) == 0)
+    plan.close()
+
+
 @pytest.mark.parametrize("pen", ["tv", "l1", "haar"])
 def test_solve_replays_bitwise_from_a_graph(pen):
     """A whole solve (batch of two) captured in a graph replays bitwise equal

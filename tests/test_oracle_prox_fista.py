@@ -429,6 +429,23 @@ def test_lambda_max_is_the_zero_solution_threshold():
     assert np.count_nonzero(z) > 0
 
 
+@pytest.mark.parametrize("pen", ["l1", "tv", "haar"])
+def test_nothing_observed_gives_zero_lipschitz_and_zero_solution(pen):
+    """An all-zero mask makes Phi = 0: the power iteration's estimate of
+    ||Phi^H Phi|| is exactly 0, every step size is admissible (delta = 1), and
+    FISTA from zero stays exactly at zero, the minimiser of lambda R(x), for
+    any weight and any (finite) measurements."""
+    g = O.Geometry(n_depth=16, n_x=8, n_k=24)
+    mask = np.zeros((1, 8, 24), dtype=np.uint8)
+    L = O.lipschitz(g, mask, iters=5)
+    assert L == 0.0
+    assert O.step_size(L) == 1.0
+    y = np.random.default_rng(42).standard_normal(O.meas_shape(g))
+    penalty = {"l1": O.PEN_L1, "tv": O.PEN_TV, "haar": O.PEN_HAAR}[pen]
+    z, _ = O.fista(y, g, mask, penalty, 0.1, O.step_size(L), 5, haar_levels=2)
+    assert np.all(z == 0)
+
+
 def test_fista_tv_reduces_objective():
     g, mask, A, y = _dense_problem()
     L = np.linalg.svd(A, compute_uv=False)[0] ** 2
