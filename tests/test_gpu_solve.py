@@ -136,6 +136,35 @@ def test_fista_matches_oracle(name):
     np.testing.assert_allclose(info["objective"], ho, rtol=1e-5)
 
 
+def test_zero_weight_runs_the_same_least_squares_iteration_for_every_penalty():
+    """lambda = 0 takes the penalty out of eq. (15): the l1 prox (threshold 0),
+    the TV prox (no TV term) and the Haar prox (threshold 0 in an orthonormal
+    basis) leave v as it is, so the three solves run FISTA on the data term
+    alone: all match the oracle's iteration, and each other to rounding (on a
+    B-scan the l1 solve fuses the gradient step, prox and next lateral pass
+    into one kernel; TV and Haar run them as separate passes)."""
+    import paper_2108_01438_amd as P
+    flush("[fista] lambda = 0")
+    og, pg = both_geoms(n_depth=128, n_x=48, n_k=128)
+    rng = np.random.default_rng(44)
+    mask = synth.mask_random_exact(rng, (1, og.n_x), og.n_k, og.n_k // 2)
+    _, y = _problem(og, rng, 20, mask)
+    y32 = y.astype(np.float32)
+    delta = O.step_size(O.lipschitz(og, mask, iters=50))
+    zo, _ = O.fista(y32.astype(np.float64), og, mask, O.PEN_L1, 0.0, delta, 20)
+    plan = P.Plan(pg, mask)
+    zs = {}
+    for pen in ("l1", "tv", "haar"):
+        z, _ = plan.mbir_solve(to_dev(y32), pen, 0.0, 20, delta=delta, haar_levels=3)
+        zs[pen] = to_host(z)
+        err = rel(zs[pen], zo)
+        print(f"[fista] lambda = 0, {pen}: rel err vs oracle {err:.3e}")
+        assert err <= SOLVE_TOL
+    assert rel(zs["tv"], zs["l1"]) <= 1e-5
+    assert rel(zs["haar"], zs["l1"]) <= 1e-5
+    plan.close()
+
+
 def test_fista_power_iteration_step():
     """delta <= 0: the solver runs the power iteration itself."""
     import paper_2108_01438_amd as P

@@ -328,6 +328,24 @@ def test_fista_equals_dense_matrix_fista(pen):
     assert np.max(np.abs(z - zd)) < 1e-12 * max(1.0, np.max(np.abs(zd)))
 
 
+@pytest.mark.parametrize("pen", [O.PEN_L1, O.PEN_TV, O.PEN_HAAR])
+def test_zero_weight_fista_is_the_dense_least_squares_iteration(pen):
+    """lambda = 0: every penalty's prox is the identity, so the oracle's FISTA
+    is the dense-matrix iteration on 1/2 ||A x - y||^2 with no prox at all."""
+    g, mask, A, y = _dense_problem()
+    g = g.with_(n_x=8)
+    rng = np.random.default_rng(13)
+    mask = (rng.random((1, 8, 12)) < 0.8).astype(np.uint8)
+    n = int(np.prod(O.img_shape(g)))
+    A = np.array([O.forward((np.eye(n)[j] * u).reshape(O.img_shape(g)), g, mask).ravel()
+                  for u in (1.0, 1j) for j in range(n)]).T
+    y = (A @ rng.standard_normal(2 * n)).reshape(O.meas_shape(g))
+    delta = 1 / (1.05 * np.linalg.svd(A, compute_uv=False)[0] ** 2)
+    z, _ = O.fista(y, g, mask, pen, 0.0, delta, 30, haar_levels=3)
+    zd = _dense_fista(A, y, O.img_shape(g), lambda v: v, delta, 30)
+    assert np.max(np.abs(z - zd)) < 1e-12 * max(1.0, np.max(np.abs(zd)))
+
+
 def test_fista_l1_kkt_and_rate():
     """Long-run l1 FISTA satisfies the KKT conditions (|g_i| <= lam off the
     support, g_i = -lam z_i/|z_i| on it) and the O(1/k^2) bound of Beck and
