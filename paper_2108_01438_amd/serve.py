@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import hashlib
 import threading
 import time
 from concurrent.futures import Future
@@ -200,8 +201,12 @@ class HipExecutor:
 
     @staticmethod
     def key(req: Request):
+        """Pool key: the geometry and a 256-bit digest of the mask (a plan is
+        reused only for the same geometry and the same mask bytes)."""
         g = req.geom
-        mk = None if req.mask is None else hash(np.ascontiguousarray(req.mask).tobytes())
+        mk = None
+        if req.mask is not None:
+            mk = hashlib.blake2b(np.ascontiguousarray(req.mask, dtype=np.uint8).tobytes(), digest_size=32).digest()
         return (dataclasses.astuple(g), mk)
 
     def footprint(self, req: Request) -> int:
