@@ -123,15 +123,23 @@ __device__ __forceinline__ void adj_cell_taps2(const float* __restrict__ kbc, co
 }
 
 // Filter H(m, q) = beam(q) e^{j(-2 k_m z_f + Omega_m)} e^{j beta (z_f - n_c dz)}.
-// ph = a.phase[m] (read by the caller, batched with the sample's other loads)
+// ph = a.phase[m] (read by the caller, batched with the sample's other loads).
+// The defocus phase beta (z_f - n_c dz) is reduced modulo 2 pi in FP64 (to
+// ~1e-11 rad for phases up to 1e5 rad; the depth range bounds them near 4e4)
+// and then taken with the FP32 sine and cosine: ~3e-7 in H, and far fewer
+// registers than the FP64 sincos, whose large-argument path would otherwise
+// set the kernels' register count.
 __device__ __forceinline__ float2 filter_h(const NufftArgs& a, float2 ph, float bq, double beta) {
   float2 h = ph;
   h.x *= bq;
   h.y *= bq;
   if (a.df != 0.0) {
-    double sn, cs;
-    sincos(beta * a.df, &sn, &cs);
-    h = cmul(h, make_float2((float)cs, (float)sn));
+    constexpr double two_pi = 6.283185307179586, inv_two_pi = 0.15915494309189535;
+    const double phase = beta * a.df;
+    const float r = (float)fma(-rint(phase * inv_two_pi), two_pi, phase);
+    float sn, cs;
+    sincosf(r, &sn, &cs);
+    h = cmul(h, make_float2(cs, sn));
   }
   return h;
 }
