@@ -233,6 +233,43 @@ int main() {
   }
   run_geometry(base_geom(2, 128, 16, 16, 128, 1), nullptr, rng, "volume 128 x 16 x 16");
   {
+    // nothing observed (all-zero mask): Phi = 0, the power iteration gives
+    // exactly 0, a solve without a step size takes delta = 1 and returns 0
+    const oct_geometry g = base_geom(1, 64, 16, 1, 64, 1);
+    const std::vector<uint8_t> none((size_t)g.n_x * g.n_k, 0);
+    oct_plan_t p = nullptr;
+    ok(oct_plan_create(&g, none.data(), &p), "plan_create (nothing observed)");
+    if (p) {
+      const size_t n_img = (size_t)g.n_x * g.n_depth, n_meas = (size_t)g.n_x * g.n_k;
+      float* y = dev_fill<float>(n_meas, rng);
+      float2* z = dev_fill<float2>(n_img, rng);
+      double L = -1.0;
+      ok(oct_lipschitz(p, 5, 1, 0, &L, nullptr), "lipschitz (nothing observed)");
+      expect(L == 0.0, "lipschitz is exactly 0 when nothing is observed");
+      for (int pen : {OCT_PEN_L1, OCT_PEN_TV, OCT_PEN_HAAR}) {
+        oct_solve_params prm{};
+        prm.penalty = pen;
+        prm.iters = 4;
+        prm.tv_inner = 5;
+        prm.haar_levels = 2;
+        prm.power_iters = 5;
+        prm.lambda = 1e-2;
+        prm.delta = 0.0;
+        oct_solve_report rep{};
+        ok(oct_mbir_solve(p, y, &prm, z, &rep, nullptr), "solve (nothing observed)");
+        expect(rep.lipschitz_est == 0.0 && rep.delta_used == 1.0, "nothing observed: L = 0, delta = 1");
+        std::vector<float> h(2 * n_img);
+        hipMemcpy(h.data(), z, h.size() * sizeof(float), hipMemcpyDeviceToHost);
+        bool zero = true;
+        for (float v : h) zero = zero && v == 0.f;
+        expect(zero, "nothing observed: the solution is exactly zero");
+      }
+      hipFree(y);
+      hipFree(z);
+      ok(oct_plan_destroy(p), "plan_destroy (nothing observed)");
+    }
+  }
+  {
     // released plan memory is reused by the next plan
     oct_plan_t p = nullptr;
     ok(oct_plan_create(&gb, nullptr, &p), "plan_create (release)");
