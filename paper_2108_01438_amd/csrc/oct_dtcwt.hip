@@ -639,6 +639,64 @@ __global__ void sfb3_kernel(Dt3Geom g, DtJobs8 J) {
   }
 }
 
+// Lateral synthesis of the volume along x (AXIS 1) or y (AXIS 2), tiled as
+// sfb_lateral_tiled: a block stages, for 64 depth lanes, the low- and
+// high-band rows that its TS outputs along the axis read, and every output
+// takes its taps from LDS.  Per output, sfb3_kernel fetches one input row per
+// tap; rows 16 KB (x) or n_x n_z samples (y) apart are not reused through the
+// caches, so each input came from memory about once per tap.  The per-tree
+// sums are formed and added in sfb3_kernel's order, so the result is the same
+// bit for bit.  blockIdx.z = tile + tiles * (the other lateral index: y for x
+// lines, x for y lines); the batch runs inside.
+template <int AXIS, bool ACC>
+__global__ void __launch_bounds__(256) sfb3_lateral_tiled(Dt3Geom g, DtJobs8 J) {
+  static_assert(AXIS == 1 || AXIS == 2, "lateral axes only");
+  constexpr int TS = 32;
+  constexpr int NS = ACC ? 2 : 1;
+  constexpr int CNT = (TS + DT_MAXT) / 2 + 1;
+  __shared__ float2 lo_s[NS][CNT * DT_LANES], hi_s[NS][CNT * DT_LANES];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int len = AXIS == 1 ? g.nx : g.ny;
+  const int h = len / 2;
+  const int tiles = (len + TS - 1) / TS;
+  const int tile = (int)(blockIdx.z % tiles), other = (int)(blockIdx.z / tiles);
+  const int n0 = blockIdx.x * DT_LANES, m0 = tile * TS;
+  const int j = blockIdx.y * NS;
+  const int stride = AXIS == 1 ? g.NZ : g.NX * g.NZ;
+  for (int b = 0; b < g.B; ++b) {
+    const int64_t item = AXIS == 1 ? (((int64_t)b * g.NY + other) * g.NX) * g.NZ
+                                   : ((int64_t)b * g.NY * g.NX + other) * g.NZ;
+    const int taps = NS == 2 ? max(J.f[j].n, J.f[j + 1].n) : J.f[j].n;   // rows staged for every job
+    const int ibase = (m0 - taps + 1) >> 1;
+    const int cnt = (m0 + TS - 1 - ((m0 - taps + 1) & ~1)) / 2 + 1;
+    if (b > 0) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      dt_stage(J.src[j + q], item, stride, h, ibase, cnt, n0, g.nz, 0, lo_s[q]);
+      dt_stage(J.src[j + q], item, stride, h, ibase, cnt, n0, g.nz, h, hi_s[q]);
+    }
+    __syncthreads();
+    const int n = n0 + lane;
+    for (int r = 0; r < TS / 4; ++r) {
+      const int m = m0 + w * (TS / 4) + r;
+      if (m >= len || n >= g.nz) continue;
+      float2 v = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const DtFilt& f = J.f[j + q];
+        float2 x = make_float2(0.f, 0.f);
+        for (int t = m & 1; t < f.n; t += 2) {
+          const int row = ((m - t) >> 1) - ibase;
+          fma2(x, f.h0[t], lo_s[q][row * DT_LANES + lane]);
+          fma2(x, f.h1[t], hi_s[q][row * DT_LANES + lane]);
+        }
+        v = q == 0 ? x : make_float2(v.x + x.x, v.y + x.y);
+      }
+      J.dst[j][item + (int64_t)m * stride + n] = make_float2(J.scale * v.x, J.scale * v.y);
+    }
+  }
+}
+
 // y analysis of all eight trees in one thread with the level's detail bands
 // combined and shrunk (or summed) on the spot, as afb_lateral4_kernel.
 template <bool SHRINK>
@@ -788,6 +846,21 @@ size_t dtcwt_work_elems(const ProxGeom& pg) {
   return (pg.lateral_dims == 2 ? 24 : 8) * n;
 }
 
+// Lateral synthesis pass of the volume: the tiled kernel, or the per-tap one
+// when the tiles and the other lateral index exceed the grid's z range.
+template <int AXIS, bool ACC>
+void sfb3_lateral(const Dt3Geom& g, const DtJobs8& J, int jobs, hipStream_t s) {
+  const int len = AXIS == 1 ? g.nx : g.ny, other = AXIS == 1 ? g.ny : g.nx;
+  const int64_t zb = (int64_t)((len + 31) / 32) * other;
+  if (zb > 65535 || (int64_t)g.NX * g.NZ > INT32_MAX) {
+    const int64_t nn = (int64_t)g.B * g.ny * g.nx * g.nz;
+    hipLaunchKernelGGL((sfb3_kernel<AXIS, ACC>), dim3(dt_grid_y(nn, jobs), jobs), dim3(256), 0, s, g, J);
+    return;
+  }
+  hipLaunchKernelGGL((sfb3_lateral_tiled<AXIS, ACC>), dim3((unsigned)((g.nz + DT_LANES - 1) / DT_LANES), jobs, (unsigned)zb),
+                     dim3(256), 0, s, g, J);
+}
+
 hipError_t launch_prox_dtcwt3(const ProxGeom& pg, int levels, const float2* v, float2* z, float tau, float2* work,
                               hipStream_t s) {
   const int64_t n = (int64_t)pg.B * pg.Ny * pg.Nx * pg.Nz;
@@ -818,8 +891,8 @@ hipError_t launch_prox_dtcwt3(const ProxGeom& pg, int levels, const float2* v, f
         jz.dst[t] = w.tree[t];
         jz.f[t] = fs[t >> 2];
       }
-      hipLaunchKernelGGL((sfb3_kernel<2, false>), dim3(dt_grid_y(nn, 8), 8), dim3(256), 0, s, gl, jy);
-      hipLaunchKernelGGL((sfb3_kernel<1, false>), dim3(dt_grid_y(nn, 8), 8), dim3(256), 0, s, gl, jx);
+      sfb3_lateral<2, false>(gl, jy, 8, s);
+      sfb3_lateral<1, false>(gl, jx, 8, s);
       hipLaunchKernelGGL((sfb3_kernel<0, false>), dim3(dt_grid_y(nn, 8), 8), dim3(256), 0, s, gl, jz);
     } else {
       // y: trees (p, ty = a) + (p, ty = b) -> S[2q], p = 4 tz + 2 tx = 2q; x: S[4 tz] + S[4 tz + 2] -> U[tz];
@@ -840,8 +913,8 @@ hipError_t launch_prox_dtcwt3(const ProxGeom& pg, int levels, const float2* v, f
       jz.f[0] = fs[0];
       jz.f[1] = fs[1];
       jz.scale = 0.125f;
-      hipLaunchKernelGGL((sfb3_kernel<2, true>), dim3(dt_grid_y(nn, 4), 4), dim3(256), 0, s, gl, jy);
-      hipLaunchKernelGGL((sfb3_kernel<1, true>), dim3(dt_grid_y(nn, 2), 2), dim3(256), 0, s, gl, jx);
+      sfb3_lateral<2, true>(gl, jy, 4, s);
+      sfb3_lateral<1, true>(gl, jx, 2, s);
       hipLaunchKernelGGL((sfb3_kernel<0, true>), dim3(dt_grid_y(nn, 1), 1), dim3(256), 0, s, gl, jz);
     }
   }
