@@ -697,6 +697,78 @@ __global__ void __launch_bounds__(256) sfb3_lateral_tiled(Dt3Geom g, DtJobs8 J) 
   }
 }
 
+// The same lateral synthesis with a sliding register window instead of LDS:
+// outputs 2p and 2p + 1 read the same NT/2 rows i = p - NT/2 + 1 .. p of each
+// band, so a thread that walks RP output pairs along the axis (one depth
+// lane, one position of the other lateral axis) loads every row once, plus
+// NT/2 - 1 rows at the start of its run, with no LDS and no barrier.  Window
+// slots are fixed at compile time (the walk is unrolled).  Taps are applied
+// in sfb_line's order and the per-tree sums added as in sfb3_kernel: the same
+// result bit for bit.
+template <int AXIS, bool ACC, int NT>
+__global__ void __launch_bounds__(256) sfb3_window(Dt3Geom g, DtJobs8 J) {
+  static_assert(AXIS == 1 || AXIS == 2, "lateral axes only");
+  constexpr int W = NT / 2, RP = 16;
+  constexpr int NS = ACC ? 2 : 1;
+  const int j = blockIdx.y * NS;
+  const int len = AXIS == 1 ? g.nx : g.ny, h = len / 2;
+  const int others = AXIS == 1 ? g.ny : g.nx;
+  const int runs = (h + RP - 1) / RP;
+  const int64_t stride = AXIS == 1 ? (int64_t)g.NZ : (int64_t)g.NX * g.NZ;
+  const int64_t total = (int64_t)g.B * others * runs * g.nz;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(t % g.nz);
+    int64_t r = t / g.nz;
+    const int run = (int)(r % runs);
+    r /= runs;
+    const int other = (int)(r % others);
+    const int b = (int)(r / others);
+    const int64_t item = (AXIS == 1 ? (((int64_t)b * g.NY + other) * g.NX) * g.NZ
+                                    : ((int64_t)b * g.NY * g.NX + other) * g.NZ) + n;
+    const int p0 = run * RP;
+    // slot u % W holds band row p0 - W + 1 + u (mod h)
+    float2 lo[NS][W], hi[NS][W];
+#pragma unroll
+    for (int u = 0; u < W - 1; ++u) {
+      int i = (p0 - W + 1 + u) % h;
+      if (i < 0) i += h;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        lo[q][u % W] = J.src[j + q][item + (int64_t)i * stride];
+        hi[q][u % W] = J.src[j + q][item + (int64_t)(h + i) * stride];
+      }
+    }
+#pragma unroll
+    for (int sp = 0; sp < RP; ++sp) {
+      const int p = p0 + sp;
+      if (p < h) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          lo[q][(W - 1 + sp) % W] = J.src[j + q][item + (int64_t)p * stride];
+          hi[q][(W - 1 + sp) % W] = J.src[j + q][item + (int64_t)(h + p) * stride];
+        }
+#pragma unroll
+        for (int odd = 0; odd < 2; ++odd) {
+          float2 v = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int q = 0; q < NS; ++q) {
+            const DtFilt& f = J.f[j + q];
+            float2 x = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int k = odd; k < NT; k += 2) {
+              const int slot = (W - 1 + sp - (k >> 1)) % W;
+              fma2(x, f.h0[k], lo[q][slot]);
+              fma2(x, f.h1[k], hi[q][slot]);
+            }
+            v = q == 0 ? x : make_float2(v.x + x.x, v.y + x.y);
+          }
+          J.dst[j][item + (int64_t)(2 * p + odd) * stride] = make_float2(J.scale * v.x, J.scale * v.y);
+        }
+      }
+    }
+  }
+}
+
 // y analysis of all eight trees in one thread with the level's detail bands
 // combined and shrunk (or summed) on the spot, as afb_lateral4_kernel.
 template <bool SHRINK>
@@ -850,6 +922,19 @@ size_t dtcwt_work_elems(const ProxGeom& pg) {
 // when the tiles and the other lateral index exceed the grid's z range.
 template <int AXIS, bool ACC>
 void sfb3_lateral(const Dt3Geom& g, const DtJobs8& J, int jobs, hipStream_t s) {
+  // every filter of the launch with 8 or 12 taps: the register window
+  const int nt = J.f[0].n;
+  bool same = true;
+  for (int q = 0; q < jobs * (ACC ? 2 : 1); ++q) same = same && J.f[q].n == nt;
+  if (same && (nt == 8 || nt == 12)) {
+    const int len = AXIS == 1 ? g.nx : g.ny, others = AXIS == 1 ? g.ny : g.nx;
+    const int64_t total = (int64_t)g.B * others * ((len / 2 + 15) / 16) * g.nz;
+    if (nt == 8)
+      hipLaunchKernelGGL((sfb3_window<AXIS, ACC, 8>), dim3(dt_grid_y(total, jobs), jobs), dim3(256), 0, s, g, J);
+    else
+      hipLaunchKernelGGL((sfb3_window<AXIS, ACC, 12>), dim3(dt_grid_y(total, jobs), jobs), dim3(256), 0, s, g, J);
+    return;
+  }
   const int len = AXIS == 1 ? g.nx : g.ny, other = AXIS == 1 ? g.ny : g.nx;
   const int64_t zb = (int64_t)((len + 31) / 32) * other;
   if (zb > 65535 || (int64_t)g.NX * g.NZ > INT32_MAX) {
