@@ -812,6 +812,135 @@ __global__ void afb3_y8_kernel(Dt3Geom g, DtJobs8 J, float tau2, double* partial
   }
 }
 
+// The first level's y analysis with a sliding register window: there the
+// eight trees read four sources (trees 2q and 2q + 1 filter the same staging
+// buffer with the two filters), and output i reads rows 2i .. 2i + NT - 1,
+// so a thread walking RP outputs along y (one depth lane, one x) keeps NT
+// rows of each source in registers and loads two new rows per output.  Taps
+// in afb_line's order: the coefficients, and every value written, are those
+// of afb3_y8_kernel bit for bit (the value pass's FP64 partial sums add the
+// same terms in another order).
+template <bool SHRINK, int NT>
+__global__ void __launch_bounds__(256) afb3_y8_window(Dt3Geom g, DtJobs8 J, float tau2, double* partial) {
+  constexpr int RP = 16;
+  __shared__ double sh[16];
+  const int len = g.ny, h = g.ny / 2, hx = g.nx / 2, hz = g.nz / 2;
+  const int runs = (h + RP - 1) / RP;
+  const int64_t total = (int64_t)g.B * runs * g.nx * g.nz;
+  const int64_t stride = (int64_t)g.NX * g.NZ;
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(t % g.nz);
+    int64_t r = t / g.nz;
+    const int x = (int)(r % g.nx);
+    r /= g.nx;
+    const int run = (int)(r % runs);
+    const int b = (int)(r / runs);
+    const int64_t base = dt3_off(g, b, 0, x, n);
+    const int i0 = run * RP;
+    const bool low3 = n < hz && x < hx;   // y-low output of the all-low band continues to the next level
+    // slot u % NT holds row (2 i0 + u) mod len of source q (trees 2q, 2q + 1)
+    float2 win[4][NT];
+#pragma unroll
+    for (int u = 0; u < NT - 2; ++u) {
+      const int row = (2 * i0 + u) % len;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) win[q][u % NT] = J.src[2 * q][base + (int64_t)row * stride];
+    }
+#pragma unroll
+    for (int si = 0; si < RP; ++si) {
+      const int i = i0 + si;
+      if (i < h) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int u = 2 * si + NT - 2 + e;
+          const int row = (2 * i0 + u) % len;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) win[q][u % NT] = J.src[2 * q][base + (int64_t)row * stride];
+        }
+        float2 lo[8], hi[8];
+#pragma unroll
+        for (int k8 = 0; k8 < 8; ++k8) {
+          const DtFilt& f = J.f[k8];
+          lo[k8] = make_float2(0.f, 0.f);
+          hi[k8] = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int k = 0; k < NT; ++k) {
+            const float2 v = win[k8 >> 1][(2 * si + k) % NT];
+            fma2(lo[k8], f.h0[k], v);
+            fma2(hi[k8], f.h1[k], v);
+          }
+        }
+        if (!low3) dt3_group<SHRINK>(lo, tau2, acc);
+        dt3_group<SHRINK>(hi, tau2, acc);
+#pragma unroll
+        for (int k8 = 0; k8 < 8; ++k8) {
+          if (SHRINK || low3) J.dst[k8][base + (int64_t)i * stride] = lo[k8];
+          if (SHRINK) J.dst[k8][base + (int64_t)(h + i) * stride] = hi[k8];
+        }
+      }
+    }
+  }
+  if (!SHRINK) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+      partial[blockIdx.x] = s;
+    }
+  }
+}
+
+// x analysis with a sliding register window (one job per blockIdx.y, one
+// source and one filter each): output i reads rows 2i .. 2i + NT - 1.
+template <int NT>
+__global__ void __launch_bounds__(256) afb3_x_window(Dt3Geom g, DtJobs8 J) {
+  constexpr int RP = 16;
+  const int j = blockIdx.y;
+  const DtFilt& f = J.f[j];
+  const int len = g.nx, h = g.nx / 2;
+  const int runs = (h + RP - 1) / RP;
+  const int64_t total = (int64_t)g.B * g.ny * runs * g.nz;
+  const int64_t stride = g.NZ;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(t % g.nz);
+    int64_t r = t / g.nz;
+    const int run = (int)(r % runs);
+    r /= runs;
+    const int y = (int)(r % g.ny);
+    const int b = (int)(r / g.ny);
+    const int64_t base = dt3_off(g, b, y, 0, n);
+    const int i0 = run * RP;
+    float2 win[NT];
+#pragma unroll
+    for (int u = 0; u < NT - 2; ++u) win[u % NT] = J.src[j][base + (int64_t)((2 * i0 + u) % len) * stride];
+#pragma unroll
+    for (int si = 0; si < RP; ++si) {
+      const int i = i0 + si;
+      if (i < h) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int u = 2 * si + NT - 2 + e;
+          win[u % NT] = J.src[j][base + (int64_t)((2 * i0 + u) % len) * stride];
+        }
+        float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+          const float2 v = win[(2 * si + k) % NT];
+          fma2(lo, f.h0[k], v);
+          fma2(hi, f.h1[k], v);
+        }
+        J.dst[j][base + (int64_t)i * stride] = lo;
+        J.dst[j][base + (int64_t)(h + i) * stride] = hi;
+      }
+    }
+  }
+}
+
 // Workspace of the volume transform: 8 trees, then staging buffers S (8) and
 // U (8), one image each.
 struct Dt3Work {
@@ -876,11 +1005,31 @@ hipError_t dt3_analysis(const Dt3Geom& g0, int levels, const float2* v, const Dt
     const int64_t nzw = (int64_t)g.B * g.ny * g.nx * (g.nz / 2), nxw = (int64_t)g.B * g.ny * (g.nx / 2) * g.nz;
     const int64_t nyw = (int64_t)g.B * (g.ny / 2) * g.nx * g.nz;
     hipLaunchKernelGGL(afb3_kernel<0>, dim3(dt_grid_y(nzw, nz_jobs), nz_jobs), dim3(256), 0, s, g, jz);
-    hipLaunchKernelGGL(afb3_kernel<1>, dim3(dt_grid_y(nxw, nx_jobs), nx_jobs), dim3(256), 0, s, g, jx);
-    if (mode == 0) {
-      hipLaunchKernelGGL((afb3_y8_kernel<true>), dim3(dt_grid(nyw)), dim3(256), 0, s, g, jy, tau2, nullptr);
+    // x: register-window kernel for the 8- and 12-tap filters
+    const int ntx = jx.f[0].n;
+    bool xw = ntx == 8 || ntx == 12;
+    for (int q = 0; q < nx_jobs; ++q) xw = xw && jx.f[q].n == ntx;
+    if (xw) {
+      const int64_t tw = (int64_t)g.B * g.ny * ((g.nx / 2 + 15) / 16) * g.nz;
+      if (ntx == 8)
+        hipLaunchKernelGGL(afb3_x_window<8>, dim3(dt_grid_y(tw, nx_jobs), nx_jobs), dim3(256), 0, s, g, jx);
+      else
+        hipLaunchKernelGGL(afb3_x_window<12>, dim3(dt_grid_y(tw, nx_jobs), nx_jobs), dim3(256), 0, s, g, jx);
     } else {
-      hipLaunchKernelGGL((afb3_y8_kernel<false>), dim3(dt_grid(nyw)), dim3(256), 0, s, g, jy, 0.f, partial);
+      hipLaunchKernelGGL(afb3_kernel<1>, dim3(dt_grid_y(nxw, nx_jobs), nx_jobs), dim3(256), 0, s, g, jx);
+    }
+    // y: at the first level the trees read four sources with two 8-tap filters: register window
+    const bool yw = lev == 0 && fs[0].n == 8 && fs[1].n == 8;
+    if (mode == 0) {
+      if (yw)
+        hipLaunchKernelGGL((afb3_y8_window<true, 8>), dim3(dt_grid(nyw)), dim3(256), 0, s, g, jy, tau2, nullptr);
+      else
+        hipLaunchKernelGGL((afb3_y8_kernel<true>), dim3(dt_grid(nyw)), dim3(256), 0, s, g, jy, tau2, nullptr);
+    } else {
+      if (yw)
+        hipLaunchKernelGGL((afb3_y8_window<false, 8>), dim3(dt_grid(nyw)), dim3(256), 0, s, g, jy, 0.f, partial);
+      else
+        hipLaunchKernelGGL((afb3_y8_kernel<false>), dim3(dt_grid(nyw)), dim3(256), 0, s, g, jy, 0.f, partial);
       partial += dt_grid(nyw);
     }
     g.ny /= 2;
