@@ -166,6 +166,11 @@ __device__ __forceinline__ void dt_group(float2 (&w)[4], float tau2, double& acc
 // (The analysis stays untiled: measured faster, its taps hit the caches.)
 constexpr int DT_LANES = 64;
 
+// Threads a register-window pass needs before it replaces the per-tap kernel
+// (about four workgroups per CU): below that the walk along the axis leaves
+// too few threads, and the per-tap kernel's rows fit the caches anyway.
+constexpr int64_t DT_WINDOW_MIN_THREADS = (int64_t)1 << 18;
+
 __device__ __forceinline__ void dt_stage(const float2* __restrict__ src, int64_t item, int NZ, int n, int base,
                                          int nrows, int n0, int nz, int rowoff, float2* __restrict__ lds) {
   for (int e = threadIdx.x; e < nrows * DT_LANES; e += blockDim.x) {
@@ -639,67 +644,12 @@ __global__ void sfb3_kernel(Dt3Geom g, DtJobs8 J) {
   }
 }
 
-// Lateral synthesis of the volume along x (AXIS 1) or y (AXIS 2), tiled as
-// sfb_lateral_tiled: a block stages, for 64 depth lanes, the low- and
-// high-band rows that its TS outputs along the axis read, and every output
-// takes its taps from LDS.  Per output, sfb3_kernel fetches one input row per
-// tap; rows 16 KB (x) or n_x n_z samples (y) apart are not reused through the
-// caches, so each input came from memory about once per tap.  The per-tree
-// sums are formed and added in sfb3_kernel's order, so the result is the same
-// bit for bit.  blockIdx.z = tile + tiles * (the other lateral index: y for x
-// lines, x for y lines); the batch runs inside.
-template <int AXIS, bool ACC>
-__global__ void __launch_bounds__(256) sfb3_lateral_tiled(Dt3Geom g, DtJobs8 J) {
-  static_assert(AXIS == 1 || AXIS == 2, "lateral axes only");
-  constexpr int TS = 32;
-  constexpr int NS = ACC ? 2 : 1;
-  constexpr int CNT = (TS + DT_MAXT) / 2 + 1;
-  __shared__ float2 lo_s[NS][CNT * DT_LANES], hi_s[NS][CNT * DT_LANES];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int len = AXIS == 1 ? g.nx : g.ny;
-  const int h = len / 2;
-  const int tiles = (len + TS - 1) / TS;
-  const int tile = (int)(blockIdx.z % tiles), other = (int)(blockIdx.z / tiles);
-  const int n0 = blockIdx.x * DT_LANES, m0 = tile * TS;
-  const int j = blockIdx.y * NS;
-  const int stride = AXIS == 1 ? g.NZ : g.NX * g.NZ;
-  for (int b = 0; b < g.B; ++b) {
-    const int64_t item = AXIS == 1 ? (((int64_t)b * g.NY + other) * g.NX) * g.NZ
-                                   : ((int64_t)b * g.NY * g.NX + other) * g.NZ;
-    const int taps = NS == 2 ? max(J.f[j].n, J.f[j + 1].n) : J.f[j].n;   // rows staged for every job
-    const int ibase = (m0 - taps + 1) >> 1;
-    const int cnt = (m0 + TS - 1 - ((m0 - taps + 1) & ~1)) / 2 + 1;
-    if (b > 0) __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-      dt_stage(J.src[j + q], item, stride, h, ibase, cnt, n0, g.nz, 0, lo_s[q]);
-      dt_stage(J.src[j + q], item, stride, h, ibase, cnt, n0, g.nz, h, hi_s[q]);
-    }
-    __syncthreads();
-    const int n = n0 + lane;
-    for (int r = 0; r < TS / 4; ++r) {
-      const int m = m0 + w * (TS / 4) + r;
-      if (m >= len || n >= g.nz) continue;
-      float2 v = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int q = 0; q < NS; ++q) {
-        const DtFilt& f = J.f[j + q];
-        float2 x = make_float2(0.f, 0.f);
-        for (int t = m & 1; t < f.n; t += 2) {
-          const int row = ((m - t) >> 1) - ibase;
-          fma2(x, f.h0[t], lo_s[q][row * DT_LANES + lane]);
-          fma2(x, f.h1[t], hi_s[q][row * DT_LANES + lane]);
-        }
-        v = q == 0 ? x : make_float2(v.x + x.x, v.y + x.y);
-      }
-      J.dst[j][item + (int64_t)m * stride + n] = make_float2(J.scale * v.x, J.scale * v.y);
-    }
-  }
-}
-
-// The same lateral synthesis with a sliding register window instead of LDS:
-// outputs 2p and 2p + 1 read the same NT/2 rows i = p - NT/2 + 1 .. p of each
-// band, so a thread that walks RP output pairs along the axis (one depth
+// Lateral synthesis of the volume along x (AXIS 1) or y (AXIS 2) with a
+// sliding register window.  Per output, sfb3_kernel fetches one input row per
+// tap; rows 16 KB (x) or n_x n_z samples (y) apart are not held by the caches
+// between neighbouring outputs, so each input came from memory about once per
+// tap.  Outputs 2p and 2p + 1 read the same NT/2 rows i = p - NT/2 + 1 .. p of
+// each band, so a thread that walks RP output pairs along the axis (one depth
 // lane, one position of the other lateral axis) loads every row once, plus
 // NT/2 - 1 rows at the start of its run, with no LDS and no barrier.  Window
 // slots are fixed at compile time (the walk is unrolled).  Taps are applied
@@ -1007,10 +957,10 @@ hipError_t dt3_analysis(const Dt3Geom& g0, int levels, const float2* v, const Dt
     hipLaunchKernelGGL(afb3_kernel<0>, dim3(dt_grid_y(nzw, nz_jobs), nz_jobs), dim3(256), 0, s, g, jz);
     // x: register-window kernel for the 8- and 12-tap filters
     const int ntx = jx.f[0].n;
-    bool xw = ntx == 8 || ntx == 12;
+    const int64_t tw = (int64_t)g.B * g.ny * ((g.nx / 2 + 15) / 16) * g.nz;
+    bool xw = (ntx == 8 || ntx == 12) && tw >= DT_WINDOW_MIN_THREADS;
     for (int q = 0; q < nx_jobs; ++q) xw = xw && jx.f[q].n == ntx;
     if (xw) {
-      const int64_t tw = (int64_t)g.B * g.ny * ((g.nx / 2 + 15) / 16) * g.nz;
       if (ntx == 8)
         hipLaunchKernelGGL(afb3_x_window<8>, dim3(dt_grid_y(tw, nx_jobs), nx_jobs), dim3(256), 0, s, g, jx);
       else
@@ -1019,7 +969,8 @@ hipError_t dt3_analysis(const Dt3Geom& g0, int levels, const float2* v, const Dt
       hipLaunchKernelGGL(afb3_kernel<1>, dim3(dt_grid_y(nxw, nx_jobs), nx_jobs), dim3(256), 0, s, g, jx);
     }
     // y: at the first level the trees read four sources with two 8-tap filters: register window
-    const bool yw = lev == 0 && fs[0].n == 8 && fs[1].n == 8;
+    const bool yw = lev == 0 && fs[0].n == 8 && fs[1].n == 8 &&
+                    (int64_t)g.B * ((g.ny / 2 + 15) / 16) * g.nx * g.nz >= DT_WINDOW_MIN_THREADS;
     if (mode == 0) {
       if (yw)
         hipLaunchKernelGGL((afb3_y8_window<true, 8>), dim3(dt_grid(nyw)), dim3(256), 0, s, g, jy, tau2, nullptr);
@@ -1067,32 +1018,24 @@ size_t dtcwt_work_elems(const ProxGeom& pg) {
   return (pg.lateral_dims == 2 ? 24 : 8) * n;
 }
 
-// Lateral synthesis pass of the volume: the tiled kernel, or the per-tap one
-// when the tiles and the other lateral index exceed the grid's z range.
+// Lateral synthesis pass of the volume: the register-window kernel for the 8-
+// and 12-tap filters on large enough sub-arrays, else the per-tap one.
 template <int AXIS, bool ACC>
 void sfb3_lateral(const Dt3Geom& g, const DtJobs8& J, int jobs, hipStream_t s) {
-  // every filter of the launch with 8 or 12 taps: the register window
   const int nt = J.f[0].n;
   bool same = true;
   for (int q = 0; q < jobs * (ACC ? 2 : 1); ++q) same = same && J.f[q].n == nt;
-  if (same && (nt == 8 || nt == 12)) {
-    const int len = AXIS == 1 ? g.nx : g.ny, others = AXIS == 1 ? g.ny : g.nx;
-    const int64_t total = (int64_t)g.B * others * ((len / 2 + 15) / 16) * g.nz;
+  const int len = AXIS == 1 ? g.nx : g.ny, others = AXIS == 1 ? g.ny : g.nx;
+  const int64_t total = (int64_t)g.B * others * ((len / 2 + 15) / 16) * g.nz;
+  if (same && (nt == 8 || nt == 12) && total >= DT_WINDOW_MIN_THREADS) {
     if (nt == 8)
       hipLaunchKernelGGL((sfb3_window<AXIS, ACC, 8>), dim3(dt_grid_y(total, jobs), jobs), dim3(256), 0, s, g, J);
     else
       hipLaunchKernelGGL((sfb3_window<AXIS, ACC, 12>), dim3(dt_grid_y(total, jobs), jobs), dim3(256), 0, s, g, J);
     return;
   }
-  const int len = AXIS == 1 ? g.nx : g.ny, other = AXIS == 1 ? g.ny : g.nx;
-  const int64_t zb = (int64_t)((len + 31) / 32) * other;
-  if (zb > 65535 || (int64_t)g.NX * g.NZ > INT32_MAX) {
-    const int64_t nn = (int64_t)g.B * g.ny * g.nx * g.nz;
-    hipLaunchKernelGGL((sfb3_kernel<AXIS, ACC>), dim3(dt_grid_y(nn, jobs), jobs), dim3(256), 0, s, g, J);
-    return;
-  }
-  hipLaunchKernelGGL((sfb3_lateral_tiled<AXIS, ACC>), dim3((unsigned)((g.nz + DT_LANES - 1) / DT_LANES), jobs, (unsigned)zb),
-                     dim3(256), 0, s, g, J);
+  const int64_t nn = (int64_t)g.B * g.ny * g.nx * g.nz;
+  hipLaunchKernelGGL((sfb3_kernel<AXIS, ACC>), dim3(dt_grid_y(nn, jobs), jobs), dim3(256), 0, s, g, J);
 }
 
 hipError_t launch_prox_dtcwt3(const ProxGeom& pg, int levels, const float2* v, float2* z, float tau, float2* work,
