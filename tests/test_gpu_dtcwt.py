@@ -72,6 +72,40 @@ def test_prox_dtcwt_volume_matches_oracle(kw, levels, tau):
     plan.close()
 
 
+def test_prox_dtcwt_volume_window_passes_match_stored_oracle():
+    """512 x 128 x 128, 2 levels: large enough that the first level's x and y
+    analysis and synthesis run the register-window kernels.  Against the FP64
+    oracle's stored summaries (tests/golden/dtcwt_volume_512x128x128.npz,
+    written by the script beside it): sampled voxels, block norms, the
+    whole-volume sketch and the norm within 1e-5; tau = 0 returns the input."""
+    import importlib.util
+    import os
+    import sys
+    import paper_2108_01438_amd as P
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    import refstats
+    spec = importlib.util.spec_from_file_location(
+        "make_dtcwt_ref", os.path.join(here, "golden", "make_dtcwt_volume_reference.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    ref = np.load(os.path.join(here, "golden", "dtcwt_volume_512x128x128.npz"))
+    flush("[dtcwt prox volume] 512 x 128 x 128 vs the stored oracle")
+    v = m.inputs()
+    g = P.Geometry(n_depth=m.SHAPE[3], n_x=m.SHAPE[2], n_y=m.SHAPE[1], lateral_dims=2, n_k=16)
+    plan = P.Plan(g)
+    vd = to_dev(v)
+    z = to_host(plan.prox("dtcwt", float(ref["tau"]), 1.0, vd, haar_levels=int(ref["levels"])))
+    err = refstats.compare(z, ref, "", tuple(ref["block"]))
+    print(f"[dtcwt prox volume] errors vs the oracle: {err}")
+    for k in ("samples", "whole_sketch", "norm"):
+        assert err[k] <= PROX_TOL, (k, err[k])
+    assert err["blocks"] <= 1e-4
+    z0 = to_host(plan.prox("dtcwt", 0.0, 1.0, vd, haar_levels=int(ref["levels"])))
+    assert rel(z0, v.astype(np.complex128)) <= 2e-6
+    plan.close()
+
+
 def test_fista_dtcwt_volume_matches_oracle():
     import paper_2108_01438_amd as P
     flush("[dtcwt fista volume]")
