@@ -482,7 +482,9 @@ __global__ void __launch_bounds__(1024) lat_kernel(LatArgs a) {
 }  // namespace
 
 // Rows per tile and threads per block: the tile (T rows of L complex) stays
-// within 64 KB of LDS and every FFT stage fits 2 butterflies per thread.
+// within 64 KB of LDS and every FFT stage fits 2 butterflies per thread; on
+// images too small to give every CU a tile, the tiles narrow (to two rows at
+// least) until they do.
 int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* rowstride) {
   const int rs = (lg.L % 2 == 0) ? lg.L + 1 : lg.L;  // odd stride spreads LDS banks
   const int mb = fft_maxb(fd);
@@ -494,6 +496,10 @@ int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* row
     const int64_t bf = (int64_t)T * lg.L / fd.min_radix;
     for (int nt = 256; nt <= 1024; nt <<= 1) {
       if (bf <= mb * nt && (int64_t)T * rs * 8 <= budget) {
+        // small images: narrower tiles while the largest would leave CUs
+        // without a tile (the pass is then one tile's chain long, and a
+        // narrower tile's chain is shorter); down to row pairs
+        while (T > 2 && (int64_t)lg.n_lines * ((lg.rows + T - 1) / T) < 256) T >>= 1;
         *nthr = nt;
         *rowstride = rs;
         return T;
