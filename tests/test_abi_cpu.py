@@ -49,6 +49,9 @@ def _g(**kw):
     (dict(n_depth=0), 1), (dict(n_k=1), 1), (dict(batch=0), 1), (dict(kb_width=5), 1),
     (dict(lateral_dims=1, n_y=3), 1), (dict(k_min=3.0, k_max=2.0), 1), (dict(oversamp=1.7, n_depth=63), 1),
     (dict(n_x=11), 4), (dict(n_depth=8192), 4), (dict(lateral_dims=2, n_y=13), 4),
+    # maximum sizes: more spectrometer pixels than the column kernels take, and grid coordinates
+    # t = K dz k / pi beyond the adjoint's 16-bit base cells (dz = 100 um: ~3.4e4 cells)
+    (dict(n_k=9000), 4), (dict(dz=100.0), 4),
 ])
 def test_plan_create_rejects_bad_geometry(kw, status):
     import paper_2108_01438_amd as P

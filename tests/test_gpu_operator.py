@@ -35,6 +35,9 @@ CASES = {
     "radix7_nx3528_16x3528": dict(n_depth=16, n_x=3528, n_k=16),
     # 4096 columns: the adjoint runs narrower workgroups
     "many_columns_64x1024_b4": dict(n_depth=64, n_x=1024, n_k=64, batch=4),
+    # largest grid coordinates the 16-bit base cells take (t up to ~3.07e4 of the 3.2e4 limit,
+    # wrapping the 128-cell grid ~240 times): an explicit depth pitch of 90 um
+    "max_t_dz90_64x8": dict(n_depth=64, n_x=8, n_k=64, dz=90.0),
 }
 
 
