@@ -38,6 +38,8 @@ CASES = {
     # largest grid coordinates the 16-bit base cells take (t up to ~3.07e4 of the 3.2e4 limit,
     # wrapping the 128-cell grid ~240 times): an explicit depth pitch of 90 um
     "max_t_dz90_64x8": dict(n_depth=64, n_x=8, n_k=64, dz=90.0),
+    # a volume one A-scan wide in y (a length-1 transform along y)
+    "volume_ny1_64x16x1": dict(n_depth=64, n_x=16, n_y=1, lateral_dims=2, n_k=64),
 }
 
 

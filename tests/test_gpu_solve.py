@@ -106,6 +106,8 @@ SOLVES = {
     "volume_64x16x16_haar_20": (dict(n_depth=64, n_x=16, n_y=16, lateral_dims=2, n_k=64), "haar", 0.01, 20, 60),
     "volume_32x16x8_tv_15": (dict(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=48), "tv", 0.005, 15, 30),
     "volume_32x16x8_l1_25": (dict(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=48), "l1", 0.01, 25, 30),
+    # one iteration: z = prox(x0 - delta grad D(x0)) and the objective at x0
+    "bscan_128x48_tv_1": (dict(n_depth=128, n_x=48, n_k=128), "tv", 0.005, 1, 40),
 }
 
 
