@@ -55,6 +55,7 @@ TV_CASES = [
     (dict(n_depth=64, n_x=40, n_k=64), 30),                   # general path (per-step passes)
     (dict(n_depth=1024, n_x=600, n_k=64, batch=2), 10),       # more tiles than CUs: blocks take several
     (dict(n_depth=24, n_x=12, n_y=10, lateral_dims=2, n_k=32), 10),   # volume
+    (dict(n_depth=200, n_x=1, n_k=64), 10),                   # one A-scan: TV along depth only
 ]
 
 
