@@ -7,6 +7,14 @@
 // Adjoint: times e^{-j Omega_m} -> D^H (unnormalised inverse 2N-point DFT) ->
 // Q^T (first N) -> the adjoint of the N-point inverse DFT (DFT / N).
 // One workgroup per column; the column lives in LDS for both transforms.
+//
+// The 2N-point DFT of u padded with N zeros is done as N-point transforms:
+// its even outputs are DFT_N(u) = the N input samples themselves (u is their
+// inverse DFT / N), its odd outputs DFT_N(u_n e^{-i pi n / N}).  Likewise
+// the first N outputs of the unnormalised inverse 2N-point DFT of b are
+// IDFT_N(b_even)_n + e^{i pi n / N} IDFT_N(b_odd)_n, and the DFT / N of the
+// first term returns b_even.  Two N-point transforms per direction instead of
+// an N-point and a 2N-point one, and N samples of LDS instead of 2N.
 #include "oct_fft.h"
 
 namespace {
@@ -26,21 +34,35 @@ __global__ void __launch_bounds__(1024) literal_dq_kernel(const float2* __restri
     for (int n = tid; n < N; n += nthr) buf[n] = src[n];
     __syncthreads();
     fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(buf, 1, N, fN, twN, tid, nthr);
-    for (int n = tid; n < M; n += nthr) buf[n] = n < N ? cscale(buf[n], inv) : make_float2(0.f, 0.f);
+    for (int n = tid; n < N; n += nthr) {   // u_n e^{-i pi n / N}
+      float sn, cs;
+      sincospif(-(float)n / (float)N, &sn, &cs);
+      buf[n] = cscale(cmul(buf[n], make_float2(cs, sn)), inv);
+    }
     __syncthreads();
-    fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(buf, 1, M, fM, twM, tid, nthr);
+    fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(buf, 1, N, fN, twN, tid, nthr);
     float2* dst = out + c * M;
-    for (int m = tid; m < M; m += nthr) dst[m] = cmul(buf[m], om[m]);
+    for (int k = tid; k < N; k += nthr) {
+      dst[2 * k] = cmul(src[k], om[2 * k]);
+      dst[2 * k + 1] = cmul(buf[k], om[2 * k + 1]);
+    }
   } else {
     const float2* src = in + c * M;
-    for (int m = tid; m < M; m += nthr) buf[m] = cmul(src[m], cconj(om[m]));
+    for (int k = tid; k < N; k += nthr) buf[k] = cmul(src[2 * k + 1], cconj(om[2 * k + 1]));
     __syncthreads();
-    fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(buf, 1, M, fM, twM, tid, nthr);
-    for (int n = tid; n < N; n += nthr) buf[n] = cscale(buf[n], inv);
+    fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(buf, 1, N, fN, twN, tid, nthr);
+    for (int n = tid; n < N; n += nthr) {   // e^{i pi n / N} / N
+      float sn, cs;
+      sincospif((float)n / (float)N, &sn, &cs);
+      buf[n] = cscale(cmul(buf[n], make_float2(cs, sn)), inv);
+    }
     __syncthreads();
     fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(buf, 1, N, fN, twN, tid, nthr);
     float2* dst = out + c * N;
-    for (int n = tid; n < N; n += nthr) dst[n] = buf[n];
+    for (int k = tid; k < N; k += nthr) {
+      const float2 be = cmul(src[2 * k], cconj(om[2 * k]));
+      dst[k] = make_float2(be.x + buf[k].x, be.y + buf[k].y);
+    }
   }
 }
 
@@ -69,7 +91,7 @@ hipError_t launch_literal_dq(bool adjoint, const float2* in, float2* out, const 
   bool one = true;
   const int nt = literal_dq_threads(fN, fM, &one);
   if (nt == 0) return hipErrorInvalidConfiguration;
-  const size_t lds = (size_t)2 * N * sizeof(float2);
+  const size_t lds = (size_t)N * sizeof(float2);
   const dim3 g((unsigned)cols), b(nt);
   if (one) {
     if (adjoint) hipLaunchKernelGGL((literal_dq_kernel<true, true>), g, b, lds, s, in, out, om, N, fN, twN, fM, twM);
