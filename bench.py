@@ -43,20 +43,24 @@ def stage_bytes(g, masked: bool, penalty: str) -> dict:
     reads its inputs and writes its outputs once.  A volume's 2-D lateral
     transform takes two passes (a 256 x 256 plane does not fit on chip): the
     second axis adds a read and a write of the image (or spectrum) per
-    transform."""
+    transform.  With every pixel observed (no mask) the solve has no
+    residual seam: the forward NUFFT stage writes the residual spectrum and
+    reads the lateral spectrum of y (formed once per solve) instead."""
     N = g.batch * g.n_y * g.n_x * g.n_depth
     M = g.batch * g.n_y * g.n_x * g.n_k
     mbits = M / 8.0 if masked else 0.0
     vol = g.lateral_dims == 2
     prox = {"tv": 48.0, "haar": 16.0, "l1": 16.0}[penalty] * N   # v (+ dual) in; z (+ dual) out
-    return {
-        "lat_fwd": 32.0 * N + (16.0 * N if vol else 0.0),   # z, z_prev in; X1 and x out (+ y pass)
-        "nufft_fwd": 8.0 * N + 8.0 * M,                     # X1 in; W out
-        "normal": 20.0 * M + mbits + (32.0 * M if vol else 0.0),   # W, y, mask in; R out (+ two y passes)
-        "nufft_adj": 8.0 * M + 8.0 * N,                     # R in; X1 out
-        "lat_update": 24.0 * N + (16.0 * N if vol else 0.0),   # X1, x in; v out (+ y pass)
-        "prox": prox,
-    }
+    st = {"lat_fwd": 32.0 * N + (16.0 * N if vol else 0.0)}    # z, z_prev in; X1 and x out (+ y pass)
+    if masked:
+        st["nufft_fwd"] = 8.0 * N + 8.0 * M                     # X1 in; W out
+        st["normal"] = 20.0 * M + mbits + (32.0 * M if vol else 0.0)   # W, y, mask in; R out (+ two y passes)
+    else:
+        st["nufft_fwd"] = 8.0 * N + 16.0 * M                    # X1, F_lat y in; R out
+    st["nufft_adj"] = 8.0 * M + 8.0 * N                         # R in; X1 out
+    st["lat_update"] = 24.0 * N + (16.0 * N if vol else 0.0)    # X1, x in; v out (+ y pass)
+    st["prox"] = prox
+    return st
 
 
 # FP32 vector peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flop
@@ -132,7 +136,8 @@ def phi_sizes_bench() -> dict:
 # kernels of the single-kernel stages (a volume's lateral stages take two or
 # three launches of the lateral kernel), by the name rocprofv3 reports
 STAGE_KERNEL = {
-    "nufft_fwd": "nufft_fwd_pair_kernel<6, false>",
+    # the volume (every pixel observed) runs the variant that writes the residual spectrum
+    "nufft_fwd": {True: "nufft_fwd_pair_kernel<6, false, true>", False: "nufft_fwd_pair_kernel<6, false, false>"},
     "nufft_adj": "nufft_adj_pair_kernel<6, true>",
     "prox": {"tv": "tv2d_tile_kernel<false>", "haar": "haar_kernel<3, 3", "l1": "prox_l1_kernel"},
 }
@@ -151,7 +156,7 @@ def stage_kernel(stage: str, penalty: str, volume: bool):
     """Kernel (name prefix) of a stage that is one launch, else None."""
     k = STAGE_KERNEL.get(stage)
     if isinstance(k, dict):
-        k = k.get(penalty)
+        k = k.get(volume) if stage == "nufft_fwd" else k.get(penalty)
     if k is None and not volume:
         k = BSCAN_STAGE_KERNEL.get(stage)
     return k
@@ -792,10 +797,14 @@ def profile_stages(args) -> dict:
     torch.cuda.set_device(0)
     name, pen = (WORKLOAD, "haar") if args.workload == "volume" else (BSCAN, "tv")
     geom = P.Geometry.from_dict(synth.preset(name)["geom"])
-    plan = P.Plan(geom)
+    mask = None
+    if args.workload != "volume":   # the B-scan's solve sees half of every A-scan (seeded, as its bench)
+        import numpy as np
+        mask = synth.mask_random_exact(np.random.default_rng(1), (1, geom.n_x), geom.n_k, geom.n_k // 2)
+    plan = P.Plan(geom, mask)
     gen = torch.Generator(device="cuda").manual_seed(5)
     y = torch.randn(geom.meas_shape, dtype=torch.float32, device="cuda", generator=gen)
-    sb = stage_bytes(geom, False, pen)
+    sb = stage_bytes(geom, mask is not None, pen)
     st = time_stages(plan, pen, y, sb, args.stage_reps)
     plan.close()
     return {"workload": name, "reps": args.stage_reps,
@@ -807,7 +816,7 @@ def time_stages(plan, penalty: str, y, sb: dict, reps: int) -> dict:
     buffers (oct_run_stage), on torch's current stream (the launch stream)."""
     import torch
     stages = {}
-    for st in plan.STAGES:
+    for st in sb:   # the stages of the solve's iteration
         for _ in range(3):
             plan.run_stage(st, penalty, y)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

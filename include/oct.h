@@ -141,7 +141,11 @@ oct_status oct_adjoint_paper(oct_plan_t plan, const float* r, void* x, void* str
 
 /* g = Phi^H (Phi x - y), the gradient of eq. (2)-(3).  half_resid_sq: device
  * double, receives 1/2 ||diag(s)(Phi x - y)||^2 summed over the batch;
- * may be NULL. */
+ * may be NULL.  With every pixel observed (s = 1) the residual's lateral
+ * round trip F_lat(Re F_lat^{-1} W - y) / N_lat equals W_h / N_lat -
+ * F_lat(y) / N_lat, W_h the Hermitian part of W over q, and the norm is
+ * taken by Parseval over the lateral frequencies: the same values up to
+ * rounding, without the inverse and forward lateral passes. */
 oct_status oct_grad(oct_plan_t plan, const void* x, const float* y, void* g,
                     double* half_resid_sq, void* stream);
 
@@ -275,7 +279,11 @@ typedef enum {
  * use), with the kernels and launch shapes oct_mbir_solve uses.  For timing
  * and profiling only; y is read by OCT_STAGE_NORMAL (device measurement,
  * may be NULL for the others); penalty selects the prox (TV with 10 inner
- * steps, Haar with 3 levels).  Asynchronous. */
+ * steps, Haar with 3 levels).  On a plan whose every pixel is observed
+ * (mask NULL or all ones), the solve folds OCT_STAGE_NORMAL into
+ * OCT_STAGE_NUFFT_FWD, which then writes the residual spectrum W/N_lat -
+ * F_lat(y)/N_lat (from the solver's stored F_lat(y)); OCT_STAGE_NORMAL
+ * still runs the general seam.  Asynchronous. */
 oct_status oct_run_stage(oct_plan_t plan, int32_t stage, int32_t penalty, const float* y, void* stream);
 
 /* Direct (non-iterative) reconstructions of Sec. 3.1: the three images of

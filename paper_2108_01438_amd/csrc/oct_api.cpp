@@ -186,6 +186,10 @@ struct oct_plan {
   int64_t X1s = 0;               // column stride of X1's y rows (n_x, or n_x + 1 for a volume)
   int4* pairs = nullptr;
   int n_pairs = 0;
+  // every measurement pixel observed (no mask, or a mask of all ones): on the
+  // half-spectrum path the residual seam reduces to R^ = W_h / N_lat - Y_h
+  bool full = true;
+  float2* yhat = nullptr;        // Y_h = F_lat(y) / N_lat of the running solve (W's layout), first use
   FftDesc fN{};
   float2* twN = nullptr;
   double* k2x4e = nullptr;       // [N] 4 k_{2j}^2
@@ -521,20 +525,22 @@ oct_status run_meas_forward(oct_plan* p, float* y, hipStream_t s, bool half) {
   return OCT_OK;
 }
 
-// r -> W = F_lat(s . r) / N_lat
-oct_status run_meas_adjoint(oct_plan* p, const float* r, hipStream_t s, bool half, bool use_mask = true) {
+// r -> W = F_lat(s . r) / N_lat (into dst, W's layout, when given)
+oct_status run_meas_adjoint(oct_plan* p, const float* r, hipStream_t s, bool half, bool use_mask = true,
+                            float2* dst = nullptr) {
   const int rows = (int)p->Mk;
+  if (!dst) dst = p->W;
   LatArgs a = lat_args(p, lines_x(p, rows), false);
   if (half) a.sa_half = p->Nxs * rows;
   if (!use_mask) a.mask = nullptr;
   a.srcf = r;
-  a.dst = p->W;
+  a.dst = dst;
   a.scale = 1.f / (float)p->Nx;
   HIPCHK(launch_lateral(LAT_ADJ_MEAS, a, s));
   if (p->lat_dims == 2) {
     LatArgs b = lat_args(p, half ? lines_y_half(p, rows) : lines_y(p, rows), true);
-    b.src = p->W;
-    b.dst = p->W;
+    b.src = dst;
+    b.dst = dst;
     b.scale = 1.f / (float)p->Ny;
     HIPCHK(launch_lateral(LAT_FFT, b, s));
   }
@@ -629,6 +635,18 @@ oct_status run_normal(oct_plan* p, const float* y, double* partial, int* nparts,
   return OCT_OK;
 }
 
+// The normal seam of a fully observed half-spectrum plan: X1 -> W = R^ =
+// W_h / N_lat - yh in the forward pair kernel (yh: Y_h = F_lat(y) / N_lat in
+// W's layout, possibly W itself; NULL for y = 0), the per-block sums of r^2
+// into partial when that is not NULL; returns #partials.
+bool spectral_seam(const oct_plan* p, bool paper) { return p->hs && p->full && !paper; }
+
+oct_status run_cols_fwd_res(oct_plan* p, const float2* yh, double* partial, int* nparts, hipStream_t s) {
+  HIPCHK(launch_nufft_fwd_pair_res(nufft_args(p), p->X1, p->W, yh, partial, s));
+  if (nparts) *nparts = (int)(p->n_pairs * p->B);
+  return OCT_OK;
+}
+
 // X1 (adjoint NUFFT output) -> g = F_lat^H X1 written to out
 oct_status run_lat_adjoint(oct_plan* p, float2* out, hipStream_t s) {
   if (p->lat_dims == 2) {
@@ -658,8 +676,18 @@ int partial_need(oct_plan* p) {
   need = std::max(need, tv_partials(pg, TV_MAX_TILED_INNER));
   need = std::max(need, tv_partials(pg, TV_MAX_TILED_INNER + 1));
   for (int lv = 1; lv <= (p->lat_dims == 1 ? 5 : 4); ++lv) need = std::max(need, dtcwt_partials(pg, lv));
+  need = std::max(need, (int)(p->n_pairs * p->B));   // the residual partials of the spectral seam
   return need;
 }
+
+// Column stride of the y rows of the spectral buffers (see plan creation):
+// a volume pads them by one column; the elements of W (the full spectrum, or
+// the padded half spectrum if larger) and of X1.
+static int64_t w_slot_stride(const oct_geometry& g) { return g.n_y > 1 ? g.n_x + 1 : g.n_x; }
+static int64_t w_elems(const oct_geometry& g) {
+  return g.batch * std::max(g.n_y * g.n_x, g.n_y * w_slot_stride(g)) * g.n_k;
+}
+static int64_t x1_elems(const oct_geometry& g) { return g.batch * g.n_y * w_slot_stride(g) * g.n_depth; }
 
 oct_status ensure_solver_state(oct_plan* p, int pen, int iters) {
   const size_t n0 = p->allocs.size();
@@ -681,6 +709,10 @@ oct_status ensure_solver_state(oct_plan* p, int pen, int iters) {
     OCTCHK(dev_alloc(p, &p->tvwork, tv_work_elems(pg)));
     HIPCHK(hipMemset(p->p0, 0, sizeof(float2) * p->n_img() * nd));
     HIPCHK(hipMemset(p->p1, 0, sizeof(float2) * p->n_img() * nd));
+  }
+  if (p->hs && p->full && !p->yhat) {
+    OCTCHK(dev_alloc(p, &p->yhat, w_elems(p->g)));
+    HIPCHK(hipMemset(p->yhat, 0, sizeof(float2) * w_elems(p->g)));
   }
   if (pen == OCT_PEN_DTCWT && !p->dtwork) {
     ProxGeom pg{(int)p->B, (int)p->Ny, (int)p->Nx, (int)p->Nz, p->lat_dims};
@@ -781,14 +813,6 @@ extern "C" {
 
 const char* oct_last_error(void) { return g_err.c_str(); }
 
-// Column stride of the y rows of the spectral buffers (see plan creation):
-// a volume pads them by one column; the elements of W (the full spectrum, or
-// the padded half spectrum if larger) and of X1.
-static int64_t w_slot_stride(const oct_geometry& g) { return g.n_y > 1 ? g.n_x + 1 : g.n_x; }
-static int64_t w_elems(const oct_geometry& g) {
-  return g.batch * std::max(g.n_y * g.n_x, g.n_y * w_slot_stride(g)) * g.n_k;
-}
-static int64_t x1_elems(const oct_geometry& g) { return g.batch * g.n_y * w_slot_stride(g) * g.n_depth; }
 
 size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   if (validate(g) != OCT_OK) return 0;
@@ -803,6 +827,7 @@ size_t oct_plan_footprint_bytes(const oct_geometry* g, int32_t penalty) {
   b += (size_t)x1_elems(*g) * 8 + (size_t)w_elems(*g) * 8;  // workspace X1, W
   b += (size_t)Nlat * 16;                        // column-pair table of the half-spectrum path
   b += (size_t)M * 4;                            // measurements scaled per item (per-item weights)
+  b += (size_t)w_elems(*g) * 8;                  // lateral spectrum of y (solves of a fully observed plan)
   if (g->model == OCT_MODEL_LITERAL)             // K's samples and the literal chain's tables
     b += (size_t)N * 8 + (size_t)g->n_depth * 16 + (size_t)g->n_k * 16;
   b += (size_t)N * 8 * 3;                        // FISTA iterates and the extrapolated point
@@ -937,8 +962,10 @@ oct_status oct_plan_create(const oct_geometry* g, const uint8_t* mask, oct_plan_
     p->mask_words = (int)((p->Mk + 31) / 32);
     std::vector<uint32_t> bits((size_t)p->Nlat * p->mask_words, 0u);
     for (int64_t l = 0; l < p->Nlat; ++l)
-      for (int64_t m = 0; m < p->Mk; ++m)
+      for (int64_t m = 0; m < p->Mk; ++m) {
         if (mask[l * p->Mk + m]) bits[(size_t)l * p->mask_words + (m >> 5)] |= 1u << (m & 31);
+        else p->full = false;
+      }
     if ((st = upload(p, &p->mask, bits)) != OCT_OK) return cleanup(st);
   }
   // column pairs (q, -q) of the half-spectrum path: q is canonical when
@@ -1099,11 +1126,17 @@ oct_status oct_ncc_noalloc(const void* x, const void* z, int64_t n, double* r_ou
 oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, double* half_resid_sq, void* stream) {
   if (!p || !x || !y || !gout) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
-  OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
-  OCTCHK(run_cols_fwd(p, s, p->hs));
   int np = 0;
   // residual partials only when the caller asks for 1/2 ||r||^2
-  OCTCHK(run_normal(p, y, half_resid_sq ? p->partial : nullptr, &np, s, p->hs));
+  if (spectral_seam(p, false)) {
+    OCTCHK(run_meas_adjoint(p, y, s, true));   // W = Y_h, read and overwritten by the forward pair kernel
+    OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
+    OCTCHK(run_cols_fwd_res(p, p->W, half_resid_sq ? p->partial : nullptr, &np, s));
+  } else {
+    OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
+    OCTCHK(run_cols_fwd(p, s, p->hs));
+    OCTCHK(run_normal(p, y, half_resid_sq ? p->partial : nullptr, &np, s, p->hs));
+  }
   if (half_resid_sq) HIPCHK(launch_reduce_sum(p->partial, np, half_resid_sq, 0.5, 0, s));
   OCTCHK(run_cols_adj(p, s, p->hs));
   OCTCHK(run_lat_adjoint(p, (float2*)gout, s));
@@ -1161,9 +1194,13 @@ oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, int32_t fla
   HIPCHK(launch_scale_by_inv_sqrt(p->za, p->za, n, p->dscal, s));
   for (int it = 0; it < iters; ++it) {
     OCTCHK(run_lat_forward(p, p->za, nullptr, nullptr, 0.f, s));
-    OCTCHK(run_cols_fwd(p, s, p->hs && !paper));
-    if (paper) OCTCHK(run_normal_paper(p, nullptr, nullptr, nullptr, s));
-    else OCTCHK(run_normal(p, nullptr, nullptr, nullptr, s, p->hs));
+    if (spectral_seam(p, paper)) {
+      OCTCHK(run_cols_fwd_res(p, nullptr, nullptr, nullptr, s));
+    } else {
+      OCTCHK(run_cols_fwd(p, s, p->hs && !paper));
+      if (paper) OCTCHK(run_normal_paper(p, nullptr, nullptr, nullptr, s));
+      else OCTCHK(run_normal(p, nullptr, nullptr, nullptr, s, p->hs));
+    }
     OCTCHK(run_cols_adj(p, s, p->hs && !paper));
     OCTCHK(run_lat_adjoint(p, p->zb, s));
     HIPCHK(launch_norm2_partial(p->zb, n, p->partial, nb, s));
@@ -1270,15 +1307,21 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
   }
   double* res_part = p->partial;
   double* pen_part = p->partial + p->partial_cap;
+  const bool spec = spectral_seam(p, paper);
+  if (spec) OCTCHK(run_meas_adjoint(p, y, s, true, true, p->yhat));   // Y_h, once per solve
   float mu_prev = k0 > 0 ? (float)mu[k0 - 1] : 0.f;
   if (fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s));
   for (int k = 0; k < prm->iters; ++k) {
     if (!fused_l1) OCTCHK(run_lat_forward(p, nullptr, zc, zo, mu_prev, s, p->xext));
-    OCTCHK(run_cols_fwd(p, s, p->hs && !paper));
     int nres = 0, npen = 0;
     // residual partials only for the objective
-    if (paper) OCTCHK(run_normal_paper(p, y, want_obj ? res_part : nullptr, &nres, s));
-    else OCTCHK(run_normal(p, y, want_obj ? res_part : nullptr, &nres, s, p->hs));
+    if (spec) {
+      OCTCHK(run_cols_fwd_res(p, p->yhat, want_obj ? res_part : nullptr, &nres, s));
+    } else {
+      OCTCHK(run_cols_fwd(p, s, p->hs && !paper));
+      if (paper) OCTCHK(run_normal_paper(p, y, want_obj ? res_part : nullptr, &nres, s));
+      else OCTCHK(run_normal(p, y, want_obj ? res_part : nullptr, &nres, s, p->hs));
+    }
     OCTCHK(run_cols_adj(p, s, p->hs && !paper));
     if (fused_l1) {
       LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
@@ -1360,7 +1403,8 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
   switch (stage) {
     case OCT_STAGE_LAT_FWD:
       return run_lat_forward(p, nullptr, p->za, p->zb, 0.5f, s, p->xext);
-    case OCT_STAGE_NUFFT_FWD:
+    case OCT_STAGE_NUFFT_FWD:   // as in a solve without the objective
+      if (spectral_seam(p, false)) return run_cols_fwd_res(p, p->yhat, nullptr, nullptr, s);
       OCTCHK(run_cols_fwd(p, s, p->hs));
       return OCT_OK;
     case OCT_STAGE_NORMAL: {

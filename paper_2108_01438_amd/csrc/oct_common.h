@@ -153,6 +153,16 @@ struct NufftArgs {
   int n_half;
 };
 
+// Residual output of the forward pair kernel (every pixel observed): R^ =
+// W_h / N_lat - yh, and per-block N_lat-weighted |R^|^2 into partial (NULL:
+// none); yh NULL stands for y = 0.
+struct PairRes {
+  const float2* yh;
+  double* partial;
+  float inv_nlat;
+  double nlat;
+};
+
 // Launchers (kernels in the .hip files; all asynchronous on `s`).
 hipError_t launch_lateral(LatMode mode, const LatArgs& a, hipStream_t s);
 int lateral_pick_tile(const LineGeom& lg, const FftDesc& fd, int* nthr, int* rowstride);
@@ -163,6 +173,12 @@ size_t nufft_adj_lds_bytes(const NufftArgs& a);
 // columns q and -q of X1, and both image columns from R^(q) (R^(-q) = conj R^(q)).
 hipError_t launch_nufft_fwd_pair(const NufftArgs& a, const float2* X1, float2* Wh, hipStream_t s);
 hipError_t launch_nufft_adj_pair(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s);
+// The forward pair kernel with the residual seam of a fully observed plan:
+// Rh = W_h / N_lat - yh (yh may be Rh itself, or NULL for y = 0), the
+// residual norm partials (one per block, n_pairs * batch) into partial when
+// that is not NULL.
+hipError_t launch_nufft_fwd_pair_res(const NufftArgs& a, const float2* X1, float2* Rh, const float2* yh,
+                                     double* partial, hipStream_t s);
 size_t nufft_pair_lds_bytes(const NufftArgs& a, bool adjoint);
 bool nufft_pair_supported(const NufftArgs& a);   // LDS and thread limits of the pair kernels
 

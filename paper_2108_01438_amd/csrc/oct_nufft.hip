@@ -560,9 +560,17 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_kernel(NufftArgs 
 // is real, so R^(-q) = conj R^(q), and both image columns come out of one
 // gather (one weight evaluation per cell-sample pair for the two columns).
 // ---------------------------------------------------------------------------
-template <int J, bool ONE>
+//
+// RES: every measurement pixel observed (s = 1).  Then the lateral round trip
+// of the residual, F_lat(Re F_lat^{-1} W - y) / N_lat, is W_h(q) / N_lat -
+// Y_h(q) with Y_h = F_lat(y) / N_lat (y is real), so the kernel stores the
+// residual spectrum R^ directly (Y_h from r.yh, which may be Wh itself: each
+// element is read, then written, by one thread; NULL means y = 0) and, when
+// r.partial is set, writes the block's share of ||r||^2 by Parseval:
+// sum_l r_l^2 = N_lat sum_q |R^(q)|^2, the pair standing for q and -q.
+template <int J, bool ONE, bool RES>
 __global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const float2* __restrict__ X1,
-                                                              float2* __restrict__ Wh) {
+                                                              float2* __restrict__ Wh, PairRes r) {
   extern __shared__ float2 gridp[];
   const int K = a.K, Nz = a.Nz, nc = a.nc;
   const int rs = K + 2 * KPAD;   // row stride: [KPAD pads | K cells | KPAD pads]
@@ -603,8 +611,11 @@ __global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const
 
   const double q2 = a.q2[pr.x];
   const float bq = a.beam[pr.x];
-  float2* __restrict__ out = Wh + ((int64_t)b * a.n_half + pr.z) * a.Mk;
+  const int64_t slot = ((int64_t)b * a.n_half + pr.z) * a.Mk;
+  float2* __restrict__ out = Wh + slot;
   float2* __restrict__ outp = pr.w >= 0 ? Wh + ((int64_t)b * a.n_half + pr.w) * a.Mk : nullptr;
+  const float2* yh = RES && r.yh ? r.yh + slot : nullptr;
+  double acc = 0.0;
   for (int m = tid; m < a.Mk; m += nthr) {
     const KP kp{a.k2x4[m], a.phase[m]};
     const double arg = kp.k2 - q2;
@@ -637,8 +648,27 @@ __global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const
       const float2 w0 = cmul(h, u0), w1 = cmul(h, u1);
       res = make_float2(0.5f * (w0.x + w1.x), 0.5f * (w0.y - w1.y));   // (W(q) + conj W(-q)) / 2
     }
+    if constexpr (RES) {
+      const float2 yv = yh ? yh[m] : make_float2(0.f, 0.f);
+      res = make_float2(fmaf(res.x, r.inv_nlat, -yv.x), fmaf(res.y, r.inv_nlat, -yv.y));
+      acc = fma((double)res.x, (double)res.x, fma((double)res.y, (double)res.y, acc));
+    }
     out[m] = res;
     if (outp) outp[m] = cconj(res);
+  }
+  if constexpr (RES) {
+    if (r.partial) {   // uniform: every thread takes part in the block sum
+      __shared__ double sh[16];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if ((tid & 63) == 0) sh[tid >> 6] = acc;
+      __syncthreads();
+      if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (nthr + 63) >> 6; ++w) t += sh[w];
+        r.partial[blockIdx.x] = t * r.nlat * (pr.x != pr.y ? 2.0 : 1.0);
+      }
+    }
   }
 }
 
@@ -988,17 +1018,33 @@ int pair_threads(const NufftArgs& a, bool adjoint) {
   return nt;
 }
 
-template <int J, bool ONE>
-hipError_t nufft_fwd_pair_t(const NufftArgs& a, const float2* X1, float2* Wh, int nthr, hipStream_t s) {
+template <int J, bool ONE, bool RES>
+hipError_t nufft_fwd_pair_t(const NufftArgs& a, const float2* X1, float2* Wh, const PairRes& r, int nthr,
+                            hipStream_t s) {
   const size_t lds = nufft_pair_lds_bytes(a, false);
   if (lds > 64 * 1024) {
-    static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_fwd_pair_kernel<J, ONE>),
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    static const hipError_t set =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_fwd_pair_kernel<J, ONE, RES>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
     if (set != hipSuccess) return set;
   }
-  hipLaunchKernelGGL((nufft_fwd_pair_kernel<J, ONE>), dim3(a.n_pairs * (a.n_cols / a.Nlat)), dim3(nthr), lds, s, a, X1,
-                     Wh);
+  hipLaunchKernelGGL((nufft_fwd_pair_kernel<J, ONE, RES>), dim3(a.n_pairs * (a.n_cols / a.Nlat)), dim3(nthr), lds, s,
+                     a, X1, Wh, r);
   return hipGetLastError();
+}
+
+template <bool RES>
+hipError_t fwd_pair_dispatch(const NufftArgs& a, const float2* X1, float2* Wh, const PairRes& r, hipStream_t s) {
+  const int nt = pair_threads(a, false);
+  const bool one = fft_one(a.fK, 2, nt);
+  switch (a.J) {
+    case 4: return one ? nufft_fwd_pair_t<4, true, RES>(a, X1, Wh, r, nt, s)
+                       : nufft_fwd_pair_t<4, false, RES>(a, X1, Wh, r, nt, s);
+    case 6: return one ? nufft_fwd_pair_t<6, true, RES>(a, X1, Wh, r, nt, s)
+                       : nufft_fwd_pair_t<6, false, RES>(a, X1, Wh, r, nt, s);
+    default: return one ? nufft_fwd_pair_t<8, true, RES>(a, X1, Wh, r, nt, s)
+                        : nufft_fwd_pair_t<8, false, RES>(a, X1, Wh, r, nt, s);
+  }
 }
 
 template <int J, bool ONE>
@@ -1029,13 +1075,17 @@ bool nufft_pair_supported(const NufftArgs& a) {
 }
 
 hipError_t launch_nufft_fwd_pair(const NufftArgs& a, const float2* X1, float2* Wh, hipStream_t s) {
-  const int nt = pair_threads(a, false);
-  const bool one = fft_one(a.fK, 2, nt);
-  switch (a.J) {
-    case 4: return one ? nufft_fwd_pair_t<4, true>(a, X1, Wh, nt, s) : nufft_fwd_pair_t<4, false>(a, X1, Wh, nt, s);
-    case 6: return one ? nufft_fwd_pair_t<6, true>(a, X1, Wh, nt, s) : nufft_fwd_pair_t<6, false>(a, X1, Wh, nt, s);
-    default: return one ? nufft_fwd_pair_t<8, true>(a, X1, Wh, nt, s) : nufft_fwd_pair_t<8, false>(a, X1, Wh, nt, s);
-  }
+  return fwd_pair_dispatch<false>(a, X1, Wh, PairRes{}, s);
+}
+
+hipError_t launch_nufft_fwd_pair_res(const NufftArgs& a, const float2* X1, float2* Rh, const float2* yh,
+                                     double* partial, hipStream_t s) {
+  PairRes r{};
+  r.yh = yh;
+  r.partial = partial;
+  r.inv_nlat = 1.f / (float)a.Nlat;
+  r.nlat = (double)a.Nlat;
+  return fwd_pair_dispatch<true>(a, X1, Rh, r, s);
 }
 
 hipError_t launch_nufft_adj_pair(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s) {

@@ -73,6 +73,37 @@ def test_forward_adjoint_grad_match_oracle(name, mask_kind):
     assert abs(float(hr.item()) - 0.5 * float(np.sum(res * res))) <= 1e-5 * 0.5 * float(np.sum(res * res))
 
 
+@pytest.mark.parametrize("name", ["bscan_200x60_k300_b2", "volume_64x16x12_b2", "bscan_odd_75x45_k90_focus",
+                                  "evanescent_64x32"])
+def test_full_mask_seam(name):
+    """With every pixel observed (eq. (7), s = 1) the gradient takes the
+    residual seam in the lateral-frequency domain; a mask array of all ones
+    must give bitwise the plan without a mask, and one unobserved pixel the
+    general seam, both within the operator tolerance of the oracle (value
+    and 1/2 ||r||^2)."""
+    import paper_2108_01438_amd as P
+    flush(f"[full-mask seam] {name}")
+    og, pg = both_geoms(**CASES[name])
+    rng = np.random.default_rng(zlib.crc32(name.encode()) + 1)
+    x32, x64 = rand_image(rng, O.img_shape(og))
+    r32, r64 = rand_meas(rng, O.meas_shape(og))
+    shp = (og.n_y if og.lateral_dims == 2 else 1, og.n_x, og.n_k)
+    ones = np.ones(shp, dtype=np.uint8)
+    one_off = ones.copy()
+    one_off[0, og.n_x // 2, og.n_k // 3] = 0
+    out = {}
+    for kind, mask in (("none", None), ("ones", ones), ("one_off", one_off)):
+        plan = P.Plan(pg, mask)
+        g, hr = plan.grad(to_dev(x32), to_dev(r32))
+        out[kind] = (to_host(g), float(hr.item()))
+        plan.close()
+        g_or, res = O.grad(x64, r64, og, None if mask is None else mask)
+        assert rel(out[kind][0], g_or) <= OP_TOL, kind
+        hr_or = 0.5 * float(np.sum(res * res))
+        assert abs(out[kind][1] - hr_or) <= 1e-5 * hr_or, kind
+    assert np.array_equal(out["none"][0], out["ones"][0]) and out["none"][1] == out["ones"][1]
+
+
 @pytest.mark.parametrize("name", ["bscan_512x64", "volume_64x16x12_b2", "bscan_200x60_k300_b2"])
 def test_adjoint_identity_fp32(name):
     """<Phi x, r> = Re<x, Phi^H r> with FP64 inner products of FP32 results."""

@@ -81,12 +81,19 @@ def test_prox_tv_cold_and_warm(kw, inner):
     assert rel(z2, zr2) <= PROX_TOL
 
 
-def test_lipschitz_matches_oracle():
+@pytest.mark.parametrize("geom,masked", [
+    (dict(n_depth=128, n_x=32, n_k=128, batch=2), True),
+    # every pixel observed: the power steps take the residual seam in the lateral-frequency domain
+    (dict(n_depth=128, n_x=32, n_k=128, batch=2), False),
+    (dict(n_depth=64, n_x=16, n_y=12, lateral_dims=2, n_k=96), False),
+])
+def test_lipschitz_matches_oracle(geom, masked):
     import paper_2108_01438_amd as P
-    flush("[lipschitz] 50 power steps")
-    og, pg = both_geoms(n_depth=128, n_x=32, n_k=128, batch=2)
+    flush(f"[lipschitz] 50 power steps {geom} masked={masked}")
+    og, pg = both_geoms(**geom)
     rng = np.random.default_rng(4)
-    mask = (rng.random((1, 32, 128)) < 0.5).astype(np.uint8)
+    lat = (og.n_y if og.lateral_dims == 2 else 1, og.n_x, og.n_k)
+    mask = (rng.random(lat) < 0.5).astype(np.uint8) if masked else None
     plan = P.Plan(pg, mask)
     L = plan.lipschitz(50, seed=11)
     Lo = O.lipschitz(og, mask, iters=50, seed=11)
