@@ -581,6 +581,18 @@ __global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const
   const int4 pr = a.pairs[blockIdx.x - b * a.n_pairs];
   const float2* __restrict__ s0 = X1 + xcol(a, b, pr.x);
   const float2* __restrict__ s1 = X1 + xcol(a, b, pr.y);
+  const int64_t slot = ((int64_t)b * a.n_half + pr.z) * a.Mk;
+  // Y_h of this thread's first four samples, loaded before the transforms;
+  // each later sample's is loaded four samples ahead (a register ring)
+  const float2* yh = RES && r.yh ? r.yh + slot : nullptr;
+  auto yload = [&](int m) { return (yh && m < a.Mk) ? yh[m] : make_float2(0.f, 0.f); };
+  float2 y0{}, y1{}, y2{}, y3{};
+  if constexpr (RES) {
+    y0 = yload(tid);
+    y1 = yload(tid + nthr);
+    y2 = yload(tid + 2 * nthr);
+    y3 = yload(tid + 3 * nthr);
+  }
 
   const bool half = K == 2 * Nz && 2 * nc == Nz &&
                     fwd_grid_fft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(g0, 2, rs, s0, s1, a.deap, a.fK,
@@ -611,10 +623,8 @@ __global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const
 
   const double q2 = a.q2[pr.x];
   const float bq = a.beam[pr.x];
-  const int64_t slot = ((int64_t)b * a.n_half + pr.z) * a.Mk;
   float2* __restrict__ out = Wh + slot;
   float2* __restrict__ outp = pr.w >= 0 ? Wh + ((int64_t)b * a.n_half + pr.w) * a.Mk : nullptr;
-  const float2* yh = RES && r.yh ? r.yh + slot : nullptr;
   double acc = 0.0;
   for (int m = tid; m < a.Mk; m += nthr) {
     const KP kp{a.k2x4[m], a.phase[m]};
@@ -649,7 +659,11 @@ __global__ void __launch_bounds__(1024) nufft_fwd_pair_kernel(NufftArgs a, const
       res = make_float2(0.5f * (w0.x + w1.x), 0.5f * (w0.y - w1.y));   // (W(q) + conj W(-q)) / 2
     }
     if constexpr (RES) {
-      const float2 yv = yh ? yh[m] : make_float2(0.f, 0.f);
+      const float2 yv = y0;
+      y0 = y1;
+      y1 = y2;
+      y2 = y3;
+      y3 = yload(m + 4 * nthr);
       res = make_float2(fmaf(res.x, r.inv_nlat, -yv.x), fmaf(res.y, r.inv_nlat, -yv.y));
       acc = fma((double)res.x, (double)res.x, fma((double)res.y, (double)res.y, acc));
     }
