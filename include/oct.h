@@ -145,7 +145,10 @@ oct_status oct_adjoint_paper(oct_plan_t plan, const float* r, void* x, void* str
  * round trip F_lat(Re F_lat^{-1} W - y) / N_lat equals W_h / N_lat -
  * F_lat(y) / N_lat, W_h the Hermitian part of W over q, and the norm is
  * taken by Parseval over the lateral frequencies: the same values up to
- * rounding, without the inverse and forward lateral passes. */
+ * rounding, without the inverse and forward lateral passes (a volume's
+ * oct_grad and every solve and power iteration take this route; a B-scan's
+ * oct_grad keeps its one-pass seam, which costs less than forming F_lat(y)
+ * per call). */
 oct_status oct_grad(oct_plan_t plan, const void* x, const float* y, void* g,
                     double* half_resid_sq, void* stream);
 

@@ -1127,8 +1127,10 @@ oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, dou
   if (!p || !x || !y || !gout) return fail(OCT_E_INVALID, "null argument");
   hipStream_t s = S(stream);
   int np = 0;
-  // residual partials only when the caller asks for 1/2 ||r||^2
-  if (spectral_seam(p, false)) {
+  // residual partials only when the caller asks for 1/2 ||r||^2.  Per call,
+  // Y_h costs a lateral pass over y: a win for a volume, whose general seam
+  // takes three passes (y, x, y), but not for a B-scan's single seam pass.
+  if (spectral_seam(p, false) && p->lat_dims == 2) {
     OCTCHK(run_meas_adjoint(p, y, s, true));   // W = Y_h, read and overwritten by the forward pair kernel
     OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
     OCTCHK(run_cols_fwd_res(p, p->W, half_resid_sq ? p->partial : nullptr, &np, s));

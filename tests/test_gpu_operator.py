@@ -76,11 +76,11 @@ def test_forward_adjoint_grad_match_oracle(name, mask_kind):
 @pytest.mark.parametrize("name", ["bscan_200x60_k300_b2", "volume_64x16x12_b2", "bscan_odd_75x45_k90_focus",
                                   "evanescent_64x32"])
 def test_full_mask_seam(name):
-    """With every pixel observed (eq. (7), s = 1) the gradient takes the
-    residual seam in the lateral-frequency domain; a mask array of all ones
-    must give bitwise the plan without a mask, and one unobserved pixel the
-    general seam, both within the operator tolerance of the oracle (value
-    and 1/2 ||r||^2)."""
+    """With every pixel observed (eq. (7), s = 1) a volume's gradient takes
+    the residual seam in the lateral-frequency domain (a B-scan's keeps its
+    one-pass seam); a mask array of all ones must give bitwise the plan
+    without a mask, and one unobserved pixel the general seam, both within
+    the operator tolerance of the oracle (value and 1/2 ||r||^2)."""
     import paper_2108_01438_amd as P
     flush(f"[full-mask seam] {name}")
     og, pg = both_geoms(**CASES[name])
