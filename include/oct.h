@@ -111,7 +111,8 @@ oct_status oct_plan_destroy(oct_plan_t plan);
 oct_status oct_plan_release(oct_plan_t plan);
 
 /* Upper bound of the device bytes a plan plus one oct_mbir_solve of the given
- * penalty hold (tables, workspace, solver state); used for admission control.
+ * penalty hold (tables, workspace, solver state, and the lateral spectrum of
+ * y that a solve on a fully observed plan keeps); used for admission control.
  * penalty < 0: the bound for a plan that runs every penalty and entry point
  * over its life (all solver states and optional buffers, which a plan keeps
  * once allocated).  Host-only, returns 0 for an invalid geometry. */
