@@ -40,6 +40,8 @@ CASES = {
     "max_t_dz90_64x8": dict(n_depth=64, n_x=8, n_k=64, dz=90.0),
     # a volume one A-scan wide in y (a length-1 transform along y)
     "volume_ny1_64x16x1": dict(n_depth=64, n_x=16, n_y=1, lateral_dims=2, n_k=64),
+    # odd n_x and n_y: no Nyquist column; only q_x = 0 pairs within the half spectrum
+    "volume_odd_32x9x7": dict(n_depth=32, n_x=9, n_y=7, lateral_dims=2, n_k=48),
 }
 
 
@@ -74,7 +76,7 @@ def test_forward_adjoint_grad_match_oracle(name, mask_kind):
 
 
 @pytest.mark.parametrize("name", ["bscan_200x60_k300_b2", "volume_64x16x12_b2", "bscan_odd_75x45_k90_focus",
-                                  "evanescent_64x32"])
+                                  "evanescent_64x32", "volume_odd_32x9x7", "volume_ny1_64x16x1"])
 def test_full_mask_seam(name):
     """With every pixel observed (eq. (7), s = 1) a volume's gradient takes
     the residual seam in the lateral-frequency domain (a B-scan's keeps its
