@@ -116,6 +116,9 @@ SOLVES = {
     "volume_32x16x8_l1_25": (dict(n_depth=32, n_x=16, n_y=8, lateral_dims=2, n_k=48), "l1", 0.01, 25, 30),
     # one iteration: z = prox(x0 - delta grad D(x0)) and the objective at x0
     "bscan_128x48_tv_1": (dict(n_depth=128, n_x=48, n_k=128), "tv", 0.005, 1, 40),
+    # fully observed, odd lateral sizes (no Nyquist column in the residual norm's pair weights)
+    "volume_odd_32x9x7_l1_15": (dict(n_depth=32, n_x=9, n_y=7, lateral_dims=2, n_k=48), "l1", 0.01, 15, 12),
+    "bscan_odd_75x45_l1_20": (dict(n_depth=75, n_x=45, n_k=90, z_focus=20.0), "l1", 0.01, 20, 15),
 }
 
 
