@@ -647,6 +647,22 @@ oct_status run_cols_fwd_res(oct_plan* p, const float2* yh, double* partial, int*
   return OCT_OK;
 }
 
+// X1 -> X1 = the adjoint columns of R^ = W_h / N_lat - yh: the two column
+// kernels with the spectral seam between them, in one launch when the pair
+// fits it (R^ stays in registers), else the residual-writing forward kernel
+// and the adjoint kernel over W
+oct_status run_cols_normal(oct_plan* p, const float2* yh, double* partial, int* nparts, hipStream_t s) {
+  const NufftArgs a = nufft_args(p);
+  if (nufft_normal_pair_supported(a)) {
+    HIPCHK(launch_nufft_normal_pair(a, p->X1, yh, partial, p->X1, s));
+    if (nparts) *nparts = (int)(p->n_pairs * p->B);
+    return OCT_OK;
+  }
+  OCTCHK(run_cols_fwd_res(p, yh, partial, nparts, s));
+  HIPCHK(launch_nufft_adj_pair(a, p->W, p->X1, s));
+  return OCT_OK;
+}
+
 // X1 (adjoint NUFFT output) -> g = F_lat^H X1 written to out
 oct_status run_lat_adjoint(oct_plan* p, float2* out, hipStream_t s) {
   if (p->lat_dims == 2) {
@@ -1131,9 +1147,12 @@ oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, dou
   // Y_h costs a lateral pass over y: a win for a volume, whose general seam
   // takes three passes (y, x, y), but not for a B-scan's single seam pass.
   if (spectral_seam(p, false) && p->lat_dims == 2) {
-    OCTCHK(run_meas_adjoint(p, y, s, true));   // W = Y_h, read and overwritten by the forward pair kernel
+    OCTCHK(run_meas_adjoint(p, y, s, true));   // W = Y_h, read by the column kernels
     OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
-    OCTCHK(run_cols_fwd_res(p, p->W, half_resid_sq ? p->partial : nullptr, &np, s));
+    OCTCHK(run_cols_normal(p, p->W, half_resid_sq ? p->partial : nullptr, &np, s));
+    if (half_resid_sq) HIPCHK(launch_reduce_sum(p->partial, np, half_resid_sq, 0.5, 0, s));
+    OCTCHK(run_lat_adjoint(p, (float2*)gout, s));
+    return OCT_OK;
   } else {
     OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
     OCTCHK(run_cols_fwd(p, s, p->hs));
@@ -1197,13 +1216,13 @@ oct_status oct_lipschitz(oct_plan_t p, int32_t iters, uint64_t seed, int32_t fla
   for (int it = 0; it < iters; ++it) {
     OCTCHK(run_lat_forward(p, p->za, nullptr, nullptr, 0.f, s));
     if (spectral_seam(p, paper)) {
-      OCTCHK(run_cols_fwd_res(p, nullptr, nullptr, nullptr, s));
+      OCTCHK(run_cols_normal(p, nullptr, nullptr, nullptr, s));
     } else {
       OCTCHK(run_cols_fwd(p, s, p->hs && !paper));
       if (paper) OCTCHK(run_normal_paper(p, nullptr, nullptr, nullptr, s));
       else OCTCHK(run_normal(p, nullptr, nullptr, nullptr, s, p->hs));
+      OCTCHK(run_cols_adj(p, s, p->hs && !paper));
     }
-    OCTCHK(run_cols_adj(p, s, p->hs && !paper));
     OCTCHK(run_lat_adjoint(p, p->zb, s));
     HIPCHK(launch_norm2_partial(p->zb, n, p->partial, nb, s));
     HIPCHK(launch_reduce_sum(p->partial, nb, p->dscal, 1.0, 0, s));
@@ -1318,13 +1337,13 @@ oct_status oct_mbir_solve(oct_plan_t p, const float* y, const oct_solve_params* 
     int nres = 0, npen = 0;
     // residual partials only for the objective
     if (spec) {
-      OCTCHK(run_cols_fwd_res(p, p->yhat, want_obj ? res_part : nullptr, &nres, s));
+      OCTCHK(run_cols_normal(p, p->yhat, want_obj ? res_part : nullptr, &nres, s));
     } else {
       OCTCHK(run_cols_fwd(p, s, p->hs && !paper));
       if (paper) OCTCHK(run_normal_paper(p, y, want_obj ? res_part : nullptr, &nres, s));
       else OCTCHK(run_normal(p, y, want_obj ? res_part : nullptr, &nres, s, p->hs));
+      OCTCHK(run_cols_adj(p, s, p->hs && !paper));
     }
-    OCTCHK(run_cols_adj(p, s, p->hs && !paper));
     if (fused_l1) {
       LatArgs a = lat_args(p, lines_x(p, (int)p->Nz), false);
       a.src = p->X1;

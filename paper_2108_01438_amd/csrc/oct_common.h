@@ -180,6 +180,14 @@ hipError_t launch_nufft_adj_pair(const NufftArgs& a, const float2* Rh, float2* X
 hipError_t launch_nufft_fwd_pair_res(const NufftArgs& a, const float2* X1, float2* Rh, const float2* yh,
                                      double* partial, hipStream_t s);
 size_t nufft_pair_lds_bytes(const NufftArgs& a, bool adjoint);
+// Fully observed plans: both column kernels of a pair in one launch, X1 ->
+// R^ = W_h / N_lat - yh (kept in registers; residual partials as above) ->
+// X = the adjoint columns (X may be X1: a pair reads its columns before it
+// writes them).  Supported when every thread's samples fit its registers.
+hipError_t launch_nufft_normal_pair(const NufftArgs& a, const float2* X1, const float2* yh, double* partial,
+                                    float2* X, hipStream_t s);
+size_t nufft_normal_pair_lds_bytes(const NufftArgs& a);
+bool nufft_normal_pair_supported(const NufftArgs& a);
 bool nufft_pair_supported(const NufftArgs& a);   // LDS and thread limits of the pair kernels
 
 // Reductions and elementwise helpers.

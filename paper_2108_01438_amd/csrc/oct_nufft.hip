@@ -937,6 +937,242 @@ __global__ void __launch_bounds__(1024, ONE ? 8 : 4) nufft_adj_pair_kernel(Nufft
   });
 }
 
+// ---------------------------------------------------------------------------
+// Fully observed plans (s = 1): the normal operator's column part for one
+// pair in one kernel.  The forward half is nufft_fwd_pair_kernel's (grid
+// rows, K-point transforms, J-tap gather, filter, Hermitian part) ending in
+// the residual spectrum R^ = W_h / N_lat - Y_h (eq. (2), (7)); R^ then stays
+// in registers as the adjoint's input (NS samples per thread): the sample's
+// beta, grid coordinate and filter serve both halves, and R^ makes no round
+// trip through HBM.  The adjoint half is nufft_adj_pair_kernel's register
+// path.  X1 may be X: a pair reads its two columns before it writes them.
+// ---------------------------------------------------------------------------
+template <int J, bool ONE, int NS>
+__global__ void __launch_bounds__(1024) nufft_normal_pair_kernel(NufftArgs a, const float2* X1, PairRes r,
+                                                                 float2* X) {
+  extern __shared__ float4 smem4[];
+  __shared__ float kc[J * KBH];
+  __shared__ int s_mf, s_dup;
+  __shared__ double sh[16];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int K = a.K, Mk = a.Mk, Nz = a.Nz, nc = a.nc;
+  const int b = blockIdx.x / a.n_pairs;
+  const int4 pr = a.pairs[blockIdx.x - b * a.n_pairs];
+  const int64_t slot = ((int64_t)b * a.n_half + pr.z) * Mk;
+  const float2* yh = r.yh ? r.yh + slot : nullptr;
+  float2 yv[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {   // loaded before the transforms
+    const int m = tid + i * nthr;
+    yv[i] = (yh && m < Mk) ? yh[m] : make_float2(0.f, 0.f);
+  }
+  if (tid == 0) {
+    s_mf = Mk;
+    s_dup = 0;
+  }
+  for (int i = tid; i < J * KBH; i += nthr) kc[i] = a.kbc[i];
+
+  float2* region = reinterpret_cast<float2*>(smem4);
+  const int rs = K + 2 * KPAD;   // forward: two grid rows with KPAD wrapped cells on each side
+  float2* g0 = region + KPAD;
+  float2* g1 = g0 + rs;
+  const float2* s0 = X1 + xcol(a, b, pr.x);
+  const float2* s1 = X1 + xcol(a, b, pr.y);
+  const bool half = K == 2 * Nz && 2 * nc == Nz &&
+                    fwd_grid_fft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(g0, 2, rs, s0, s1, a.deap, a.fK,
+                                                                                a.twK, tid, nthr);
+  if (!half) {
+    for (int i = tid; i < K - Nz; i += nthr) {
+      g0[Nz - nc + i] = make_float2(0.f, 0.f);
+      g1[Nz - nc + i] = make_float2(0.f, 0.f);
+    }
+    batched_for(Nz, tid, nthr, [&](int n) { return VD2{s0[n], s1[n], a.deap[n]}; },
+                [&](int n, VD2 v) {
+                  int idx = n - nc;
+                  if (idx < 0) idx += K;
+                  g0[idx] = cscale(v.a, v.d);
+                  g1[idx] = cscale(v.b, v.d);
+                });
+    __syncthreads();
+    fft_rows_sized<ONE, false, OCT_CT_K_SIZES>(g0, 2, rs, a.fK, a.twK, tid, nthr);
+  }
+  if (tid < 4 * KPAD) {
+    float2* g = tid < 2 * KPAD ? g0 : g1;
+    const int t = tid & (2 * KPAD - 1);
+    const int c = t < KPAD ? t - KPAD : K + t - KPAD;
+    g[c] = g[t < KPAD ? c + K : c - K];
+  }
+  __syncthreads();
+
+  const double q2 = a.q2[pr.x];
+  const float bq = a.beam[pr.x];
+  int cb[NS];
+  float xr[NS];
+  float2 u0r[NS], u1r[NS];
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int m = tid + i * nthr;
+    cb[i] = EVANESCENT;
+    xr[i] = 0.f;
+    u0r[i] = u1r[i] = make_float2(0.f, 0.f);
+    if (m < Mk) {
+      const KP kp{a.k2x4[m], a.phase[m]};
+      const double arg = kp.k2 - q2;
+      float2 res = make_float2(0.f, 0.f), hc = make_float2(0.f, 0.f);
+      if (arg > 0.0) {
+        if (m == 0 || a.k2x4[m - 1] - q2 <= 0.0) s_mf = m;
+        const double beta = beta_of(arg);
+        const double t = a.ct * beta;
+        const double tw = fma(-(double)K, floor(t * a.invK), t);
+        const double flw = floor(tw);
+        const float x = (float)(2.0 * (tw - flw) - 1.0);
+        const int c0 = (int)flw - J / 2 + 1;
+        float2 v0 = make_float2(0.f, 0.f), v1 = make_float2(0.f, 0.f);
+        const float x2 = x * x;
+#pragma unroll
+        for (int jj = 0; jj < J / 2; ++jj) {
+          float wlo, whi;
+          kb_pair(a.kbc + jj * 2 * KBH, x, x2, wlo, whi);
+          const float2 a0 = g0[c0 + jj], a1 = g0[c0 + J - 1 - jj];
+          const float2 b0 = g1[c0 + jj], b1 = g1[c0 + J - 1 - jj];
+          v0.x = fmaf(wlo, a0.x, v0.x);
+          v0.y = fmaf(wlo, a0.y, v0.y);
+          v0.x = fmaf(whi, a1.x, v0.x);
+          v0.y = fmaf(whi, a1.y, v0.y);
+          v1.x = fmaf(wlo, b0.x, v1.x);
+          v1.y = fmaf(wlo, b0.y, v1.y);
+          v1.x = fmaf(whi, b1.x, v1.x);
+          v1.y = fmaf(whi, b1.y, v1.y);
+        }
+        const float2 h = filter_h(a, kp.ph, bq, beta);
+        const float2 w0 = cmul(h, v0), w1 = cmul(h, v1);
+        res = make_float2(0.5f * (w0.x + w1.x), 0.5f * (w0.y - w1.y));   // (W(q) + conj W(-q)) / 2
+        hc = cconj(h);
+        const double fl = floor(t);
+        cb[i] = (int)fl;
+        xr[i] = (float)(2.0 * (t - fl) - 1.0);
+      }
+      res = make_float2(fmaf(res.x, r.inv_nlat, -yv[i].x), fmaf(res.y, r.inv_nlat, -yv[i].y));
+      acc = fma((double)res.x, (double)res.x, fma((double)res.y, (double)res.y, acc));
+      if (cb[i] != EVANESCENT) {
+        u0r[i] = cmul(hc, res);
+        u1r[i] = cmul(hc, cconj(res));
+      }
+    }
+  }
+  if (r.partial) {   // uniform
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((tid & 63) == 0) sh[tid >> 6] = acc;
+  }
+  __syncthreads();   // the forward grid is dead: the adjoint's arrays take its place
+  if (r.partial && tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (nthr + 63) >> 6; ++w) t += sh[w];
+    r.partial[blockIdx.x] = t * r.nlat * (pr.x != pr.y ? 2.0 : 1.0);
+  }
+  short* bm = reinterpret_cast<short*>(reinterpret_cast<float*>(region + 2 * Mk) + Mk);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int m = tid + i * nthr;
+    if (m < Mk) bm[m] = cb[i] == EVANESCENT ? EVANESCENT16 : (short)cb[i];   // t < 32000 (plan creation)
+  }
+  __syncthreads();
+  // from here as in nufft_adj_pair_kernel (its register path, NS samples per thread)
+  const bool regs = true;
+  float2* grid = region;
+  float2* us0 = region;
+  float2* us1 = us0 + Mk;
+  float* xm = reinterpret_cast<float*>(us1 + Mk);
+  short* first = bm + Mk;
+  const int mf = s_mf;
+  int umin = 0, umax = -1;
+  if (mf < Mk) {
+    umin = bm[mf] - J / 2 + 1;
+    umax = bm[Mk - 1] + J / 2;
+  }
+  const int span = umax - umin + 1;
+  const int nph = span > K ? (span + K - 1) / K : 1;
+
+  // Scatter path: with distinct base cells (consecutive samples at least a
+  // cell apart: sigma >= 2, up to rounding, which the check below catches)
+  // and a span within K cells, tap j of every sample hits a different grid
+  // cell, so one LDS pass per tap adds w_j u into the cells with no
+  // conflicts.  Taps go from J - 1 down to 0, i.e. each cell receives its
+  // samples in increasing m: the order of the cell gather.
+  if (regs && nph == 1) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int m = tid + i * nthr;
+      if (m > mf && m < Mk && bm[m] <= bm[m - 1]) s_dup = 1;
+    }
+  }
+  __syncthreads();
+  if (regs && nph == 1 && !s_dup) {
+    for (int i = tid; i < 2 * K; i += nthr) grid[i] = make_float2(0.f, 0.f);   // over the base cells: read above
+    float w[NS][J];
+    int g0[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const float x = xr[i], x2 = x * x;
+#pragma unroll
+      for (int jj = 0; jj < J / 2; ++jj) kb_pair(a.kbc + jj * 2 * KBH, x, x2, w[i][jj], w[i][J - 1 - jj]);
+      int g = (cb[i] - J / 2 + 1) % K;
+      g0[i] = g < 0 ? g + K : g;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = J - 1; j >= 0; --j) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int m = tid + i * nthr;
+        if (m >= mf && m < Mk) {
+          int g = g0[i] + j;
+          if (g >= K) g -= K;
+          float2 c0 = grid[g], c1 = grid[K + g];
+          c0.x = fmaf(w[i][j], u0r[i].x, c0.x);
+          c0.y = fmaf(w[i][j], u0r[i].y, c0.y);
+          c1.x = fmaf(w[i][j], u1r[i].x, c1.x);
+          c1.y = fmaf(w[i][j], u1r[i].y, c1.y);
+          grid[g] = c0;
+          grid[K + g] = c1;
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    if (regs) {   // the gather reads the samples from LDS
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int m = tid + i * nthr;
+        if (m < Mk) {
+          xm[m] = xr[i];
+          us0[m] = u0r[i];
+          us1[m] = u1r[i];
+        }
+      }
+      __syncthreads();
+    }
+    adj_pair_gather<J>(a, kc, q2, bm, xm, us0, us1, first, grid, mf, umin, umax, span, nph, tid, nthr);
+  }
+
+  float2* __restrict__ d0 = X + xcol(a, b, pr.x);
+  float2* __restrict__ d1 = X + xcol(a, b, pr.y);
+  const bool two = pr.y != pr.x;
+  if (K == 2 * Nz && 2 * nc == Nz &&
+      adj_grid_ifft_half_sized<FftCfg<ONE>::MAXB, OCT_CT_K_SIZES>(grid, 2, K, d0, two ? d1 : nullptr, a.deap, nc,
+                                                                   a.fK, a.twK, tid, nthr))
+    return;
+  fft_rows_sized<ONE, true, OCT_CT_K_SIZES>(grid, 2, K, a.fK, a.twK, tid, nthr);
+  batched_for(Nz, tid, nthr, [&](int n) { return a.deap[n]; }, [&](int n, float d) {
+    int idx = n - nc;
+    if (idx < 0) idx += K;
+    d0[n] = cscale(grid[idx], d);
+    if (two) d1[n] = cscale(grid[K + idx], d);
+  });
+}
+
 
 // Threads per column: enough for the FFT stages, and wide enough that the
 // per-column work is short (the column count of a B-scan is only ~1000).
@@ -1100,6 +1336,53 @@ hipError_t launch_nufft_fwd_pair_res(const NufftArgs& a, const float2* X1, float
   r.inv_nlat = 1.f / (float)a.Nlat;
   r.nlat = (double)a.Nlat;
   return fwd_pair_dispatch<true>(a, X1, Rh, r, s);
+}
+
+namespace {
+constexpr int NORMAL_NS = 4;   // samples per thread of the fused pair kernel
+
+template <int J, bool ONE>
+hipError_t nufft_normal_pair_t(const NufftArgs& a, const float2* X1, const PairRes& r, float2* X, int nthr,
+                               hipStream_t s) {
+  const size_t lds = nufft_normal_pair_lds_bytes(a);
+  if (lds > 64 * 1024 - 1024) {
+    static const hipError_t set =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&nufft_normal_pair_kernel<J, ONE, NORMAL_NS>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    if (set != hipSuccess) return set;
+  }
+  hipLaunchKernelGGL((nufft_normal_pair_kernel<J, ONE, NORMAL_NS>), dim3(a.n_pairs * (a.n_cols / a.Nlat)),
+                     dim3(nthr), lds, s, a, X1, r, X);
+  return hipGetLastError();
+}
+}  // namespace
+
+size_t nufft_normal_pair_lds_bytes(const NufftArgs& a) {
+  const size_t f = nufft_pair_lds_bytes(a, false), g = nufft_pair_lds_bytes(a, true);
+  return f > g ? f : g;
+}
+
+// the forward kernel's threads; every thread's samples and grid cells fit its registers
+bool nufft_normal_pair_supported(const NufftArgs& a) {
+  const int nt = pair_threads(a, false);
+  return nufft_pair_supported(a) && nufft_normal_pair_lds_bytes(a) <= 156 * 1024 && a.Mk <= NORMAL_NS * nt &&
+         (a.K + nt - 1) / nt <= ADJ_MAXC;
+}
+
+hipError_t launch_nufft_normal_pair(const NufftArgs& a, const float2* X1, const float2* yh, double* partial,
+                                    float2* X, hipStream_t s) {
+  const int nt = pair_threads(a, false);
+  const bool one = fft_one(a.fK, 2, nt);
+  PairRes r{};
+  r.yh = yh;
+  r.partial = partial;
+  r.inv_nlat = 1.f / (float)a.Nlat;
+  r.nlat = (double)a.Nlat;
+  switch (a.J) {
+    case 4: return one ? nufft_normal_pair_t<4, true>(a, X1, r, X, nt, s) : nufft_normal_pair_t<4, false>(a, X1, r, X, nt, s);
+    case 6: return one ? nufft_normal_pair_t<6, true>(a, X1, r, X, nt, s) : nufft_normal_pair_t<6, false>(a, X1, r, X, nt, s);
+    default: return one ? nufft_normal_pair_t<8, true>(a, X1, r, X, nt, s) : nufft_normal_pair_t<8, false>(a, X1, r, X, nt, s);
+  }
 }
 
 hipError_t launch_nufft_adj_pair(const NufftArgs& a, const float2* Rh, float2* X, hipStream_t s) {
