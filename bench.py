@@ -44,8 +44,10 @@ def stage_bytes(g, masked: bool, penalty: str) -> dict:
     transform takes two passes (a 256 x 256 plane does not fit on chip): the
     second axis adds a read and a write of the image (or spectrum) per
     transform.  With every pixel observed (no mask) the solve has no
-    residual seam: the forward NUFFT stage writes the residual spectrum and
-    reads the lateral spectrum of y (formed once per solve) instead."""
+    residual seam and one column stage: a kernel per column pair that reads
+    X1 and the lateral spectrum of y (formed once per solve), keeps the
+    residual spectrum on chip and writes the adjoint columns (every unmasked
+    workload here fits it)."""
     N = g.batch * g.n_y * g.n_x * g.n_depth
     M = g.batch * g.n_y * g.n_x * g.n_k
     mbits = M / 8.0 if masked else 0.0
@@ -55,9 +57,9 @@ def stage_bytes(g, masked: bool, penalty: str) -> dict:
     if masked:
         st["nufft_fwd"] = 8.0 * N + 8.0 * M                     # X1 in; W out
         st["normal"] = 20.0 * M + mbits + (32.0 * M if vol else 0.0)   # W, y, mask in; R out (+ two y passes)
+        st["nufft_adj"] = 8.0 * M + 8.0 * N                     # R in; X1 out
     else:
-        st["nufft_fwd"] = 8.0 * N + 16.0 * M                    # X1, F_lat y in; R out
-    st["nufft_adj"] = 8.0 * M + 8.0 * N                         # R in; X1 out
+        st["nufft_normal"] = 16.0 * N + 8.0 * M                 # X1, F_lat y in; X1 out (R stays on chip)
     st["lat_update"] = 24.0 * N + (16.0 * N if vol else 0.0)    # X1, x in; v out (+ y pass)
     st["prox"] = prox
     return st
@@ -136,9 +138,9 @@ def phi_sizes_bench() -> dict:
 # kernels of the single-kernel stages (a volume's lateral stages take two or
 # three launches of the lateral kernel), by the name rocprofv3 reports
 STAGE_KERNEL = {
-    # the volume (every pixel observed) runs the variant that writes the residual spectrum
-    "nufft_fwd": {True: "nufft_fwd_pair_kernel<6, false, true>", False: "nufft_fwd_pair_kernel<6, false, false>"},
+    "nufft_fwd": "nufft_fwd_pair_kernel<6, false, false>",
     "nufft_adj": "nufft_adj_pair_kernel<6, true>",
+    "nufft_normal": "nufft_normal_pair_kernel<6, false, 4>",
     "prox": {"tv": "tv2d_tile_kernel<false>", "haar": "haar_kernel<3, 3", "l1": "prox_l1_kernel"},
 }
 BSCAN_STAGE_KERNEL = {
@@ -148,7 +150,8 @@ BSCAN_STAGE_KERNEL = {
 }
 STAGE_SOURCE = {
     "lat_fwd": "oct_lateral.hip", "normal": "oct_lateral.hip", "lat_update": "oct_lateral.hip",
-    "nufft_fwd": "oct_nufft.hip", "nufft_adj": "oct_nufft.hip", "prox": "oct_prox.hip",
+    "nufft_fwd": "oct_nufft.hip", "nufft_adj": "oct_nufft.hip", "nufft_normal": "oct_nufft.hip",
+    "prox": "oct_prox.hip",
 }
 
 
@@ -156,7 +159,7 @@ def stage_kernel(stage: str, penalty: str, volume: bool):
     """Kernel (name prefix) of a stage that is one launch, else None."""
     k = STAGE_KERNEL.get(stage)
     if isinstance(k, dict):
-        k = k.get(volume) if stage == "nufft_fwd" else k.get(penalty)
+        k = k.get(penalty)
     if k is None and not volume:
         k = BSCAN_STAGE_KERNEL.get(stage)
     return k
@@ -226,7 +229,10 @@ def traffic_json(workload: str, penalty: str, volume: bool, fetch_dir: str, writ
     fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
     out = {"workload": workload, "fetch_scale": fs, "write_scale": ws, "copy_bytes_each_way": copy_bytes,
            "stages": {}}
-    for st in ("lat_fwd", "nufft_fwd", "normal", "nufft_adj", "lat_update", "prox"):
+    # the stages of the workload's iteration: the B-scan is masked, the volume fully observed
+    stages = (("lat_fwd", "nufft_normal", "lat_update", "prox") if volume else
+              ("lat_fwd", "nufft_fwd", "normal", "nufft_adj", "lat_update", "prox"))
+    for st in stages:
         k = stage_kernel(st, penalty, volume)
         if k is None:
             continue

@@ -275,7 +275,9 @@ typedef enum {
   OCT_STAGE_NORMAL = 2,     /* W = F_lat(s.(Re F_lat^-1 W - y)) / N_lat (eq. (2), (7))  */
   OCT_STAGE_NUFFT_ADJ = 3,  /* X1 = NUFFT_q^H(conj(H) . W)              (eq. (3))       */
   OCT_STAGE_LAT_UPDATE = 4, /* v = x - delta F_lat^H X1                 (eq. (15))      */
-  OCT_STAGE_PROX = 5        /* z = prox(v) for the given penalty        (eq. (16))      */
+  OCT_STAGE_PROX = 5,       /* z = prox(v) for the given penalty        (eq. (16))      */
+  OCT_STAGE_NUFFT_NORMAL = 6 /* X1 = NUFFT_q^H(conj(H) . (H . KB-NUFFT_q(X1) residual spectrum)),
+                                every pixel observed (eq. (2)-(7))                          */
 } oct_stage;
 
 /* Run one stage of a FISTA iteration on the plan's own workspace and solver
@@ -284,10 +286,14 @@ typedef enum {
  * and profiling only; y is read by OCT_STAGE_NORMAL (device measurement,
  * may be NULL for the others); penalty selects the prox (TV with 10 inner
  * steps, Haar with 3 levels).  On a plan whose every pixel is observed
- * (mask NULL or all ones), the solve folds OCT_STAGE_NORMAL into
- * OCT_STAGE_NUFFT_FWD, which then writes the residual spectrum W/N_lat -
- * F_lat(y)/N_lat (from the solver's stored F_lat(y)); OCT_STAGE_NORMAL
- * still runs the general seam.  Asynchronous. */
+ * (mask NULL or all ones) the solve's column stages are one:
+ * OCT_STAGE_NUFFT_NORMAL, the forward columns, the residual spectrum
+ * W_h/N_lat - F_lat(y)/N_lat (from the solver's stored F_lat(y)) and the
+ * adjoint columns in one kernel per column pair (or the two pair kernels
+ * when a pair's samples do not fit its registers); OCT_E_UNSUPPORTED on a
+ * masked plan.  The other stages still run as named: OCT_STAGE_NUFFT_FWD
+ * then writes the residual spectrum, and OCT_STAGE_NORMAL runs the general
+ * seam.  Asynchronous. */
 oct_status oct_run_stage(oct_plan_t plan, int32_t stage, int32_t penalty, const float* y, void* stream);
 
 /* Direct (non-iterative) reconstructions of Sec. 3.1: the three images of

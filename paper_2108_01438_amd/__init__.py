@@ -316,7 +316,7 @@ class Plan:
                              sp, ctypes.c_void_p(_stream_ptr(stream))))
         return z
 
-    STAGES = ("lat_fwd", "nufft_fwd", "normal", "nufft_adj", "lat_update", "prox")
+    STAGES = ("lat_fwd", "nufft_fwd", "normal", "nufft_adj", "lat_update", "prox", "nufft_normal")
 
     def run_stage(self, stage, penalty="tv", y=None, stream=None):
         """One stage of a FISTA iteration on the plan's workspace (timing only)."""

@@ -1145,8 +1145,10 @@ oct_status oct_grad(oct_plan_t p, const void* x, const float* y, void* gout, dou
   int np = 0;
   // residual partials only when the caller asks for 1/2 ||r||^2.  Per call,
   // Y_h costs a lateral pass over y: a win for a volume, whose general seam
-  // takes three passes (y, x, y), but not for a B-scan's single seam pass.
-  if (spectral_seam(p, false) && p->lat_dims == 2) {
+  // takes three passes (y, x, y), and where the one-kernel column pair saves
+  // the spectrum's round trip; a B-scan whose pairs need the two kernels
+  // keeps its single seam pass.
+  if (spectral_seam(p, false) && (p->lat_dims == 2 || nufft_normal_pair_supported(nufft_args(p)))) {
     OCTCHK(run_meas_adjoint(p, y, s, true));   // W = Y_h, read by the column kernels
     OCTCHK(run_lat_forward(p, (const float2*)x, nullptr, nullptr, 0.f, s));
     OCTCHK(run_cols_normal(p, p->W, half_resid_sq ? p->partial : nullptr, &np, s));
@@ -1454,6 +1456,9 @@ oct_status oct_run_stage(oct_plan_t p, int32_t stage, int32_t pen, const float* 
       HIPCHK(launch_lateral(LAT_UPDATE, a, s));
       return OCT_OK;
     }
+    case OCT_STAGE_NUFFT_NORMAL:
+      if (!spectral_seam(p, false)) return fail(OCT_E_UNSUPPORTED, "OCT_STAGE_NUFFT_NORMAL needs a fully observed plan");
+      return run_cols_normal(p, p->yhat, nullptr, nullptr, s);
     case OCT_STAGE_PROX: {
       int np = 0;
       return run_prox(p, pen, 1e-3f, INFINITY, 10, 3, p->xext, p->zb, pen == OCT_PEN_TV ? p->p0 : nullptr,
