@@ -73,3 +73,29 @@ def test_per_item_weights_reject_unsupported():
     with pytest.raises(P.OctError) as e:
         plan.mbir_solve(y, "l1", [1.0, -2.0], 3, delta=1e-3)
     assert e.value.status == P.OCT_E_INVALID
+
+
+def test_per_item_weights_fully_observed_match_oracle():
+    """Per-item weights on a fully observed plan (the residual seam in the
+    lateral-frequency domain, the measurement's lateral spectrum formed from
+    the per-item scaled measurements): every item's z^K matches the oracle's
+    FISTA at its own lambda (eq. (15))."""
+    import dataclasses
+    import paper_2108_01438_amd as P
+    og, pg = both_geoms(n_depth=64, n_x=16, n_k=64)
+    rng = np.random.default_rng(67)
+    x_true = synth.scatterers(rng, O.img_shape(og), 8)
+    y = synth.noisy(O.forward(x_true, og), synth.standard_normal(rng, O.meas_shape(og)), None, 0.01)
+    y32 = y.astype(np.float32)
+    y64 = y32.astype(np.float64)
+    lam_max = O.lambda_max(y64, og, None)
+    delta = O.step_size(O.lipschitz(og, None, iters=30))
+    lams = [lam_max * f for f in (0.02, 0.1, 0.3)]
+    flush("[per-item weights, fully observed] oracle")
+    zo = [O.fista(y64, og, None, O.PEN_L1, lam, delta, 20)[0] for lam in lams]
+    plan = P.Plan(dataclasses.replace(pg, batch=len(lams)))
+    yb = np.repeat(y32, len(lams), axis=0)
+    z, _ = plan.mbir_solve(to_dev(yb), "l1", lams, 20, delta=delta)
+    z = to_host(z)
+    for b in range(len(lams)):
+        assert rel(z[b:b + 1], zo[b]) <= 1e-4, b
